@@ -1,0 +1,217 @@
+"""ctypes front end of the CPU oracle (``oracle.cpp``) — TEST INFRASTRUCTURE ONLY.
+
+The oracle is the plain statement of the PatchMatch depth-map estimation step of the
+paper (Sec. III-B, Sec. III-C, Eq. 4, Eq. 5, Algorithm 1 "depth map estimation").
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg may
+import this package; the GPU library never does.
+
+Each function here only marshals arguments; all arithmetic is in ``oracle.cpp``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+CMAX = 2.0
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with g++ (single-threaded, no fast-math, no fp contraction)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-mfma",
+           "-fPIC", "-shared", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("n_views", C.c_int32),
+        ("width", C.POINTER(C.c_int32)),
+        ("height", C.POINTER(C.c_int32)),
+        ("images", C.POINTER(C.POINTER(C.c_float))),
+        ("K", C.POINTER(C.c_double)),
+        ("R", C.POINTER(C.c_double)),
+        ("t", C.POINTER(C.c_double)),
+        ("d_lo", C.c_double),
+        ("d_hi", C.c_double),
+        ("window", C.c_int32),
+        ("dilation", C.c_int32),
+        ("top_k", C.c_int32),
+        ("bilateral", C.c_int32),
+        ("sigma_s", C.c_double),
+        ("sigma_c", C.c_double),
+        ("eps_v", C.c_double),
+        ("eps_c", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER(_Problem)
+        dp = C.POINTER(C.c_double)
+        fp = C.POINTER(C.c_float)
+        ip = C.POINTER(C.c_int32)
+        up = C.POINTER(C.c_uint32)
+        L.oracle_philox4x32_10.argtypes = [up, up, up]
+        L.oracle_patchmatch.argtypes = [P, C.c_int, C.c_int, fp, fp, fp]
+        L.oracle_init.argtypes = [P, C.c_int, dp, dp]
+        L.oracle_halfsweep.argtypes = [P, C.c_int, C.c_int, C.c_int, dp, dp, ip, C.c_int, C.c_int, C.c_int]
+        L.oracle_eval_cost.argtypes = [P, C.c_int, dp, dp, dp, ip, ip, C.c_int]
+        L.oracle_homography.argtypes = [P, C.c_int, dp, C.c_double, C.c_int, C.c_int, dp]
+        L.oracle_bilinear.argtypes = [fp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int]
+        L.oracle_bilinear.restype = C.c_double
+        L.oracle_aggregate.argtypes = [dp, ip, C.c_int, C.c_int, C.c_double, C.c_int]
+        L.oracle_aggregate.restype = C.c_double
+        for f in ("oracle_patchmatch", "oracle_init", "oracle_halfsweep", "oracle_eval_cost", "oracle_homography"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class Problem:
+    """A reference view (index 0) plus sources, with cameras and solver parameters."""
+
+    def __init__(self, images: Sequence[np.ndarray], K, R, t, depth_range, window: int, dilation: int,
+                 top_k: int = 0, bilateral: bool = True, sigma_s: Optional[float] = None,
+                 sigma_c: float = 12.0, eps_v: float = 1e-4, eps_c: float = 1e-4, seed: int = 0x5EED):
+        self.images = [np.ascontiguousarray(im, dtype=np.float32) for im in images]
+        n = len(self.images)
+        self.K = np.ascontiguousarray(np.asarray(K, dtype=np.float64).reshape(n, 9))
+        self.R = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(n, 9))
+        self.t = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(n, 3))
+        self.w = np.array([im.shape[1] for im in self.images], dtype=np.int32)
+        self.h = np.array([im.shape[0] for im in self.images], dtype=np.int32)
+        self._imgptrs = (C.POINTER(C.c_float) * n)(*[_ptr(im, C.c_float) for im in self.images])
+        if sigma_s is None:
+            sigma_s = (window - 1) / 2.0
+        self.window, self.dilation, self.top_k = window, dilation, top_k
+        self.s = _Problem(n, _ptr(self.w, C.c_int32), _ptr(self.h, C.c_int32), self._imgptrs,
+                          _ptr(self.K, C.c_double), _ptr(self.R, C.c_double), _ptr(self.t, C.c_double),
+                          float(depth_range[0]), float(depth_range[1]), window, dilation, top_k,
+                          1 if bilateral else 0, float(sigma_s), float(sigma_c), float(eps_v), float(eps_c),
+                          int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+    @property
+    def W(self):
+        return int(self.w[0])
+
+    @property
+    def H(self):
+        return int(self.h[0])
+
+    @property
+    def n_src(self):
+        return len(self.images) - 1
+
+    @classmethod
+    def from_scene(cls, scene, window, dilation, top_k=0, **kw):
+        return cls(scene.images, scene.K, scene.R, scene.t, scene.depth_range, window, dilation, top_k, **kw)
+
+    def radius(self):
+        return self.dilation * ((self.window - 1) // (2 * self.dilation))
+
+    def valid_mask(self):
+        r = self.radius()
+        m = np.zeros((self.H, self.W), dtype=bool)
+        if self.H - 2 * r > 0 and self.W - 2 * r > 0:
+            m[r:self.H - r, r:self.W - r] = True
+        return m
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(o, C.c_uint32))
+    return o
+
+
+def patchmatch(pb: Problem, iters: int, fp64: bool = False):
+    """Full run -> (depth (H,W), normal (H,W,3), cost (H,W)) float32."""
+    H, W = pb.H, pb.W
+    d = np.zeros((H, W), np.float32)
+    n = np.zeros((H, W, 3), np.float32)
+    c = np.zeros((H, W), np.float32)
+    rc = lib().oracle_patchmatch(C.byref(pb.s), iters, int(fp64), _ptr(d, C.c_float), _ptr(n, C.c_float),
+                                 _ptr(c, C.c_float))
+    if rc != 0:
+        raise ValueError("oracle_patchmatch failed (singular reference K?)")
+    return d, n, c
+
+
+def init(pb: Problem, fp64: bool = False):
+    planes = np.zeros((pb.H, pb.W, 4), np.float64)
+    cost = np.zeros((pb.H, pb.W), np.float64)
+    if lib().oracle_init(C.byref(pb.s), int(fp64), _ptr(planes, C.c_double), _ptr(cost, C.c_double)) != 0:
+        raise ValueError("oracle_init failed")
+    return planes, cost
+
+
+def halfsweep(pb: Problem, planes, cost, iteration: int, colour: int, fp64: bool = False, subset=None,
+              propagate: bool = True, refine: bool = True):
+    P = np.ascontiguousarray(planes, dtype=np.float64).copy()
+    Cc = np.ascontiguousarray(cost, dtype=np.float64).copy()
+    sub = None if subset is None else np.ascontiguousarray(subset, dtype=np.int32)
+    rc = lib().oracle_halfsweep(C.byref(pb.s), iteration, colour, int(fp64), _ptr(P, C.c_double),
+                                _ptr(Cc, C.c_double), None if sub is None else _ptr(sub, C.c_int32),
+                                0 if sub is None else len(sub), int(propagate), int(refine))
+    if rc != 0:
+        raise ValueError("oracle_halfsweep failed")
+    return P, Cc
+
+
+def eval_cost(pb: Problem, planes, fp64: bool = False, subset=None):
+    """Cost of the given planes -> (cost (H,W), per_view (H,W,n_src), valid (H,W,n_src))."""
+    P = np.ascontiguousarray(planes, dtype=np.float64)
+    H, W, n = pb.H, pb.W, pb.n_src
+    cost = np.full((H, W), CMAX, np.float64)
+    pv = np.full((H, W, n), CMAX, np.float64)
+    ok = np.zeros((H, W, n), np.int32)
+    sub = None if subset is None else np.ascontiguousarray(subset, dtype=np.int32)
+    rc = lib().oracle_eval_cost(C.byref(pb.s), int(fp64), _ptr(P, C.c_double), _ptr(cost, C.c_double),
+                                _ptr(pv, C.c_double), _ptr(ok, C.c_int32),
+                                None if sub is None else _ptr(sub, C.c_int32), 0 if sub is None else len(sub))
+    if rc != 0:
+        raise ValueError("oracle_eval_cost failed")
+    return cost, pv, ok.astype(bool)
+
+
+def homography(pb: Problem, j: int, n, d: float, x: int, y: int):
+    nn = np.ascontiguousarray(n, dtype=np.float64)
+    Hm = np.zeros(9, np.float64)
+    lib().oracle_homography(C.byref(pb.s), j, _ptr(nn, C.c_double), float(d), int(x), int(y), _ptr(Hm, C.c_double))
+    return Hm.reshape(3, 3)
+
+
+def bilinear(img, u: float, v: float, fp64: bool = True) -> float:
+    im = np.ascontiguousarray(img, dtype=np.float32)
+    return lib().oracle_bilinear(_ptr(im, C.c_float), im.shape[1], im.shape[0], float(u), float(v), int(fp64))
+
+
+def aggregate(cj, valid, top_k: int = 0, eps_c: float = 1e-4, fp64: bool = True) -> float:
+    c = np.ascontiguousarray(cj, dtype=np.float64)
+    v = np.ascontiguousarray(valid, dtype=np.int32)
+    return lib().oracle_aggregate(_ptr(c, C.c_double), _ptr(v, C.c_int32), len(c), top_k, eps_c, int(fp64))

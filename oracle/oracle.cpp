@@ -1,0 +1,688 @@
+// PatchMatch multi-view stereo oracle — TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, single-threaded CPU statement of what the PHI-MVS depth-map
+// estimation step computes (paper Sec. III-B random initialisation, Sec. III-C
+// depth map estimation with Eq. 4 and Eq. 5, Algorithm 1 "depth map estimation").
+// Only the tests, the smoke check and the benchmark's CPU-baseline leg may load it;
+// the GPU library never does, and the two share no code.
+//
+// Every function is written for one pixel / one hypothesis / one view at a time in
+// the order the paper states the method; there is no blocking, fusion or
+// reordering.  The arithmetic type T is float ("FP32 canonical": every rounding
+// step written out, fma only where written) or double (FP64, used to state the
+// error of the FP32 results).  Points the paper leaves open follow these readings:
+//
+//  * Cost (Eq. 4): weighted ZNCC over the dilated window; weight 1 everywhere
+//    reproduces Eq. 4 exactly; bilateral weights come from the reference patch
+//    only: w = exp(-(a-a_c)^2 / (2 sc^2)) * exp(-s^2 (k1^2 + k2^2) / (2 ss^2)), each
+//    factor evaluated in FP64 and, in FP32 mode, rounded to float.
+//  * Sums are shifted by the centre samples (a - a_c, b - b_c) before squaring; NCC
+//    is shift invariant, so this changes nothing but cancellation.
+//  * Border rule: a view is invalid when any warped tap leaves
+//    [0, W-1] x [0, H-1] or lies behind the source camera (w <= 0).  It is tested at
+//    the four window corners: for w > 0 the plane-induced homography maps the window
+//    rectangle onto the convex quadrilateral spanned by the corner images, so the
+//    corner test is exactly the all-taps test.  Every tap's sample position is then
+//    clamped into the image (a no-op in exact arithmetic) before bilinear sampling.
+//  * C_max = 1 - Z_min with Z_min = -1, so C_max = 2; omega in Eq. 5 is 1; a view's
+//    validity is an explicit flag instead of a float comparison with C_max; the
+//    inverse cost weight uses max(C_j, eps_c); a view with weighted variance below
+//    eps_v (either patch) is invalid; Eq. 5 is taken over the K lowest-cost valid
+//    views (K = 0: all valid views, which is the paper's Eq. 5), summed in ascending
+//    (cost, view) order.
+//  * Depth is reference-camera Z; normals live in the reference camera frame and
+//    face the camera (n . r_p < 0); initial normals are drawn as in Sec. III-B and
+//    flipped to face the camera.
+//  * Random refinement (Sec. III-C, last paragraph): Delta_d in [-d_hi/4, d_hi/4],
+//    Delta_theta in [-pi/2, pi/2], Delta_phi in [-pi/12, pi/12] applied to
+//    (theta, phi) = (atan2(n_y, n_x), acos(n_z)); candidates (d_new, n_old),
+//    (d_old, n_new), (d_new, n_new) in that order, strict improvement, first listed
+//    wins ties; an out-of-range d_new drops the two candidates that use it.  The
+//    normals are formed in FP64 (then rounded to float in FP32 mode).
+//  * Red/black propagation (Sec. III intro): each pixel of one colour looks at 8
+//    regions of the other colour (4 near "V" regions of 9 offsets, 4 far strips of
+//    10 offsets), takes the lowest-cost pixel of each region, re-expresses its plane
+//    at the pixel by ray-plane intersection, and keeps the best candidate if it
+//    strictly lowers the cost.  Refinement of a colour follows its propagation; one
+//    iteration is red then black.
+//  * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed and counter
+//    = (pixel index y*W + x, iteration, phase, 0); uniforms (x >> 8) * 2^-24.
+//  * Pixels whose reference window leaves the image are invalid: never updated,
+//    output depth 0, normal 0, cost C_max.
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+const int kPhaseInit = 0;
+const int kPhaseRefine = 1;
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11.
+void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// uniform in [0, 1) with 24 random bits (exact in float)
+double unit24(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+// ---------------------------------------------------------------- small FP64 linear algebra
+void mat3_mul(const double* A, const double* B, double* C) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[i * 3 + k] * B[k * 3 + j];
+      C[i * 3 + j] = s;
+    }
+}
+
+void mat3_transpose(const double* A, double* T) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) T[i * 3 + j] = A[j * 3 + i];
+}
+
+void mat3_vec(const double* A, const double* v, double* o) {
+  for (int i = 0; i < 3; ++i) o[i] = A[i * 3 + 0] * v[0] + A[i * 3 + 1] * v[1] + A[i * 3 + 2] * v[2];
+}
+
+// inverse by the adjugate; returns false when singular
+bool mat3_inverse(const double* A, double* inv) {
+  double c00 = A[4] * A[8] - A[5] * A[7];
+  double c01 = A[5] * A[6] - A[3] * A[8];
+  double c02 = A[3] * A[7] - A[4] * A[6];
+  double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+  double id = 1.0 / det;
+  inv[0] = c00 * id;
+  inv[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+  inv[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+  inv[3] = c01 * id;
+  inv[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+  inv[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+  inv[6] = c02 * id;
+  inv[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+  inv[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+// The problem as plain arrays.  View 0 is the reference, views 1..n_views-1 the
+// sources.  Cameras map world to camera: X_cam = R X_world + t; K has last row
+// (0, 0, 1).  Images are grey values (0..255 for 8-bit input), row-major H x W.
+typedef struct {
+  int32_t n_views;
+  const int32_t* width;
+  const int32_t* height;
+  const float* const* images;
+  const double* K;  // n_views * 9
+  const double* R;  // n_views * 9
+  const double* t;  // n_views * 3
+  double d_lo, d_hi;
+  int32_t window, dilation, top_k, bilateral;
+  double sigma_s, sigma_c, eps_v, eps_c;
+  uint64_t seed;
+} oracle_problem;
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+T fmaT(T a, T b, T c) { return std::fma(a, b, c); }
+
+template <typename T>
+struct V3 { T x, y, z; };
+
+// Eq. 5 over the K lowest-cost valid views (K <= 0: all valid views):
+// C = n_sel / sum_sel 1 / max(C_j, eps_c), summed in ascending (C_j, j) order; C_max when none is valid.
+template <typename T>
+T aggregate(const T* cj, const int* ok, int n, int top_k, T eps_c) {
+  std::vector<int> order;
+  for (int j = 0; j < n; ++j)
+    if (ok[j]) order.push_back(j);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return cj[a] < cj[b] || (cj[a] == cj[b] && a < b); });
+  int k = top_k > 0 ? std::min<int>(top_k, (int)order.size()) : (int)order.size();
+  if (k == 0) return T(2);
+  T sum = T(0);
+  for (int i = 0; i < k; ++i) sum = sum + T(1) / std::fmax(cj[order[i]], eps_c);
+  return (T)k / sum;
+}
+
+template <typename T>
+T dot3(const V3<T>& a, const V3<T>& b) { return fmaT(a.x, b.x, fmaT(a.y, b.y, a.z * b.z)); }
+
+template <typename T>
+T lerp(T a, T b, T t) { return fmaT(t, b - a, a); }
+
+// The solver's view of the problem in arithmetic type T.
+template <typename T>
+struct Solver {
+  const oracle_problem* pb;
+  int W, H, n_src, R_now, s;
+  double Kinv_d[9];     // reference K^-1 in FP64
+  T Kinv[9];            // ... rounded to T
+  std::vector<T> M;     // n_src * 9: K_j R_rel K_0^-1
+  std::vector<T> e;     // n_src * 3: K_j t_rel
+  T d_lo, d_hi, eps_v, eps_c;
+  static constexpr double kCmax = 2.0;
+
+  bool setup(const oracle_problem* p) {
+    pb = p;
+    W = p->width[0];
+    H = p->height[0];
+    n_src = p->n_views - 1;
+    s = p->dilation;
+    R_now = (p->window - 1) / (2 * p->dilation);
+    if (!mat3_inverse(p->K, Kinv_d)) return false;
+    for (int i = 0; i < 9; ++i) Kinv[i] = (T)Kinv_d[i];
+    M.assign(9 * n_src, T(0));
+    e.assign(3 * n_src, T(0));
+    double R0t[9];
+    mat3_transpose(p->R, R0t);
+    for (int j = 0; j < n_src; ++j) {
+      const double* Kj = p->K + 9 * (j + 1);
+      const double* Rj = p->R + 9 * (j + 1);
+      const double* tj = p->t + 3 * (j + 1);
+      double Rrel[9], Rt0[3], trel[3], KR[9], Mj[9], ej[3];
+      mat3_mul(Rj, R0t, Rrel);              // R_rel = R_j R_0^T
+      mat3_vec(Rrel, p->t, Rt0);            // R_rel t_0
+      for (int i = 0; i < 3; ++i) trel[i] = tj[i] - Rt0[i];  // t_rel = t_j - R_rel t_0
+      mat3_mul(Kj, Rrel, KR);
+      mat3_mul(KR, Kinv_d, Mj);             // M_j = (K_j R_rel) K_0^-1
+      mat3_vec(Kj, trel, ej);               // e_j = K_j t_rel
+      for (int i = 0; i < 9; ++i) M[9 * j + i] = (T)Mj[i];
+      for (int i = 0; i < 3; ++i) e[3 * j + i] = (T)ej[i];
+    }
+    d_lo = (T)p->d_lo;
+    d_hi = (T)p->d_hi;
+    eps_v = (T)p->eps_v;
+    eps_c = (T)p->eps_c;
+    return true;
+  }
+
+  bool pixel_valid(int x, int y) const {
+    int r = s * R_now;
+    return x - r >= 0 && x + r <= W - 1 && y - r >= 0 && y + r <= H - 1;
+  }
+
+  T ref(int x, int y) const { return (T)pb->images[0][(size_t)y * W + x]; }
+
+  // viewing ray of reference pixel (x, y): K_0^-1 (x, y, 1)
+  V3<T> ray(int x, int y) const {
+    T X = (T)x, Y = (T)y;
+    return {fmaT(Kinv[0], X, fmaT(Kinv[1], Y, Kinv[2])),
+            fmaT(Kinv[3], X, fmaT(Kinv[4], Y, Kinv[5])),
+            fmaT(Kinv[6], X, fmaT(Kinv[7], Y, Kinv[8]))};
+  }
+
+  // the same ray in FP64 (used to orient drawn normals)
+  void ray_d(int x, int y, double* r) const {
+    double X = x, Y = y;
+    r[0] = std::fma(Kinv_d[0], X, std::fma(Kinv_d[1], Y, Kinv_d[2]));
+    r[1] = std::fma(Kinv_d[3], X, std::fma(Kinv_d[4], Y, Kinv_d[5]));
+    r[2] = std::fma(Kinv_d[6], X, std::fma(Kinv_d[7], Y, Kinv_d[8]));
+  }
+
+  // bilateral weight factors
+  T w_colour(T da) const {
+    if (!pb->bilateral) return T(1);
+    double d = (double)da;
+    return (T)std::exp(-(d * d) / (2.0 * pb->sigma_c * pb->sigma_c));
+  }
+  T w_space(int k1, int k2) const {
+    if (!pb->bilateral) return T(1);
+    double r2 = (double)(s * s) * (double)(k1 * k1 + k2 * k2);
+    return (T)std::exp(-r2 / (2.0 * pb->sigma_s * pb->sigma_s));
+  }
+
+  // bilinear sample of source view v (1-based view index) at (u, v), position clamped into the image
+  T sample(int view, T u, T v) const {
+    int Wj = pb->width[view], Hj = pb->height[view];
+    const float* img = pb->images[view];
+    u = std::fmin(std::fmax(u, T(0)), (T)(Wj - 1));
+    v = std::fmin(std::fmax(v, T(0)), (T)(Hj - 1));
+    T fx0 = std::floor(u), fy0 = std::floor(v);
+    T fx = u - fx0, fy = v - fy0;
+    int x0 = (int)fx0, y0 = (int)fy0;
+    int x1 = std::min(x0 + 1, Wj - 1), y1 = std::min(y0 + 1, Hj - 1);
+    T i00 = (T)img[(size_t)y0 * Wj + x0], i01 = (T)img[(size_t)y0 * Wj + x1];
+    T i10 = (T)img[(size_t)y1 * Wj + x0], i11 = (T)img[(size_t)y1 * Wj + x1];
+    T top = lerp(i00, i01, fx);
+    T bot = lerp(i10, i11, fx);
+    return lerp(top, bot, fy);
+  }
+
+  // homography of source j (0-based) induced by the plane (n, d) seen at reference pixel p
+  // H_j = M_j + e_j m^T with m = K_0^-T n / rho, rho = d (n . r_p)
+  void homography(int j, const V3<T>& n, T rho, T* Hm) const {
+    T kn[3];
+    for (int c = 0; c < 3; ++c)
+      kn[c] = fmaT(Kinv[0 * 3 + c], n.x, fmaT(Kinv[1 * 3 + c], n.y, Kinv[2 * 3 + c] * n.z));
+    T m[3] = {kn[0] / rho, kn[1] / rho, kn[2] / rho};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) Hm[r * 3 + c] = fmaT(e[3 * j + r], m[c], M[9 * j + r * 3 + c]);
+  }
+
+  // warp reference position (X, Y) with H: returns w (third coordinate) and the divided position
+  T warp(const T* Hm, T X, T Y, T* up, T* vp) const {
+    T u = fmaT(Hm[0], X, fmaT(Hm[1], Y, Hm[2]));
+    T v = fmaT(Hm[3], X, fmaT(Hm[4], Y, Hm[5]));
+    T w = fmaT(Hm[6], X, fmaT(Hm[7], Y, Hm[8]));
+    T r = T(1) / w;
+    *up = u * r;
+    *vp = v * r;
+    return w;
+  }
+
+  // Aggregated cost (Eq. 5 over the best-K valid views) of plane (n, d) at pixel (x, y).
+  // per_view / valid (optional, length n_src) receive each source's C_j and flag.
+  T cost(int x, int y, const V3<T>& n, T d, T* per_view, int32_t* valid_out) const {
+    std::vector<T> cj(n_src, (T)kCmax);
+    std::vector<int> ok(n_src, 0);
+    auto finish = [&]() -> T {
+      if (per_view)
+        for (int j = 0; j < n_src; ++j) per_view[j] = cj[j];
+      if (valid_out)
+        for (int j = 0; j < n_src; ++j) valid_out[j] = ok[j];
+      return aggregate<T>(cj.data(), ok.data(), n_src, pb->top_k, eps_c);
+    };
+
+    V3<T> rp = ray(x, y);
+    T nr = dot3(n, rp);
+    if (!(nr < T(0))) return finish();
+    T rho = d * nr;
+
+    // reference side of the window (independent of the plane and the view)
+    const int R = R_now;
+    const int taps = (2 * R + 1) * (2 * R + 1);
+    std::vector<T> wk(taps), wak(taps);
+    T a_c = ref(x, y);
+    T S_w = 0, S_a = 0, S_aa = 0;
+    for (int k2 = -R, t = 0; k2 <= R; ++k2)
+      for (int k1 = -R; k1 <= R; ++k1, ++t) {
+        T a = ref(x + s * k1, y + s * k2) - a_c;
+        T w = w_colour(a) * w_space(k1, k2);
+        T wa = w * a;
+        S_w = S_w + w;
+        S_a = S_a + wa;
+        S_aa = fmaT(wa, a, S_aa);
+        wk[t] = w;
+        wak[t] = wa;
+      }
+    T mu_a = S_a / S_w;
+    T var_a = S_aa / S_w - mu_a * mu_a;
+    if (!(var_a >= eps_v)) return finish();
+
+    for (int j = 0; j < n_src; ++j) {
+      const int view = j + 1;
+      const T Wm1 = (T)(pb->width[view] - 1), Hm1 = (T)(pb->height[view] - 1);
+      T Hm[9];
+      homography(j, n, rho, Hm);
+      // border rule at the four window corners
+      bool inside = true;
+      const int cx[4] = {-R, R, -R, R}, cy[4] = {-R, -R, R, R};
+      for (int c = 0; c < 4; ++c) {
+        T up, vp;
+        T w = warp(Hm, (T)(x + s * cx[c]), (T)(y + s * cy[c]), &up, &vp);
+        if (!(w > T(0)) || !(up >= T(0) && up <= Wm1 && vp >= T(0) && vp <= Hm1)) inside = false;
+      }
+      if (!inside) continue;
+      T up, vp;
+      warp(Hm, (T)x, (T)y, &up, &vp);
+      T b_c = sample(view, up, vp);
+      T S_b = 0, S_bb = 0, S_ab = 0;
+      for (int k2 = -R, t = 0; k2 <= R; ++k2)
+        for (int k1 = -R; k1 <= R; ++k1, ++t) {
+          warp(Hm, (T)(x + s * k1), (T)(y + s * k2), &up, &vp);
+          T b = sample(view, up, vp) - b_c;
+          T tb = wk[t] * b;
+          S_b = S_b + tb;
+          S_bb = fmaT(tb, b, S_bb);
+          S_ab = fmaT(wak[t], b, S_ab);
+        }
+      T mu_b = S_b / S_w;
+      T var_b = S_bb / S_w - mu_b * mu_b;
+      T cov = S_ab / S_w - mu_a * mu_b;
+      if (!(var_b >= eps_v)) continue;
+      T z = cov / std::sqrt(var_a * var_b);
+      z = std::fmin(std::fmax(z, T(-1)), T(1));
+      cj[j] = T(1) - z;
+      ok[j] = 1;
+    }
+    return finish();
+  }
+
+  void draw(int x, int y, int iteration, int phase, T u[4]) const {
+    uint32_t ctr[4] = {(uint32_t)((uint64_t)y * (uint64_t)W + (uint64_t)x), (uint32_t)iteration,
+                       (uint32_t)phase, 0u};
+    uint32_t key[2] = {(uint32_t)(pb->seed & 0xFFFFFFFFu), (uint32_t)(pb->seed >> 32)};
+    uint32_t o[4];
+    philox4x32_10(ctr, key, o);
+    for (int i = 0; i < 4; ++i) u[i] = (T)unit24(o[i]);
+  }
+
+  // normal from spherical angles (FP64), turned to face the camera at pixel (x, y)
+  V3<T> facing_normal(int x, int y, double theta, double phi) const {
+    double n[3] = {std::cos(theta) * std::sin(phi), std::sin(theta) * std::sin(phi), std::cos(phi)};
+    double r[3];
+    ray_d(x, y, r);
+    if (n[0] * r[0] + n[1] * r[1] + n[2] * r[2] > 0.0) {
+      n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2];
+    }
+    return {(T)n[0], (T)n[1], (T)n[2]};
+  }
+
+  // Sec. III-B: d uniform in the depth range, theta in [0, 2 pi], phi in [-pi/2, pi/2]
+  void init_pixel(int x, int y, T* plane, T* c) const {
+    T u[4];
+    draw(x, y, 0, kPhaseInit, u);
+    T d = fmaT(u[0], d_hi - d_lo, d_lo);
+    double theta = 2.0 * kPi * (double)u[1];
+    double phi = kPi * ((double)u[2] - 0.5);
+    V3<T> n = facing_normal(x, y, theta, phi);
+    plane[0] = n.x; plane[1] = n.y; plane[2] = n.z; plane[3] = d;
+    *c = cost(x, y, n, d, nullptr, nullptr);
+  }
+
+  // red/black propagation of pixel (x, y): reads the other colour's state
+  void propagate_pixel(int x, int y, const T* planes, const T* costs, T* plane_out, T* c_out) const {
+    static const int up_near[9][2] = {{0, -1}, {-1, -2}, {1, -2}, {0, -3}, {-2, -3}, {2, -3}, {-1, -4}, {1, -4}, {0, -5}};
+    const size_t p = (size_t)y * W + x;
+    V3<T> rp = ray(x, y);
+    T best_c = costs[p];
+    int best_g = -1;
+    V3<T> best_n{0, 0, 0};
+    T best_d = 0;
+    for (int g = 0; g < 8; ++g) {
+      const int dir = g & 3;  // up, down, left, right
+      const bool far = g >= 4;
+      const int count = far ? 10 : 9;
+      int qx = -1, qy = -1;
+      T qc = 0;
+      for (int i = 0; i < count; ++i) {
+        int dx = far ? 0 : up_near[i][0];
+        int dy = far ? -(2 * (i + 3) + 1) : up_near[i][1];
+        int ox, oy;
+        if (dir == 0) { ox = dx; oy = dy; }
+        else if (dir == 1) { ox = dx; oy = -dy; }
+        else if (dir == 2) { ox = dy; oy = dx; }
+        else { ox = -dy; oy = dx; }
+        int xq = x + ox, yq = y + oy;
+        if (xq < 0 || xq >= W || yq < 0 || yq >= H || !pixel_valid(xq, yq)) continue;
+        T c = costs[(size_t)yq * W + xq];
+        if (qx < 0 || c < qc) { qx = xq; qy = yq; qc = c; }
+      }
+      if (qx < 0) continue;
+      const T* pq = planes + 4 * ((size_t)qy * W + qx);
+      V3<T> nq{pq[0], pq[1], pq[2]};
+      T dq = pq[3];
+      V3<T> rq = ray(qx, qy);
+      V3<T> Xq{dq * rq.x, dq * rq.y, dq * rq.z};
+      T num = dot3(nq, Xq);
+      T den = dot3(nq, rp);
+      if (!(den < T(0))) continue;
+      T dn = num / den;
+      if (!(dn >= d_lo && dn <= d_hi)) continue;
+      T c = cost(x, y, nq, dn, nullptr, nullptr);
+      if (c < best_c) { best_c = c; best_g = g; best_n = nq; best_d = dn; }
+    }
+    const T* cur = planes + 4 * p;
+    if (best_g >= 0) {
+      plane_out[0] = best_n.x; plane_out[1] = best_n.y; plane_out[2] = best_n.z; plane_out[3] = best_d;
+      *c_out = best_c;
+    } else {
+      for (int i = 0; i < 4; ++i) plane_out[i] = cur[i];
+      *c_out = costs[p];
+    }
+  }
+
+  // random refinement of pixel (x, y) at the given iteration
+  void refine_pixel(int x, int y, int iteration, T* plane, T* c) const {
+    T u[4];
+    draw(x, y, iteration, kPhaseRefine, u);
+    V3<T> n_old{plane[0], plane[1], plane[2]};
+    T d_old = plane[3];
+    T dd = (T(2) * u[0] - T(1)) * (d_hi * T(0.25));
+    T d_new = d_old + dd;
+    bool d_ok = d_new >= d_lo && d_new <= d_hi;
+    double theta = std::atan2((double)n_old.y, (double)n_old.x);
+    double nz = std::fmin(std::fmax((double)n_old.z, -1.0), 1.0);
+    double phi = std::acos(nz);
+    double dtheta = (2.0 * (double)u[1] - 1.0) * (kPi / 2.0);
+    double dphi = (2.0 * (double)u[2] - 1.0) * (kPi / 12.0);
+    V3<T> n_new = facing_normal(x, y, theta + dtheta, phi + dphi);
+    T best = *c;
+    int pick = -1;
+    T c1 = d_ok ? cost(x, y, n_old, d_new, nullptr, nullptr) : (T)kCmax;
+    if (d_ok && c1 < best) { best = c1; pick = 0; }
+    T c2 = cost(x, y, n_new, d_old, nullptr, nullptr);
+    if (c2 < best) { best = c2; pick = 1; }
+    T c3 = d_ok ? cost(x, y, n_new, d_new, nullptr, nullptr) : (T)kCmax;
+    if (d_ok && c3 < best) { best = c3; pick = 2; }
+    if (pick == 0) { plane[3] = d_new; }
+    else if (pick == 1) { plane[0] = n_new.x; plane[1] = n_new.y; plane[2] = n_new.z; }
+    else if (pick == 2) { plane[0] = n_new.x; plane[1] = n_new.y; plane[2] = n_new.z; plane[3] = d_new; }
+    *c = best;
+  }
+};
+
+template <typename T>
+void load_state(const double* planes, const double* costs, size_t n, std::vector<T>& P, std::vector<T>& C) {
+  P.resize(4 * n);
+  C.resize(n);
+  for (size_t i = 0; i < 4 * n; ++i) P[i] = (T)planes[i];
+  for (size_t i = 0; i < n; ++i) C[i] = (T)costs[i];
+}
+
+template <typename T>
+void store_state(const std::vector<T>& P, const std::vector<T>& C, double* planes, double* costs) {
+  for (size_t i = 0; i < P.size(); ++i) planes[i] = (double)P[i];
+  for (size_t i = 0; i < C.size(); ++i) costs[i] = (double)C[i];
+}
+
+template <typename T>
+int run_init(const oracle_problem* pb, double* planes, double* costs) {
+  Solver<T> S;
+  if (!S.setup(pb)) return -1;
+  for (int y = 0; y < S.H; ++y)
+    for (int x = 0; x < S.W; ++x) {
+      size_t p = (size_t)y * S.W + x;
+      T pl[4] = {0, 0, 0, 0}, c = (T)Solver<T>::kCmax;
+      if (S.pixel_valid(x, y)) S.init_pixel(x, y, pl, &c);
+      for (int i = 0; i < 4; ++i) planes[4 * p + i] = (double)pl[i];
+      costs[p] = (double)c;
+    }
+  return 0;
+}
+
+// one half-sweep of one colour: propagation then refinement, on all pixels of the colour
+// (or on the listed ones only; updates within a colour are independent)
+template <typename T>
+int run_halfsweep(const oracle_problem* pb, int iteration, int colour, double* planes, double* costs,
+                  const int32_t* subset, int n_subset, int do_prop, int do_refine) {
+  Solver<T> S;
+  if (!S.setup(pb)) return -1;
+  const size_t n = (size_t)S.W * S.H;
+  std::vector<T> P, C;
+  load_state<T>(planes, costs, n, P, C);
+  std::vector<T> Pn = P, Cn = C;
+  auto visit = [&](int x, int y) {
+    if (((x + y) & 1) != colour || !S.pixel_valid(x, y)) return;
+    size_t p = (size_t)y * S.W + x;
+    T pl[4], c;
+    if (do_prop) S.propagate_pixel(x, y, P.data(), C.data(), pl, &c);
+    else { for (int i = 0; i < 4; ++i) pl[i] = P[4 * p + i]; c = C[p]; }
+    if (do_refine) S.refine_pixel(x, y, iteration, pl, &c);
+    for (int i = 0; i < 4; ++i) Pn[4 * p + i] = pl[i];
+    Cn[p] = c;
+  };
+  if (subset) {
+    for (int i = 0; i < n_subset; ++i) visit(subset[i] % S.W, subset[i] / S.W);
+  } else {
+    for (int y = 0; y < S.H; ++y)
+      for (int x = 0; x < S.W; ++x) visit(x, y);
+  }
+  store_state<T>(Pn, Cn, planes, costs);
+  return 0;
+}
+
+template <typename T>
+int run_patchmatch(const oracle_problem* pb, int iters, float* depth, float* normal, float* cost_out) {
+  Solver<T> S;
+  if (!S.setup(pb)) return -1;
+  const size_t n = (size_t)S.W * S.H;
+  std::vector<T> P(4 * n, T(0)), C(n, (T)Solver<T>::kCmax);
+  for (int y = 0; y < S.H; ++y)
+    for (int x = 0; x < S.W; ++x)
+      if (S.pixel_valid(x, y)) S.init_pixel(x, y, &P[4 * ((size_t)y * S.W + x)], &C[(size_t)y * S.W + x]);
+  for (int it = 1; it <= iters; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      // the other colour is read-only during this half-sweep, so in-place updates are exact
+      for (int y = 0; y < S.H; ++y)
+        for (int x = 0; x < S.W; ++x) {
+          if (((x + y) & 1) != colour || !S.pixel_valid(x, y)) continue;
+          size_t p = (size_t)y * S.W + x;
+          T pl[4], c;
+          S.propagate_pixel(x, y, P.data(), C.data(), pl, &c);
+          S.refine_pixel(x, y, it, pl, &c);
+          for (int i = 0; i < 4; ++i) P[4 * p + i] = pl[i];
+          C[p] = c;
+        }
+    }
+  for (size_t p = 0; p < n; ++p) {
+    int x = (int)(p % S.W), y = (int)(p / S.W);
+    bool v = S.pixel_valid(x, y);
+    depth[p] = v ? (float)P[4 * p + 3] : 0.0f;
+    for (int i = 0; i < 3; ++i) normal[3 * p + i] = v ? (float)P[4 * p + i] : 0.0f;
+    cost_out[p] = v ? (float)C[p] : (float)Solver<T>::kCmax;
+  }
+  return 0;
+}
+
+template <typename T>
+int run_eval(const oracle_problem* pb, const double* planes, double* cost_out, double* per_view,
+             int32_t* valid, const int32_t* subset, int n_subset) {
+  Solver<T> S;
+  if (!S.setup(pb)) return -1;
+  std::vector<T> pv(S.n_src);
+  std::vector<int32_t> ok(S.n_src);
+  auto visit = [&](size_t p) {
+    int x = (int)(p % S.W), y = (int)(p / S.W);
+    T c = (T)Solver<T>::kCmax;
+    std::fill(pv.begin(), pv.end(), (T)Solver<T>::kCmax);
+    std::fill(ok.begin(), ok.end(), 0);
+    if (S.pixel_valid(x, y)) {
+      const double* pl = planes + 4 * p;
+      V3<T> n{(T)pl[0], (T)pl[1], (T)pl[2]};
+      c = S.cost(x, y, n, (T)pl[3], pv.data(), ok.data());
+    }
+    cost_out[p] = (double)c;
+    if (per_view)
+      for (int j = 0; j < S.n_src; ++j) per_view[p * S.n_src + j] = (double)pv[j];
+    if (valid)
+      for (int j = 0; j < S.n_src; ++j) valid[p * S.n_src + j] = ok[j];
+  };
+  if (subset) {
+    for (int i = 0; i < n_subset; ++i) visit((size_t)subset[i]);
+  } else {
+    for (size_t p = 0; p < (size_t)S.W * S.H; ++p) visit(p);
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Philox4x32-10 block: counter ctr[4], key key[2] -> out[4]
+void oracle_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  philox4x32_10(ctr, key, out);
+}
+
+// Full PatchMatch run (init + iters x (red, black)); outputs row-major H x W (x3 for normal).
+int oracle_patchmatch(const oracle_problem* pb, int iters, int fp64, float* depth, float* normal, float* cost) {
+  return fp64 ? run_patchmatch<double>(pb, iters, depth, normal, cost)
+              : run_patchmatch<float>(pb, iters, depth, normal, cost);
+}
+
+// Random initialisation of every pixel: planes (H*W*4: n.x, n.y, n.z, d), costs (H*W).
+int oracle_init(const oracle_problem* pb, int fp64, double* planes, double* costs) {
+  return fp64 ? run_init<double>(pb, planes, costs) : run_init<float>(pb, planes, costs);
+}
+
+// One half-sweep (colour 0 = red (x+y even), 1 = black) in place on (planes, costs).
+int oracle_halfsweep(const oracle_problem* pb, int iteration, int colour, int fp64, double* planes, double* costs,
+                     const int32_t* subset, int n_subset, int do_prop, int do_refine) {
+  return fp64 ? run_halfsweep<double>(pb, iteration, colour, planes, costs, subset, n_subset, do_prop, do_refine)
+              : run_halfsweep<float>(pb, iteration, colour, planes, costs, subset, n_subset, do_prop, do_refine);
+}
+
+// Cost of given planes (H*W*4) at every pixel (or at the listed pixels only).
+int oracle_eval_cost(const oracle_problem* pb, int fp64, const double* planes, double* cost, double* per_view,
+                     int32_t* valid, const int32_t* subset, int n_subset) {
+  return fp64 ? run_eval<double>(pb, planes, cost, per_view, valid, subset, n_subset)
+              : run_eval<float>(pb, planes, cost, per_view, valid, subset, n_subset);
+}
+
+// FP64 homography of source j (0-based) for plane (n, d) seen at reference pixel (x, y).
+int oracle_homography(const oracle_problem* pb, int j, const double* n, double d, int x, int y, double* Hout) {
+  Solver<double> S;
+  if (!S.setup(pb)) return -1;
+  V3<double> nn{n[0], n[1], n[2]};
+  double rho = d * dot3(nn, S.ray(x, y));
+  S.homography(j, nn, rho, Hout);
+  return 0;
+}
+
+// Bilinear sample (position clamped into the image) of a single image.
+double oracle_bilinear(const float* img, int W, int H, double u, double v, int fp64) {
+  int32_t w[2] = {W, W}, h[2] = {H, H};
+  const float* ims[2] = {img, img};
+  oracle_problem pb{};
+  pb.n_views = 2;
+  pb.width = w;
+  pb.height = h;
+  pb.images = ims;
+  if (fp64) {
+    Solver<double> S;
+    S.pb = &pb;
+    return S.sample(1, u, v);
+  }
+  Solver<float> S;
+  S.pb = &pb;
+  return (double)S.sample(1, (float)u, (float)v);
+}
+
+// Eq. 5 over the best-K valid views, for hand-set per-view costs.
+double oracle_aggregate(const double* cj, const int32_t* valid, int n, int top_k, double eps_c, int fp64) {
+  std::vector<int> ok(valid, valid + n);
+  if (fp64) return aggregate<double>(cj, ok.data(), n, top_k, eps_c);
+  std::vector<float> cf(cj, cj + n);
+  return (double)aggregate<float>(cf.data(), ok.data(), n, top_k, (float)eps_c);
+}
+
+}  // extern "C"
