@@ -1,0 +1,194 @@
+#!/usr/bin/env python
+"""Benchmark of the PatchMatch depth-map estimation step on one MI355X.
+
+A step is one whole depth map: random initialisation plus 8 iterations of red/black
+propagation and refinement, with outputs (depth, normal, cost) in device memory.  The
+default workload is the 3200x2130 reference with 10 sources, a 31x31 window at
+dilation 3 (11x11 taps), top-5 aggregation and 8 iterations, on a seeded synthetic
+piecewise-planar scene; images are resident in HBM before the timed region.
+
+Printed: one JSON line with the metric, the evaluate-and-select kernel's roofline
+figures (live HIP-event timing of every launch in the timed region, algorithmic flops
+from the exact number of hypotheses scored) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms per 3200×2130 depth map (10 src, 8 it); learned vs random init at equal cost"
+FLOPS_PER_TAP_VIEW = 23            # algorithmic flops per (tap, view), FMA = 2
+PEAK_FP32_VECTOR_TFLOPS = 157.3    # MI355X FP32 vector peak: 256 CU x 2.4 GHz x 256 flop/clk
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def nominal_tap_views(valid_px, n_src, taps, iters):
+    # 1 initial hypothesis + per iteration 8 propagation + 3 refinement candidates
+    return valid_px * (1 + 11 * iters) * n_src * taps
+
+
+def cpu_baseline(scene_full, solver, iters, crop=(320, 213)):
+    """The plain single-threaded oracle on the centre crop (its own problem instance),
+    init + `iters` iterations, scaled to one full depth map by nominal tap-views."""
+    import oracle
+    import scenegen as sg
+
+    sc = sg.crop_reference(scene_full, *crop)
+    pb = oracle.Problem.from_scene(sc, solver["window"], solver["dilation"], top_k=solver["top_k"],
+                                   bilateral=True, sigma_s=(solver["window"] - 1) / 2.0, sigma_c=12.0,
+                                   seed=sg.PM_SEED)
+    t0 = time.perf_counter()
+    oracle.patchmatch(pb, iters)
+    dt = time.perf_counter() - t0
+    R = (solver["window"] - 1) // (2 * solver["dilation"])
+    taps = (2 * R + 1) ** 2
+    n_src = len(sc.images) - 1
+    sample_tv = nominal_tap_views(int(pb.valid_mask().sum()), n_src, taps, iters)
+    H, W = scene_full.images[0].shape
+    r = solver["dilation"] * R
+    full_valid = max(0, H - 2 * r) * max(0, W - 2 * r)
+    full_tv = nominal_tap_views(full_valid, n_src, taps, solver["iters"])
+    return {
+        "value": dt * 1e3 * full_tv / sample_tv,
+        "unit": "ms per depth map (extrapolated)",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{crop[0]}x{crop[1]} centre crop of the reference (sources whole), init + {iters} iteration(s), "
+                  f"FP32 oracle single-threaded, {dt:.2f} s for {sample_tv:.3e} nominal tap-views; scaled by "
+                  f"nominal tap-views to the full {W}x{H} {solver['iters']}-iteration depth map ({full_tv:.3e})",
+        "sample_seconds": dt,
+        "ns_per_tap_view": dt * 1e9 / sample_tv,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="highres", choices=["highres", "mid", "mid_dense", "tiny"])
+    ap.add_argument("--cpu-iters", type=int, default=1, help="iterations of the oracle's bounded sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs the depth-map estimation on one GPU; --gpus above 1 is not "
+              "supported (see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2104_06165_amd as pm
+    import scenegen as sg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = args.workload
+    scene_name = "mid" if wl.startswith("mid") else wl
+    solver = sg.SOLVER[wl]
+    cfg = sg.CONFIGS[scene_name]
+    log(f"[bench] rendering the {wl} scene ({cfg.width}x{cfg.height}, {cfg.n_src} sources, {cfg.n_planes} planes)")
+    t0 = time.time()
+    scene = sg.workload_scene(scene_name, device="cuda")
+    log(f"[bench] scene ready in {time.time() - t0:.1f} s")
+
+    ctx = pm.Context(0)
+    ctx.set_scene(scene)
+    n_src = len(scene.images) - 1
+    srcs = list(range(1, n_src + 1))
+    params = pm.Params(top_k=solver["top_k"], bilateral=True, sigma_spatial_px=(solver["window"] - 1) / 2.0,
+                       seed=sg.PM_SEED)
+    H, W = scene.images[0].shape
+    out = (torch.empty((H, W), dtype=torch.float32, device="cuda"),
+           torch.empty((H, W, 3), dtype=torch.float32, device="cuda"),
+           torch.empty((H, W), dtype=torch.float32, device="cuda"))
+
+    def run():
+        return ctx.patchmatch(0, srcs, solver["window"], solver["dilation"], solver["iters"], params, out=out)
+
+    # exact number of hypotheses scored per depth map (deterministic: counter-based RNG)
+    ctx.diag_enable(pm.DIAG_COUNT)
+    run()
+    n_hyp, _, _ = ctx.diag_read()
+    ctx.diag_enable(0)
+    for i in range(args.warmup):
+        run()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+
+    ctx.diag_enable(pm.DIAG_TIME)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    _, launches, kernel_ms = ctx.diag_read()
+    ctx.diag_enable(0)
+    ms_per_step = elapsed * 1e3 / args.steps
+    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms per depth map")
+
+    R = (solver["window"] - 1) // (2 * solver["dilation"])
+    taps = (2 * R + 1) ** 2
+    launches_per_step = launches / args.steps
+    flops_per_step = float(n_hyp) * n_src * taps * FLOPS_PER_TAP_VIEW
+    avg_launch_ms = kernel_ms / launches
+    achieved = flops_per_step / launches_per_step / (avg_launch_ms * 1e-3) / 1e12
+    depth, normal, cost = out
+    d = depth.cpu().numpy()
+    c = cost.cpu().numpy()
+    r = solver["dilation"] * R
+    valid = np.zeros_like(d, dtype=bool)
+    valid[r:H - r, r:W - r] = True
+    rel = np.abs(d - scene.gt_depth) / scene.gt_depth
+    textured = scene.textured[scene.gt_plane]
+
+    line = {
+        "metric": METRIC,
+        "value": ms_per_step,
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": f"synthetic (seeded piecewise-planar scene, seed {sg.SCENE_SEEDS[scene_name]}); random init",
+        "config": {"workload": f"{wl}: 1 reference + {n_src} sources at {W}x{H}, {solver['window']}x{solver['window']} "
+                               f"window at dilation {solver['dilation']} ({2 * R + 1}x{2 * R + 1} taps), "
+                               f"top-{solver['top_k']}, {solver['iters']} iterations",
+                   "width": W, "height": H, "n_src": n_src, "window": solver["window"],
+                   "dilation": solver["dilation"], "top_k": solver["top_k"], "iters": solver["iters"],
+                   "planes": cfg.n_planes, "images": "fp16 in HBM", "cost": "fp32"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": "select_kernel (evaluate-and-select)", "avg_launch_ms": avg_launch_ms,
+                     "launches_per_step": launches_per_step,
+                     "kernel_share_of_step": kernel_ms / (elapsed * 1e3)},
+        "hypotheses_per_step": n_hyp,
+        "cost_evals_per_s": n_hyp * n_src / (ms_per_step * 1e-3),
+        "tap_views_per_s": n_hyp * n_src * taps / (ms_per_step * 1e-3),
+        "quality": {"mean_cost": float(c[valid].mean()),
+                    "depth_within_1pct": float((rel[valid] < 0.01).mean()),
+                    "depth_within_1pct_textured": float((rel[valid & textured] < 0.01).mean())},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on its bounded sample")
+        line["cpu_baseline"] = cpu_baseline(scene, solver, args.cpu_iters)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

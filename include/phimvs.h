@@ -1,0 +1,164 @@
+/*
+ * phimvs.h — C ABI of the MI355X (gfx950) PatchMatch multi-view stereo library.
+ *
+ * The library computes, for each pixel x of a reference image, a plane hypothesis
+ * (depth d_x, normal n_x) from the reference image, a set of source images and their
+ * cameras: the "depth map estimation" step of PHI-MVS (paper Sec. III intro, Sec.
+ * III-B, Sec. III-C, Algorithm 1).  Hypotheses are scored by the weighted ZNCC of a
+ * dilated support window (Eq. 4) warped into each source by the plane-induced
+ * homography, aggregated over the best-K sources (Eq. 5), and searched by random
+ * initialisation, red/black checkerboard propagation and random refinement.
+ *
+ * Conventions
+ *   - Images are row-major, pixel (x, y) at column x, row y; pixel centres sit at
+ *     integer coordinates.  8-bit grey values (PHIMVS_U8) are the supported input.
+ *   - Cameras map world to camera: X_cam = R X_world + t.  K is 3x3 with last row
+ *     (0, 0, 1).  All camera matrices are row-major doubles.
+ *   - Depth is the reference camera's Z.  Normals are in the reference camera frame,
+ *     facing the camera (n . K^-1 (x, y, 1) < 0).
+ *   - Outputs are row-major: depth H*W, normal H*W*3, cost H*W (float32).  Pixels
+ *     whose reference window leaves the image are invalid: depth 0, normal 0,
+ *     cost PHIMVS_COST_MAX.
+ *   - "planes" arrays are H*W*4 float32 (n.x, n.y, n.z, d) per pixel, row-major.
+ *
+ * Ownership and memory
+ *   - The caller owns every buffer it passes.  phimvs_set_views copies the images
+ *     (host or device) into library-owned device memory; the caller may free its
+ *     copies on return.
+ *   - Arguments with an "on_device" flag are device pointers (on the context's
+ *     device) when the flag is non-zero, host pointers otherwise.  Device outputs are
+ *     written asynchronously on the context's stream; host outputs are complete when
+ *     the call returns.
+ *
+ * Errors and threading
+ *   - Every int-returning call returns PHIMVS_OK (0) or a negative PHIMVS_E_* code and
+ *     then sets a message readable with phimvs_last_error.  No exception crosses the
+ *     ABI.  A context is not thread-safe: use one context per host thread / stream.
+ */
+#ifndef PHIMVS_H
+#define PHIMVS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PHIMVS_COST_MAX 2.0f /* C_max = 1 - Z_min with Z_min = -1 (Sec. III-C, Eq. 5) */
+#define PHIMVS_MAX_SOURCES 12
+
+enum {
+  PHIMVS_OK = 0,
+  PHIMVS_E_ARG = -1,         /* invalid argument (message names it)                 */
+  PHIMVS_E_STATE = -2,       /* call out of order (e.g. step before prepare)         */
+  PHIMVS_E_DEVICE = -3,      /* HIP runtime error                                    */
+  PHIMVS_E_OOM = -4,         /* device allocation failed                             */
+  PHIMVS_E_UNSUPPORTED = -5  /* valid request the library does not implement         */
+};
+
+enum { PHIMVS_U8 = 0 };
+
+typedef struct phimvs_ctx phimvs_ctx;
+
+/* One input image.  stride_bytes = 0 means tightly packed rows. */
+typedef struct {
+  int32_t width, height;
+  int64_t stride_bytes;
+  int32_t dtype;       /* PHIMVS_U8 */
+  const void* data;
+  int32_t on_device;   /* non-zero: data is a device pointer */
+} phimvs_image;
+
+/* Solver parameters (Sec. III-C); phimvs_default_params fills the defaults. */
+typedef struct {
+  int32_t top_k;            /* Eq. 5 over the K lowest-cost valid sources; 0 = all (the paper's Eq. 5) */
+  int32_t bilateral;        /* 0: weight 1 on every tap (Eq. 4 exactly); 1: bilateral weights           */
+  double sigma_spatial_px;  /* bilateral spatial sigma in full-resolution px; <= 0: window radius        */
+  double sigma_color;       /* bilateral colour sigma in grey levels (default 12)                      */
+  double eps_var;           /* a patch with weighted variance below this is invalid (default 1e-4)     */
+  double eps_cost;          /* per-source cost floor in the inverse weights of Eq. 5 (default 1e-4)    */
+  uint64_t seed;            /* Philox4x32-10 key for the random draws (default 0x5EED)                 */
+} phimvs_params;
+
+void phimvs_default_params(phimvs_params* p);
+
+/* Create a context on HIP device `device_ordinal`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+int phimvs_create(phimvs_ctx** out, int device_ordinal, void* hip_stream);
+void phimvs_destroy(phimvs_ctx* ctx);
+const char* phimvs_last_error(const phimvs_ctx* ctx);
+/* Re-target the context's stream (e.g. the caller's current stream). */
+int phimvs_set_stream(phimvs_ctx* ctx, void* hip_stream);
+/* Block until all work issued on the context's stream has finished. */
+int phimvs_sync(phimvs_ctx* ctx);
+
+/* Upload the images and cameras of a scene (paper Sec. III: "images and camera
+ * parameters" are the input).  K, R: n_views*9; t: n_views*3; depth_range:
+ * n_views*2 (d_lo, d_hi per view, used when that view is the reference; requires
+ * 0 < d_lo < d_hi).  Replaces any previous scene. */
+int phimvs_set_views(phimvs_ctx* ctx, int n_views, const phimvs_image* images, const double* K,
+                     const double* R, const double* t, const double* depth_range);
+
+/* Full depth-map estimation of view `ref` against sources `srcs` (Algorithm 1
+ * "depth map estimation": random initialisation, then `iters` x (red half-sweep,
+ * black half-sweep), each half-sweep = propagation then random refinement).
+ * window: odd side length in full-resolution px; dilation: tap stride s with
+ * (window - 1) % (2 s) == 0, so taps are x + s k, k = -r..r, r = (window-1)/(2 s)
+ * (Sec. III-C, dilated matching window).  p = NULL uses the defaults.  Outputs as
+ * described above, on device if out_on_device. */
+int phimvs_patchmatch(phimvs_ctx* ctx, int ref, const int* srcs, int n_srcs, int window, int dilation,
+                      int iters, const phimvs_params* p, float* depth, float* normal, float* cost,
+                      int out_on_device);
+
+/* ---- step-wise interface (the same computation, one stage at a time) ---- */
+
+/* Fix the problem for the calls below and allocate its state. */
+int phimvs_prepare(phimvs_ctx* ctx, int ref, const int* srcs, int n_srcs, int window, int dilation,
+                   const phimvs_params* p);
+/* Random initialisation (Sec. III-B) of every valid pixel, with its cost.  If
+ * `proposal` (planes layout) is given, each pixel keeps the proposal instead of its
+ * random plane when the proposal's cost is not higher (learned-initialisation gate). */
+int phimvs_init_planes(phimvs_ctx* ctx, const float* proposal, int on_device);
+/* One half-sweep: propagation from the other colour then random refinement (Sec.
+ * III-C) of colour `colour` (0: red, (x + y) even; 1: black) at iteration
+ * `iteration` (>= 1; it keys the random draws).  do_propagate / do_refine select
+ * the two stages (both 1 in the full method). */
+int phimvs_step(phimvs_ctx* ctx, int iteration, int colour, int do_propagate, int do_refine);
+/* Read / overwrite the current state (planes layout + cost H*W). */
+int phimvs_get_state(phimvs_ctx* ctx, float* planes, float* cost, int on_device);
+int phimvs_set_state(phimvs_ctx* ctx, const float* planes, const float* cost, int on_device);
+/* Write depth / normal / cost of the current state (output layout). */
+int phimvs_output(phimvs_ctx* ctx, float* depth, float* normal, float* cost, int on_device);
+/* Cost (Eq. 5) of the given planes at every pixel; per_view (H*W*n_srcs, or NULL)
+ * receives each source's 1 - Z (PHIMVS_COST_MAX when that source is invalid) and
+ * valid (H*W*n_srcs bytes, or NULL) its validity flag. */
+int phimvs_eval_cost(phimvs_ctx* ctx, const float* planes, float* cost, float* per_view, uint8_t* valid,
+                     int on_device);
+
+/* ---- diagnostics ---- */
+
+/* flags: PHIMVS_DIAG_COUNT counts the (pixel, hypothesis) pairs the evaluate-and-select
+ * kernels score; PHIMVS_DIAG_TIME brackets every evaluate-and-select launch with HIP
+ * events on the context's stream.  Enabling resets both; 0 disables. */
+enum { PHIMVS_DIAG_COUNT = 1, PHIMVS_DIAG_TIME = 2 };
+int phimvs_diag_enable(phimvs_ctx* ctx, int flags);
+/* Synchronise the stream and read the diagnostics gathered since enabling: hypotheses
+ * scored, number of evaluate-and-select launches timed and their summed duration (ms).
+ * Any pointer may be NULL. */
+int phimvs_diag_read(phimvs_ctx* ctx, uint64_t* hypotheses, uint64_t* launches, double* kernel_ms);
+
+/* ---- self-test ---- */
+
+/* The kernels divide by the third homogeneous coordinate w of every warped tap with a
+ * fast reciprocal that must equal the correctly rounded 1/w on [2^-100, 2^100] (the
+ * kernels fall back to IEEE division outside it).  This compares that reciprocal with
+ * the correctly rounded one on the float bit patterns [first_bits, first_bits + count)
+ * and returns the number of mismatches (and one mismatching pattern). */
+int phimvs_check_reciprocal(phimvs_ctx* ctx, uint32_t first_bits, uint32_t count, uint64_t* mismatches,
+                            uint32_t* example_bits);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHIMVS_H */

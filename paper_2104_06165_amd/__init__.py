@@ -1,0 +1,280 @@
+"""Python binding of the MI355X PatchMatch multi-view stereo library (``libphimvs.so``).
+
+Argument marshalling only: every step of the depth-map estimation runs in the HIP
+kernels behind the C ABI declared in ``include/phimvs.h``.  Device buffers are torch
+tensors on the context's GPU; work is issued on torch's current stream.  Importing
+this package does not need a GPU, but creating a ``Context`` does, and a missing or
+unbuilt library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphimvs.so")
+
+PHIMVS_OK = 0
+ERRORS = {-1: "PHIMVS_E_ARG", -2: "PHIMVS_E_STATE", -3: "PHIMVS_E_DEVICE", -4: "PHIMVS_E_OOM",
+          -5: "PHIMVS_E_UNSUPPORTED"}
+COST_MAX = 2.0
+MAX_SOURCES = 12
+
+#: every symbol the C ABI exports (include/phimvs.h)
+EXPORTS = ("phimvs_default_params", "phimvs_create", "phimvs_destroy", "phimvs_last_error", "phimvs_set_stream",
+           "phimvs_sync", "phimvs_set_views", "phimvs_patchmatch", "phimvs_prepare", "phimvs_init_planes",
+           "phimvs_step", "phimvs_get_state", "phimvs_set_state", "phimvs_output", "phimvs_eval_cost",
+           "phimvs_diag_enable", "phimvs_diag_read", "phimvs_check_reciprocal")
+DIAG_COUNT = 1
+DIAG_TIME = 2
+
+
+class PhimvsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Image(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("stride_bytes", C.c_int64), ("dtype", C.c_int32),
+                ("data", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("top_k", C.c_int32), ("bilateral", C.c_int32), ("sigma_spatial_px", C.c_double),
+                ("sigma_color", C.c_double), ("eps_var", C.c_double), ("eps_cost", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+@dataclass
+class Params:
+    top_k: int = 0
+    bilateral: bool = True
+    sigma_spatial_px: float = 0.0  # <= 0: the window radius
+    sigma_color: float = 12.0
+    eps_var: float = 1e-4
+    eps_cost: float = 1e-4
+    seed: int = 0x5EED
+
+    def _c(self) -> _Params:
+        return _Params(int(self.top_k), 1 if self.bilateral else 0, float(self.sigma_spatial_px),
+                       float(self.sigma_color), float(self.eps_var), float(self.eps_cost),
+                       int(self.seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+_lib = None
+
+
+def lib():
+    """Load libphimvs.so (built by ``paper_2104_06165_amd.build``); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2104_06165_amd.build` "
+                              "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, fp, dp = C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double)
+        L.phimvs_default_params.argtypes = [C.POINTER(_Params)]
+        L.phimvs_default_params.restype = None
+        L.phimvs_create.argtypes = [C.POINTER(vp), ip, vp]
+        L.phimvs_destroy.argtypes = [vp]
+        L.phimvs_destroy.restype = None
+        L.phimvs_last_error.argtypes = [vp]
+        L.phimvs_last_error.restype = C.c_char_p
+        L.phimvs_set_stream.argtypes = [vp, vp]
+        L.phimvs_sync.argtypes = [vp]
+        L.phimvs_set_views.argtypes = [vp, ip, C.POINTER(_Image), dp, dp, dp, dp]
+        L.phimvs_patchmatch.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip, ip, ip, C.POINTER(_Params), fp, fp, fp, ip]
+        L.phimvs_prepare.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip, ip, C.POINTER(_Params)]
+        L.phimvs_init_planes.argtypes = [vp, fp, ip]
+        L.phimvs_step.argtypes = [vp, ip, ip, ip, ip]
+        L.phimvs_get_state.argtypes = [vp, fp, fp, ip]
+        L.phimvs_set_state.argtypes = [vp, fp, fp, ip]
+        L.phimvs_output.argtypes = [vp, fp, fp, fp, ip]
+        L.phimvs_eval_cost.argtypes = [vp, fp, fp, fp, vp, ip]
+        L.phimvs_diag_enable.argtypes = [vp, ip]
+        L.phimvs_diag_read.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
+        L.phimvs_check_reciprocal.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64),
+                                              C.POINTER(C.c_uint32)]
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if name not in ("phimvs_default_params", "phimvs_destroy", "phimvs_last_error"):
+                f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def default_params() -> Params:
+    p = _Params()
+    lib().phimvs_default_params(C.byref(p))
+    return Params(p.top_k, bool(p.bilateral), p.sigma_spatial_px, p.sigma_color, p.eps_var, p.eps_cost, p.seed)
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Context:
+    """One library context on one GPU, issuing work on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        torch.cuda.init()
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib().phimvs_create(C.byref(h), device, C.c_void_p(stream))
+        if rc != PHIMVS_OK:
+            raise PhimvsError(rc, "phimvs_create failed")
+        self.h = h
+        self.W = self.H = None
+        self.n_src = None
+        self.views = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().phimvs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != PHIMVS_OK:
+            raise PhimvsError(rc, lib().phimvs_last_error(self.h).decode())
+
+    def _sync_stream(self):
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        self._check(lib().phimvs_set_stream(self.h, C.c_void_p(s)))
+
+    # ------------------------------------------------------------------ scene
+    def set_views(self, images: Sequence, K, R, t, depth_ranges):
+        """images: uint8 arrays (H, W) (numpy on the host, or torch on this device)."""
+        self._sync_stream()
+        n = len(images)
+        ims = (_Image * n)()
+        keep = []
+        for i, im in enumerate(images):
+            if isinstance(im, np.ndarray):
+                a = np.ascontiguousarray(im, dtype=np.uint8)
+                keep.append(a)
+                ims[i] = _Image(a.shape[1], a.shape[0], 0, 0, a.ctypes.data, 0)
+            else:
+                a = im.contiguous()
+                if a.dtype != self.torch.uint8:
+                    raise TypeError("images must be uint8")
+                keep.append(a)
+                ims[i] = _Image(a.shape[1], a.shape[0], 0, 0, a.data_ptr(), 1)
+        Kd = np.ascontiguousarray(np.asarray(K, dtype=np.float64).reshape(n, 9))
+        Rd = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(n, 9))
+        td = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(n, 3))
+        dr = np.ascontiguousarray(np.asarray(depth_ranges, dtype=np.float64).reshape(n, 2))
+        dp = C.POINTER(C.c_double)
+        self._check(lib().phimvs_set_views(self.h, n, ims, Kd.ctypes.data_as(dp), Rd.ctypes.data_as(dp),
+                                           td.ctypes.data_as(dp), dr.ctypes.data_as(dp)))
+        self.views = [(int(a.shape[0]), int(a.shape[1])) for a in keep]
+
+    def set_scene(self, scene):
+        """Upload a ``scenegen.Scene`` (every view uses the scene's depth range)."""
+        n = len(scene.images)
+        self.set_views(scene.images, scene.K, scene.R, scene.t, np.tile(np.asarray(scene.depth_range), (n, 1)))
+
+    # ------------------------------------------------------------------ full run
+    def patchmatch(self, ref: int, srcs: Sequence[int], window: int, dilation: int, iters: int,
+                   params: Optional[Params] = None, out=None):
+        """-> (depth (H, W), normal (H, W, 3), cost (H, W)) float32 tensors on the device."""
+        torch = self.torch
+        self._sync_stream()
+        # an out-of-range ref is the library's to reject (PHIMVS_E_ARG)
+        H, W = self.views[ref] if 0 <= ref < len(self.views) else (1, 1)
+        if out is None:
+            out = (torch.empty((H, W), dtype=torch.float32, device=self.device),
+                   torch.empty((H, W, 3), dtype=torch.float32, device=self.device),
+                   torch.empty((H, W), dtype=torch.float32, device=self.device))
+        sa = (C.c_int * len(srcs))(*srcs)
+        p = (params or default_params())._c()
+        self._check(lib().phimvs_patchmatch(self.h, ref, sa, len(srcs), window, dilation, iters, C.byref(p),
+                                            out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), 1))
+        return out
+
+    # ------------------------------------------------------------------ step-wise
+    def prepare(self, ref: int, srcs: Sequence[int], window: int, dilation: int, params: Optional[Params] = None):
+        self._sync_stream()
+        sa = (C.c_int * len(srcs))(*srcs)
+        p = (params or default_params())._c()
+        self._check(lib().phimvs_prepare(self.h, ref, sa, len(srcs), window, dilation, C.byref(p)))
+        self.H, self.W = self.views[ref]  # ref validated by the library
+        self.n_src = len(srcs)
+
+    def init_planes(self, proposal=None):
+        self._sync_stream()
+        self._check(lib().phimvs_init_planes(self.h, _dptr(proposal), 1))
+
+    def step(self, iteration: int, colour: int, propagate: bool = True, refine: bool = True):
+        self._sync_stream()
+        self._check(lib().phimvs_step(self.h, iteration, colour, int(propagate), int(refine)))
+
+    def get_state(self):
+        torch = self.torch
+        self._sync_stream()
+        planes = torch.empty((self.H, self.W, 4), dtype=torch.float32, device=self.device)
+        cost = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
+        self._check(lib().phimvs_get_state(self.h, planes.data_ptr(), cost.data_ptr(), 1))
+        return planes, cost
+
+    def set_state(self, planes, cost):
+        self._sync_stream()
+        planes = planes.contiguous().float()
+        cost = cost.contiguous().float()
+        self._check(lib().phimvs_set_state(self.h, planes.data_ptr(), cost.data_ptr(), 1))
+        self._keep = (planes, cost)
+
+    def output(self):
+        torch = self.torch
+        self._sync_stream()
+        d = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
+        n = torch.empty((self.H, self.W, 3), dtype=torch.float32, device=self.device)
+        c = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
+        self._check(lib().phimvs_output(self.h, d.data_ptr(), n.data_ptr(), c.data_ptr(), 1))
+        return d, n, c
+
+    def eval_cost(self, planes, per_view: bool = False):
+        """Cost of the given planes (H, W, 4) -> cost (H, W) [, per-view (H, W, n), valid (H, W, n)]."""
+        torch = self.torch
+        self._sync_stream()
+        planes = planes.contiguous().float()
+        cost = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
+        pv = vm = None
+        if per_view:
+            pv = torch.empty((self.H, self.W, self.n_src), dtype=torch.float32, device=self.device)
+            vm = torch.empty((self.H, self.W, self.n_src), dtype=torch.uint8, device=self.device)
+        self._check(lib().phimvs_eval_cost(self.h, planes.data_ptr(), cost.data_ptr(), _dptr(pv), _dptr(vm), 1))
+        return (cost, pv, vm) if per_view else cost
+
+    def sync(self):
+        self._check(lib().phimvs_sync(self.h))
+
+    def diag_enable(self, flags: int):
+        self._sync_stream()
+        self._check(lib().phimvs_diag_enable(self.h, flags))
+
+    def diag_read(self):
+        """-> (hypotheses scored, evaluate launches timed, their summed duration in ms)."""
+        n, l, ms = C.c_uint64(), C.c_uint64(), C.c_double()
+        self._check(lib().phimvs_diag_read(self.h, C.byref(n), C.byref(l), C.byref(ms)))
+        return int(n.value), int(l.value), float(ms.value)
+
+    def check_reciprocal(self, first_bits: int, count: int):
+        m = C.c_uint64()
+        e = C.c_uint32()
+        self._check(lib().phimvs_check_reciprocal(self.h, first_bits, count, C.byref(m), C.byref(e)))
+        return int(m.value), int(e.value)

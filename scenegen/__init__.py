@@ -355,7 +355,8 @@ def _render(world: _World, K, R_m, C_m, w, h, view_key, noise_sigma, seed, chunk
     C = torch.tensor(C_m, dtype=_DT, device=d)
     img = torch.empty((h, w), dtype=_DT, device=d)
     if chunk_rows is None:
-        chunk_rows = max(1, int(1_000_000 // w))
+        budget = 4_000_000 if str(d).startswith("cuda") else 1_000_000
+        chunk_rows = max(1, int(budget // w))
     xs = torch.arange(w, dtype=_DT, device=d)
     for y0 in range(0, h, chunk_rows):
         y1 = min(h, y0 + chunk_rows)

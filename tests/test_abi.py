@@ -1,0 +1,47 @@
+"""The C-ABI library loads and exports every entry point include/phimvs.h declares
+(no GPU needed: only symbol lookup and the argument checks that fail before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2104_06165_amd as pm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "phimvs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(phimvs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("phimvs_create", "phimvs_set_views", "phimvs_patchmatch", "phimvs_eval_cost",
+                     "phimvs_step", "phimvs_get_state", "phimvs_set_state", "phimvs_init_planes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(pm.LIB_PATH)
+    names = _declared()
+    assert names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pm.EXPORTS)
+
+
+def test_default_params_and_null_context_errors():
+    p = pm.default_params()
+    assert p.top_k == 0 and p.bilateral and p.sigma_color == 12.0 and p.eps_var == 1e-4 and p.seed == 0x5EED
+    L = pm.lib()
+    # calls on a null context fail with PHIMVS_E_ARG instead of crashing
+    assert L.phimvs_prepare(None, 0, None, 0, 7, 1, None) == -1
+    assert L.phimvs_step(None, 1, 0, 1, 1) == -1
+    assert L.phimvs_set_views(None, 2, None, None, None, None, None) == -1
+    assert L.phimvs_last_error(None) == b"null context"
+    out = ctypes.c_void_p()
+    rc = L.phimvs_create(ctypes.byref(out), -1, None)
+    assert rc in (-3,)  # no such device
