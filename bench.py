@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--workload", default="highres", choices=["highres", "mid", "mid_dense", "tiny"])
     ap.add_argument("--cpu-iters", type=int, default=1, help="iterations of the oracle's bounded sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM-counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -92,6 +94,16 @@ def main():
     import scenegen as sg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        # one elementwise kernel that reads and writes exactly n bytes each
+        n = args.copy_calibration << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
+        return
     wl = args.workload
     scene_name = "mid" if wl.startswith("mid") else wl
     solver = sg.SOLVER[wl]

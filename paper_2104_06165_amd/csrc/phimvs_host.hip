@@ -27,7 +27,7 @@ struct ViewData {
   double K[9], R[9], t[3];
   double d_lo = 0, d_hi = 0;
   __half* plain = nullptr;
-  uint2* quad = nullptr;
+  uint32_t* quad = nullptr;
 };
 
 template <typename T>
@@ -266,7 +266,7 @@ int phimvs_set_views(phimvs_ctx* c, int n_views, const phimvs_image* images, con
     v.d_hi = depth_range[2 * i + 1];
     const size_t npx = (size_t)v.W * v.H;
     HIPCHECK(c, hipMalloc((void**)&v.plain, npx * sizeof(__half)));
-    HIPCHECK(c, hipMalloc((void**)&v.quad, npx * sizeof(uint2)));
+    HIPCHECK(c, hipMalloc((void**)&v.quad, npx * sizeof(uint32_t)));
     const int64_t stride = im.stride_bytes ? im.stride_bytes : im.width;
     int rc = ensure(c, c->io_u8, npx);
     if (rc) return rc;

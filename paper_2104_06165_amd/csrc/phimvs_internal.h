@@ -16,7 +16,7 @@ struct SrcDev {
   float e[3];           // K_j t_rel
   float Wm1, Hm1;       // last valid sample position
   int W, H;
-  const uint2* quad;    // W*H fp16 texel quads
+  const uint32_t* quad; // W*H 8-bit texel quads
 };
 
 // problem block, passed by value (kernel arguments live in the constant path)
@@ -52,7 +52,7 @@ struct Step {
 hipError_t launch_select(int mode, const Args& A, const Step& S, hipStream_t st);
 // kind 0: random initialisation (+ proposal), 1: propagation, 2: refinement candidates
 hipError_t launch_candidates(int kind, const Args& A, const Step& S, hipStream_t st);
-hipError_t launch_build_view(const uint8_t* img, int64_t stride, int W, int H, __half* plain, uint2* quad,
+hipError_t launch_build_view(const uint8_t* img, int64_t stride, int W, int H, __half* plain, uint32_t* quad,
                              hipStream_t st);
 hipError_t launch_unpack(const Args& A, float* planes, float* depth, float* normal, float* cost, hipStream_t st);
 hipError_t launch_pack(const Args& A, const float* planes, const float* cost, hipStream_t st);

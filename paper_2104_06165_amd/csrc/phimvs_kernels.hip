@@ -62,20 +62,21 @@ __device__ __forceinline__ float rcp_nr(float w) {
   return __builtin_fmaf(e, r0, r0);
 }
 
-__device__ __forceinline__ float h_lo(uint32_t v) { return __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))); }
-__device__ __forceinline__ float h_hi(uint32_t v) { return __half2float(__ushort_as_half((unsigned short)(v >> 16))); }
-
 // bilinear sample from a texel-quad image at a position already clamped into the image:
-// quad (x0, y0) = (I[y0][x0], I[y0][x1] - I[y0][x0], I[y1][x0], I[y1][x1] - I[y1][x0]),
-// so lerp(a, b, t) = fma(t, b - a, a) needs no subtraction for the two row lerps.
-__device__ __forceinline__ float sample_quad(const uint2* __restrict__ quad, int W, float up, float vp) {
+// the 32-bit quad at (x0, y0) holds the bytes I[y0][x0], I[y0][x1], I[y1][x0], I[y1][x1]
+// (x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1)); lerp(a, b, t) = fma(t, b - a, a) with
+// exact integer differences.  Four bytes per record (half of an fp16 quad) halve the L1
+// lines each lane's window walks through, which is what bounds the gathers.
+__device__ __forceinline__ float sample_quad(const uint32_t* __restrict__ quad, int W, float up, float vp) {
   // up, vp >= 0: fract(u) = u - floor(u) exactly
   const float fx = __builtin_amdgcn_fractf(up);
   const float fy = __builtin_amdgcn_fractf(vp);
   const uint32_t x0 = (uint32_t)up, y0 = (uint32_t)vp;
-  const uint2 q = quad[__umul24(y0, (uint32_t)W) + x0];
-  const float top = __builtin_fmaf(fx, h_hi(q.x), h_lo(q.x));
-  const float bot = __builtin_fmaf(fx, h_hi(q.y), h_lo(q.y));
+  const uint32_t q = quad[__umul24(y0, (uint32_t)W) + x0];
+  const float t00 = (float)(q & 0xFFu), t01 = (float)((q >> 8) & 0xFFu);
+  const float t10 = (float)((q >> 16) & 0xFFu), t11 = (float)(q >> 24);
+  const float top = __builtin_fmaf(fx, t01 - t00, t00);
+  const float bot = __builtin_fmaf(fx, t11 - t10, t10);
   return __builtin_fmaf(fy, bot - top, top);
 }
 
@@ -571,19 +572,17 @@ __global__ __launch_bounds__(256) void select_kernel(Args A, Step S) {
 }
 
 // ---------------------------------------------------------------------------- image preparation
-// 8-bit image -> fp16 copy and fp16 texel quads (exact: integers and their differences)
+// 8-bit image -> fp16 copy (reference tiles) and 8-bit texel quads (bilinear gathers)
 __global__ void build_view_kernel(const uint8_t* __restrict__ img, int64_t stride, int W, int H,
-                                  __half* __restrict__ plain, uint2* __restrict__ quad) {
+                                  __half* __restrict__ plain, uint32_t* __restrict__ quad) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= W || y >= H) return;
   const int x1 = min(x + 1, W - 1), y1 = min(y + 1, H - 1);
-  const float i00 = (float)img[(size_t)y * stride + x], i01 = (float)img[(size_t)y * stride + x1];
-  const float i10 = (float)img[(size_t)y1 * stride + x], i11 = (float)img[(size_t)y1 * stride + x1];
-  plain[(size_t)y * W + x] = __float2half(i00);
-  const uint32_t a = (uint32_t)__half_as_ushort(__float2half(i00)) | ((uint32_t)__half_as_ushort(__float2half(i01 - i00)) << 16);
-  const uint32_t b = (uint32_t)__half_as_ushort(__float2half(i10)) | ((uint32_t)__half_as_ushort(__float2half(i11 - i10)) << 16);
-  quad[(size_t)y * W + x] = make_uint2(a, b);
+  const uint32_t i00 = img[(size_t)y * stride + x], i01 = img[(size_t)y * stride + x1];
+  const uint32_t i10 = img[(size_t)y1 * stride + x], i11 = img[(size_t)y1 * stride + x1];
+  plain[(size_t)y * W + x] = __float2half((float)i00);
+  quad[(size_t)y * W + x] = i00 | (i01 << 8) | (i10 << 16) | (i11 << 24);
 }
 
 // colour planes -> row-major planes (n, d) + cost, or depth / normal / cost
@@ -643,7 +642,7 @@ namespace phimvs_internal {
 
 template <int NV>
 static hipError_t launch_nv(int mode, const Args& A, const Step& S, dim3 grid, size_t lds, hipStream_t st) {
-  constexpr int G = NV <= 6 ? NV : (NV + 1) / 2;
+  constexpr int G = NV < 2 ? NV : 2;  // two views per pass over the taps (occupancy)
   if (mode == 0) hipLaunchKernelGGL((pmk::select_kernel<NV, G, 0>), grid, dim3(256), lds, st, A, S);
   else if (mode == 1) hipLaunchKernelGGL((pmk::select_kernel<NV, G, 1>), grid, dim3(256), lds, st, A, S);
   else hipLaunchKernelGGL((pmk::select_kernel<NV, G, 2>), grid, dim3(256), lds, st, A, S);
@@ -678,7 +677,7 @@ hipError_t launch_candidates(int kind, const Args& A, const Step& S, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_build_view(const uint8_t* img, int64_t stride, int W, int H, __half* plain, uint2* quad,
+hipError_t launch_build_view(const uint8_t* img, int64_t stride, int W, int H, __half* plain, uint32_t* quad,
                              hipStream_t st) {
   hipLaunchKernelGGL(pmk::build_view_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, img, stride, W, H, plain, quad);
   return hipGetLastError();
