@@ -135,6 +135,50 @@ int phimvs_output(phimvs_ctx* ctx, float* depth, float* normal, float* cost, int
 int phimvs_eval_cost(phimvs_ctx* ctx, const float* planes, float* cost, float* per_view, uint8_t* valid,
                      int on_device);
 
+/* ---- batches of reference views ---- */
+
+/* One depth map of a batch: reference view, its sources, window / dilation as for
+ * phimvs_patchmatch, and device outputs (depth H*W, normal H*W*3, cost H*W; any may be
+ * NULL).  srcs is read during the call only. */
+typedef struct {
+  int32_t ref;
+  const int32_t* srcs;
+  int32_t n_srcs;
+  int32_t window, dilation;
+  phimvs_params params;
+  float* depth;
+  float* normal;
+  float* cost;
+} phimvs_job;
+
+/* Depth-map estimation of every job of the batch in shared launches: each phase
+ * (initialisation, a colour's propagation, a colour's refinement) is one launch over
+ * the tiles of all jobs, so references of different sizes and source counts share the
+ * GPU.  With use_graph != 0 the whole launch sequence is captured once into a hipGraph
+ * (per batch geometry, iteration count and tuning) and replayed on later calls.  Work
+ * is issued on the context's stream; outputs are complete when that stream is.  Each
+ * job's result equals its own phimvs_patchmatch result. */
+int phimvs_patchmatch_batch(phimvs_ctx* ctx, int n_jobs, const phimvs_job* jobs, int iters, int use_graph);
+
+/* Launch configuration of the evaluate-and-select kernel: tile_rows (4, 2 or 1) rows of
+ * 256 / tile_rows same-colour pixels per workgroup; persistent != 0 runs a fixed grid
+ * of wgs_per_cu workgroups per compute unit pulling tiles from per-XCD queues, else
+ * one workgroup per tile.  ms is the time measured by phimvs_autotune. */
+typedef struct {
+  int32_t tile_rows;
+  int32_t persistent;
+  int32_t wgs_per_cu;
+  double ms;
+} phimvs_tuning;
+
+int phimvs_set_tuning(phimvs_ctx* ctx, const phimvs_tuning* t);
+int phimvs_get_tuning(phimvs_ctx* ctx, phimvs_tuning* t);
+/* Time every built-in configuration on the given batch (graph replays, `iters`
+ * iterations), keep the fastest in the context and report all of them in results
+ * (capacity *n_results, updated to the number written). */
+int phimvs_autotune(phimvs_ctx* ctx, int n_jobs, const phimvs_job* jobs, int iters, phimvs_tuning* results,
+                    int* n_results);
+
 /* ---- diagnostics ---- */
 
 /* flags: PHIMVS_DIAG_COUNT counts the (pixel, hypothesis) pairs the evaluate-and-select

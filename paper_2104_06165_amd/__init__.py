@@ -28,6 +28,7 @@ MAX_SOURCES = 12
 EXPORTS = ("phimvs_default_params", "phimvs_create", "phimvs_destroy", "phimvs_last_error", "phimvs_set_stream",
            "phimvs_sync", "phimvs_set_views", "phimvs_patchmatch", "phimvs_prepare", "phimvs_init_planes",
            "phimvs_step", "phimvs_get_state", "phimvs_set_state", "phimvs_output", "phimvs_eval_cost",
+           "phimvs_patchmatch_batch", "phimvs_set_tuning", "phimvs_get_tuning", "phimvs_autotune",
            "phimvs_diag_enable", "phimvs_diag_read", "phimvs_check_reciprocal")
 DIAG_COUNT = 1
 DIAG_TIME = 2
@@ -48,6 +49,24 @@ class _Params(C.Structure):
     _fields_ = [("top_k", C.c_int32), ("bilateral", C.c_int32), ("sigma_spatial_px", C.c_double),
                 ("sigma_color", C.c_double), ("eps_var", C.c_double), ("eps_cost", C.c_double),
                 ("seed", C.c_uint64)]
+
+
+class _Job(C.Structure):
+    _fields_ = [("ref", C.c_int32), ("srcs", C.POINTER(C.c_int32)), ("n_srcs", C.c_int32), ("window", C.c_int32),
+                ("dilation", C.c_int32), ("params", _Params), ("depth", C.c_void_p), ("normal", C.c_void_p),
+                ("cost", C.c_void_p)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("tile_rows", C.c_int32), ("persistent", C.c_int32), ("wgs_per_cu", C.c_int32), ("ms", C.c_double)]
+
+
+@dataclass
+class Tuning:
+    tile_rows: int = 4
+    persistent: bool = False
+    wgs_per_cu: int = 0
+    ms: float = 0.0
 
 
 @dataclass
@@ -96,6 +115,10 @@ def lib():
         L.phimvs_set_state.argtypes = [vp, fp, fp, ip]
         L.phimvs_output.argtypes = [vp, fp, fp, fp, ip]
         L.phimvs_eval_cost.argtypes = [vp, fp, fp, fp, vp, ip]
+        L.phimvs_patchmatch_batch.argtypes = [vp, ip, C.POINTER(_Job), ip, ip]
+        L.phimvs_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+        L.phimvs_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+        L.phimvs_autotune.argtypes = [vp, ip, C.POINTER(_Job), ip, C.POINTER(_Tuning), C.POINTER(C.c_int)]
         L.phimvs_diag_enable.argtypes = [vp, ip]
         L.phimvs_diag_read.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
         L.phimvs_check_reciprocal.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64),
@@ -262,6 +285,61 @@ class Context:
 
     def sync(self):
         self._check(lib().phimvs_sync(self.h))
+
+    # ------------------------------------------------------------------ batches
+    def _jobs(self, jobs):
+        """jobs: dicts with ref, srcs, window, dilation, params (optional), and device tensors
+        depth / normal / cost (optional; allocated when missing)."""
+        torch = self.torch
+        arr = (_Job * len(jobs))()
+        keep = []
+        outs = []
+        for i, j in enumerate(jobs):
+            H, W = self.views[j["ref"]] if 0 <= j["ref"] < len(self.views) else (1, 1)
+            d = j.get("depth")
+            n = j.get("normal")
+            c = j.get("cost")
+            if d is None:
+                d = torch.empty((H, W), dtype=torch.float32, device=self.device)
+            if n is None:
+                n = torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+            if c is None:
+                c = torch.empty((H, W), dtype=torch.float32, device=self.device)
+            sa = (C.c_int32 * len(j["srcs"]))(*j["srcs"])
+            keep.append(sa)
+            p = (j.get("params") or default_params())._c()
+            arr[i] = _Job(j["ref"], sa, len(j["srcs"]), j["window"], j["dilation"], p, d.data_ptr(), n.data_ptr(),
+                          c.data_ptr())
+            outs.append((d, n, c))
+        return arr, keep, outs
+
+    def patchmatch_batch(self, jobs, iters: int, use_graph: bool = True):
+        """-> list of (depth, normal, cost) device tensors, one per job."""
+        self._sync_stream()
+        arr, keep, outs = self._jobs(jobs)
+        self._check(lib().phimvs_patchmatch_batch(self.h, len(jobs), arr, iters, int(use_graph)))
+        return outs
+
+    def set_tuning(self, t: Tuning):
+        self._check(lib().phimvs_set_tuning(self.h, C.byref(_Tuning(t.tile_rows, int(t.persistent), t.wgs_per_cu,
+                                                                     t.ms))))
+
+    def get_tuning(self) -> Tuning:
+        t = _Tuning()
+        self._check(lib().phimvs_get_tuning(self.h, C.byref(t)))
+        return Tuning(t.tile_rows, bool(t.persistent), t.wgs_per_cu, t.ms)
+
+    def autotune(self, jobs, iters: int = 1):
+        """Time the built-in launch configurations on this batch; keep the fastest.
+        -> (best Tuning, list of every Tuning with its time)."""
+        self._sync_stream()
+        arr, keep, outs = self._jobs(jobs)
+        cap = 32
+        res = (_Tuning * cap)()
+        n = C.c_int(cap)
+        self._check(lib().phimvs_autotune(self.h, len(jobs), arr, iters, res, C.byref(n)))
+        allr = [Tuning(r.tile_rows, bool(r.persistent), r.wgs_per_cu, r.ms) for r in res[:n.value]]
+        return self.get_tuning(), allr
 
     def diag_enable(self, flags: int):
         self._sync_stream()

@@ -2,9 +2,10 @@
 //
 // Responsibilities: argument validation, the FP64 per-problem constants (relative
 // poses, M_j = K_j R_rel K_0^-1, e_j = K_j t_rel, K_0^-1, bilateral weight tables),
-// device memory for views and state, and the launch sequence of the depth-map
-// estimation step (Algorithm 1: initialisation, then per iteration a red and a
-// black half-sweep).
+// device memory for views and solver state, the job table every kernel reads, and the
+// launch sequence of the depth-map estimation step (Algorithm 1: initialisation, then
+// per iteration a red and a black half-sweep, each propagation then refinement), issued
+// eagerly or replayed from a captured hipGraph.
 
 #include <hip/hip_runtime.h>
 
@@ -36,22 +37,42 @@ struct DevBuf {
   size_t n = 0;
 };
 
+// device state of one job
+struct JobState {
+  DevBuf<float4> plane[2];
+  DevBuf<float> cost[2];
+  DevBuf<float4> cand;
+  DevBuf<float> wcol, wsp;
+};
+
+// a set of jobs with their table on the device and their launch geometry
+struct Batch {
+  std::vector<Job> jobs;         // host copy of the table
+  std::vector<JobState> state;
+  Job* d_jobs = nullptr;
+  size_t d_cap = 0;
+  int total_tiles = 0, total_cblk = 0, max_r = 0, max_taps = 0, tile_rows = 4;
+  std::string layout_key;        // problems + tile shape the state was built for
+  // captured launch sequence
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string graph_key;
+  DevBuf<unsigned int> queues;   // 8 counters per evaluate launch
+};
+
 }  // namespace
 
 struct phimvs_ctx {
   int device = 0;
+  int n_cu = 256;
   hipStream_t stream = nullptr;
+  hipStream_t capture_stream = nullptr;  // private stream graphs are recorded on
   std::string err;
   std::vector<ViewData> views;
   bool prepared = false;
-  Args args{};
-  int ref = -1;
-  std::vector<int> srcs;
-  DevBuf<float4> plane[2];
-  DevBuf<float> cost[2];
-  DevBuf<float4> cand;  // up to 8 candidate planes per pixel of one colour
-  DevBuf<float> wcol, wsp;
-  std::vector<float> wcol_h, wsp_h;
+  Batch single;                   // the step-wise interface's job
+  Batch multi;                    // phimvs_patchmatch_batch
+  phimvs_tuning tuning{4, 0, 0, 0.0};
   DevBuf<float> io_a, io_b, io_c;  // staging for host inputs / outputs
   DevBuf<uint8_t> io_u8;
   // diagnostics
@@ -95,6 +116,34 @@ void release(DevBuf<T>& b) {
   b.n = 0;
 }
 
+void release_graph(Batch& b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
+  b.graph_key.clear();
+}
+
+void release_batch(Batch& b) {
+  release_graph(b);
+  for (auto& s : b.state) {
+    for (int k = 0; k < 2; ++k) {
+      release(s.plane[k]);
+      release(s.cost[k]);
+    }
+    release(s.cand);
+    release(s.wcol);
+    release(s.wsp);
+  }
+  b.state.clear();
+  b.jobs.clear();
+  b.layout_key.clear();
+  if (b.d_jobs) (void)hipFree(b.d_jobs);
+  b.d_jobs = nullptr;
+  b.d_cap = 0;
+  release(b.queues);
+}
+
 bool finite_all(const double* v, int n) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
@@ -104,7 +153,8 @@ bool finite_all(const double* v, int n) {
 // C = A B (3x3, row-major), summed left to right
 void mul33(const double* A, const double* B, double* C) {
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) C[i * 3 + j] = A[i * 3 + 0] * B[0 * 3 + j] + A[i * 3 + 1] * B[1 * 3 + j] + A[i * 3 + 2] * B[2 * 3 + j];
+    for (int j = 0; j < 3; ++j)
+      C[i * 3 + j] = A[i * 3 + 0] * B[0 * 3 + j] + A[i * 3 + 1] * B[1 * 3 + j] + A[i * 3 + 2] * B[2 * 3 + j];
 }
 
 void mulv3(const double* A, const double* v, double* o) {
@@ -142,13 +192,279 @@ bool orthonormal(const double* R) {
   return e < 1e-4;
 }
 
-int validate_params(phimvs_ctx* c, const phimvs_params& p, int n_srcs) {
-  if (p.top_k < 0 || p.top_k > n_srcs) return fail(c, PHIMVS_E_ARG, "top_k must be in [0, n_srcs]");
+struct Problem {
+  int ref;
+  std::vector<int> srcs;
+  int window, dilation;
+  phimvs_params p;
+};
+
+std::string problem_key(const Problem& P) {
+  std::string k = std::to_string(P.ref) + "," + std::to_string(P.window) + "," + std::to_string(P.dilation) + "," +
+                  std::to_string(P.p.top_k) + "," + std::to_string(P.p.bilateral) + "," + std::to_string(P.p.seed) +
+                  "," + std::to_string(P.p.sigma_color) + "," + std::to_string(P.p.sigma_spatial_px) + "," +
+                  std::to_string(P.p.eps_var) + "," + std::to_string(P.p.eps_cost);
+  for (int s : P.srcs) k += ";" + std::to_string(s);
+  return k;
+}
+
+int validate_problem(phimvs_ctx* c, const Problem& P) {
+  const int nv = (int)c->views.size();
+  if (nv == 0) return fail(c, PHIMVS_E_STATE, "no views: call phimvs_set_views first");
+  if (P.ref < 0 || P.ref >= nv) return fail(c, PHIMVS_E_ARG, "ref out of range");
+  if (P.srcs.empty()) return fail(c, PHIMVS_E_ARG, "need at least one source view");
+  if ((int)P.srcs.size() > PHIMVS_MAX_SOURCES)
+    return fail(c, PHIMVS_E_UNSUPPORTED, "at most 12 source views per reference");
+  for (size_t i = 0; i < P.srcs.size(); ++i) {
+    if (P.srcs[i] < 0 || P.srcs[i] >= nv) return fail(c, PHIMVS_E_ARG, "source index out of range");
+    if (P.srcs[i] == P.ref) return fail(c, PHIMVS_E_ARG, "the reference cannot be one of its sources");
+    for (size_t k = 0; k < i; ++k)
+      if (P.srcs[k] == P.srcs[i]) return fail(c, PHIMVS_E_ARG, "duplicate source view");
+  }
+  if (P.dilation < 1) return fail(c, PHIMVS_E_ARG, "dilation must be >= 1");
+  if (P.window < 3 || P.window % 2 == 0 || (P.window - 1) % (2 * P.dilation) != 0)
+    return fail(c, PHIMVS_E_ARG, "window must be odd with (window - 1) % (2 dilation) == 0");
+  const int R = (P.window - 1) / (2 * P.dilation);
+  if (R > 15) return fail(c, PHIMVS_E_UNSUPPORTED, "at most 31 taps per window side");
+  if (P.dilation * R > 30) return fail(c, PHIMVS_E_UNSUPPORTED, "window radius above 30 px");
+  const phimvs_params& p = P.p;
+  const int n = (int)P.srcs.size();
+  if (p.top_k < 0 || p.top_k > n) return fail(c, PHIMVS_E_ARG, "top_k must be in [0, n_srcs]");
   if (!std::isfinite(p.sigma_spatial_px) || !(std::isfinite(p.sigma_color) && p.sigma_color > 0))
     return fail(c, PHIMVS_E_ARG, "bilateral sigmas must be finite, sigma_color > 0");
   if (!(p.eps_var >= 0 && std::isfinite(p.eps_var)) || !(p.eps_cost > 0 && std::isfinite(p.eps_cost)))
     return fail(c, PHIMVS_E_ARG, "eps_var must be >= 0 and eps_cost > 0");
   return PHIMVS_OK;
+}
+
+// fill the problem block of one job and allocate its state
+int setup_job(phimvs_ctx* c, const Problem& P, Job& J, JobState& S) {
+  const ViewData& V0 = c->views[P.ref];
+  const phimvs_params& p = P.p;
+  Args& A = J.A;
+  A = Args{};
+  const int R = (P.window - 1) / (2 * P.dilation);
+  A.W = V0.W;
+  A.H = V0.H;
+  A.Wc = (V0.W + 1) / 2;
+  A.R = R;
+  A.s = P.dilation;
+  A.n_src = (int)P.srcs.size();
+  A.top_k = p.top_k;
+  A.bilateral = p.bilateral ? 1 : 0;
+  A.n_taps = (2 * R + 1) * (2 * R + 1);
+  double K0i[9];
+  inv33(V0.K, K0i);
+  for (int i = 0; i < 9; ++i) {
+    A.Kinv[i] = (float)K0i[i];
+    A.Kinv_d[i] = K0i[i];
+  }
+  A.d_lo = (float)V0.d_lo;
+  A.d_hi = (float)V0.d_hi;
+  A.eps_v = (float)p.eps_var;
+  A.eps_c = (float)p.eps_cost;
+  A.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
+  A.seed_hi = (uint32_t)(p.seed >> 32);
+  A.ref = V0.plain;
+  // relative poses and the plane-independent parts of the homographies (FP64)
+  double R0t[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) R0t[i * 3 + j] = V0.R[j * 3 + i];
+  for (int k = 0; k < A.n_src; ++k) {
+    const ViewData& Vj = c->views[P.srcs[k]];
+    double Rrel[9], Rt0[3], trel[3], KR[9], M[9], e[3];
+    mul33(Vj.R, R0t, Rrel);
+    mulv3(Rrel, V0.t, Rt0);
+    for (int i = 0; i < 3; ++i) trel[i] = Vj.t[i] - Rt0[i];
+    mul33(Vj.K, Rrel, KR);
+    mul33(KR, K0i, M);
+    mulv3(Vj.K, trel, e);
+    SrcDev& D = A.src[k];
+    for (int i = 0; i < 9; ++i) D.M[i] = (float)M[i];
+    for (int i = 0; i < 3; ++i) D.e[i] = (float)e[i];
+    D.W = Vj.W;
+    D.H = Vj.H;
+    D.Wm1 = (float)(Vj.W - 1);
+    D.Hm1 = (float)(Vj.H - 1);
+    D.quad = Vj.quad;
+  }
+  // bilateral weight factors: colour (|a - a_c| = 0..255) and space (tap offsets)
+  const double sc = p.sigma_color;
+  const double ss = p.sigma_spatial_px > 0 ? p.sigma_spatial_px : (double)((P.window - 1) / 2);
+  std::vector<float> wc(256), ws(A.n_taps);
+  for (int i = 0; i < 256; ++i) {
+    const double d = (double)i;
+    wc[i] = p.bilateral ? (float)std::exp(-(d * d) / (2.0 * sc * sc)) : 1.0f;
+  }
+  for (int k2 = -R, t = 0; k2 <= R; ++k2)
+    for (int k1 = -R; k1 <= R; ++k1, ++t) {
+      const double r2 = (double)(P.dilation * P.dilation) * (double)(k1 * k1 + k2 * k2);
+      ws[t] = p.bilateral ? (float)std::exp(-r2 / (2.0 * ss * ss)) : 1.0f;
+    }
+  int rc;
+  if ((rc = ensure(c, S.wcol, 256)) || (rc = ensure(c, S.wsp, ws.size()))) return rc;
+  HIPCHECK(c, hipMemcpyAsync(S.wcol.p, wc.data(), 256 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(S.wsp.p, ws.data(), ws.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));  // the host vectors go out of scope
+  A.wcol = S.wcol.p;
+  A.wsp = S.wsp.p;
+  const size_t ncol = (size_t)A.Wc * A.H;
+  for (int k = 0; k < 2; ++k) {
+    if ((rc = ensure(c, S.plane[k], ncol)) || (rc = ensure(c, S.cost[k], ncol))) return rc;
+    A.plane[k] = S.plane[k].p;
+    A.cost[k] = S.cost[k].p;
+  }
+  if ((rc = ensure(c, S.cand, 8 * ncol))) return rc;
+  J.cand = S.cand.p;
+  J.planes_in = nullptr;
+  J.cost_out = J.per_view_out = nullptr;
+  J.valid_out = nullptr;
+  J.depth_out = J.normal_out = J.final_cost_out = J.planes_out = nullptr;
+  return PHIMVS_OK;
+}
+
+// tile / block offsets of every job for the current tile shape, and the launch-wide maxima
+void layout(Batch& b, int tile_rows) {
+  b.tile_rows = tile_rows;
+  const int TC = kBlock / tile_rows;
+  int t = 0, k = 0;
+  b.max_r = 0;
+  b.max_taps = 0;
+  for (Job& J : b.jobs) {
+    J.tile0 = t;
+    J.tiles_x = (J.A.Wc + TC - 1) / TC;
+    J.tiles_y = (J.A.H + tile_rows - 1) / tile_rows;
+    t += J.tiles_x * J.tiles_y;
+    J.cblk0 = k;
+    J.cblk_x = (J.A.Wc + 127) / 128;
+    k += J.cblk_x * J.A.H;
+    b.max_r = std::max(b.max_r, J.A.s * J.A.R);
+    b.max_taps = std::max(b.max_taps, J.A.n_taps);
+  }
+  b.total_tiles = t;
+  b.total_cblk = k;
+}
+
+int upload_jobs(phimvs_ctx* c, Batch& b) {
+  const size_t bytes = b.jobs.size() * sizeof(Job);
+  if (b.d_cap < bytes) {
+    if (b.d_jobs) HIPCHECK(c, hipFree(b.d_jobs));
+    b.d_jobs = nullptr;
+    HIPCHECK(c, hipMalloc((void**)&b.d_jobs, bytes));
+    b.d_cap = bytes;
+  }
+  // the table is read by work already queued: wait for it before overwriting
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  HIPCHECK(c, hipMemcpy(b.d_jobs, b.jobs.data(), bytes, hipMemcpyHostToDevice));
+  return PHIMVS_OK;
+}
+
+Launch base_launch(const Batch& b) {
+  Launch L{};
+  L.n_jobs = (int)b.jobs.size();
+  L.tile_rows = b.tile_rows;
+  L.total_tiles = b.total_tiles;
+  L.total_cblk = b.total_cblk;
+  return L;
+}
+
+int eval_grid(const phimvs_ctx* c, const Batch& b, bool persistent) {
+  if (!persistent) return ((b.total_tiles + 7) / 8) * 8;
+  const int wgs = std::max(1, c->tuning.wgs_per_cu) * c->n_cu;
+  return ((std::min(wgs, b.total_tiles) + 7) / 8) * 8;
+}
+
+// one evaluate-and-select launch (queue: 8 zeroed counters when persistent), with the
+// optional diagnostics around it
+hipError_t run_eval(phimvs_ctx* c, Batch& b, Launch L, unsigned int* queue) {
+  const bool persistent = c->tuning.persistent != 0;
+  L.persistent = persistent ? 1 : 0;
+  L.queue = queue;
+  if (c->diag & PHIMVS_DIAG_COUNT) L.count = c->diag_count;
+  const size_t lds = eval_lds_bytes(b.tile_rows, b.max_r, b.max_taps);
+  const int grid = eval_grid(c, b, persistent);
+  hipError_t e;
+  if (c->diag & PHIMVS_DIAG_TIME) {
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+    c->diag_events.emplace_back(e0, e1);
+    if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) return e;
+    if ((e = launch_eval(b.d_jobs, L, grid, lds, c->stream)) != hipSuccess) return e;
+    return hipEventRecord(e1, c->stream);
+  }
+  return launch_eval(b.d_jobs, L, grid, lds, c->stream);
+}
+
+// the launch sequence of init + iters x (red, black) x (propagate, refine) (+ unpack);
+// each evaluate launch gets its own 8 queue counters from b.queues, zeroed first by a
+// kernel (no memset node, so the sequence replays correctly from a graph)
+int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack) {
+  const int n_eval = 2 + 4 * iters;
+  if (b.queues.n < (size_t)8 * n_eval) return fail(c, PHIMVS_E_STATE, "queue counters not allocated");
+  HIPCHECK(c, launch_zero(b.queues.p, 8 * n_eval, c->stream));
+  int q = 0;
+  Launch L = base_launch(b);
+  for (int colour = 0; colour < 2; ++colour) {
+    L.colour = colour;
+    L.mode = 0;
+    L.ncand = 1;
+    HIPCHECK(c, launch_candidates(0, b.d_jobs, L, c->stream));
+    HIPCHECK(c, run_eval(c, b, L, b.queues.p + 8 * q++));
+  }
+  for (int it = 1; it <= iters; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      L.colour = colour;
+      L.iteration = it;
+      L.mode = 1;
+      L.ncand = 8;
+      HIPCHECK(c, launch_candidates(1, b.d_jobs, L, c->stream));
+      HIPCHECK(c, run_eval(c, b, L, b.queues.p + 8 * q++));
+      L.ncand = 3;
+      HIPCHECK(c, launch_candidates(2, b.d_jobs, L, c->stream));
+      HIPCHECK(c, run_eval(c, b, L, b.queues.p + 8 * q++));
+    }
+  if (do_unpack) HIPCHECK(c, launch_unpack(b.d_jobs, base_launch(b), c->stream));
+  return PHIMVS_OK;
+}
+
+int need_prepared(phimvs_ctx* c) {
+  if (!c) return PHIMVS_E_ARG;
+  if (!c->prepared) return fail(c, PHIMVS_E_STATE, "call phimvs_prepare first");
+  return PHIMVS_OK;
+}
+
+// device pointer for an input array: either the caller's, or a staging copy of host data
+int input_ptr(phimvs_ctx* c, DevBuf<float>& stage, const float* p, size_t n, int on_device, const float** out) {
+  if (on_device) {
+    *out = p;
+    return PHIMVS_OK;
+  }
+  int rc = ensure(c, stage, n);
+  if (rc) return rc;
+  HIPCHECK(c, hipMemcpyAsync(stage.p, p, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  *out = stage.p;
+  return PHIMVS_OK;
+}
+
+// evaluate launch outside a sequence (its own queue)
+int eval_once(phimvs_ctx* c, Batch& b, Launch L) {
+  int rc = ensure(c, b.queues, 8);
+  if (rc) return rc;
+  HIPCHECK(c, launch_zero(b.queues.p, 8, c->stream));
+  HIPCHECK(c, run_eval(c, b, L, b.queues.p));
+  return PHIMVS_OK;
+}
+
+Problem make_problem(int ref, const int* srcs, int n_srcs, int window, int dilation, const phimvs_params* pp) {
+  Problem P;
+  P.ref = ref;
+  if (srcs && n_srcs > 0) P.srcs.assign(srcs, srcs + n_srcs);
+  P.window = window;
+  P.dilation = dilation;
+  if (pp) P.p = *pp;
+  else phimvs_default_params(&P.p);
+  return P;
 }
 
 }  // namespace
@@ -176,6 +492,9 @@ int phimvs_create(phimvs_ctx** out, int device_ordinal, void* hip_stream) {
   if (!c) return PHIMVS_E_OOM;
   c->device = device_ordinal;
   c->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device_ordinal) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
   *out = c;
   return PHIMVS_OK;
 }
@@ -193,13 +512,9 @@ void phimvs_destroy(phimvs_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   free_views(c);
-  for (int k = 0; k < 2; ++k) {
-    release(c->plane[k]);
-    release(c->cost[k]);
-  }
-  release(c->cand);
-  release(c->wcol);
-  release(c->wsp);
+  release_batch(c->single);
+  release_batch(c->multi);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   release(c->io_a);
   release(c->io_b);
   release(c->io_c);
@@ -216,7 +531,7 @@ const char* phimvs_last_error(const phimvs_ctx* c) { return c ? c->err.c_str() :
 
 int phimvs_set_stream(phimvs_ctx* c, void* hip_stream) {
   if (!c) return PHIMVS_E_ARG;
-  c->stream = (hipStream_t)hip_stream;
+  c->stream = (hipStream_t)hip_stream;  // a captured graph replays on whatever stream launches it
   return PHIMVS_OK;
 }
 
@@ -252,6 +567,8 @@ int phimvs_set_views(phimvs_ctx* c, int n_views, const phimvs_image* images, con
   HIPCHECK(c, hipSetDevice(c->device));
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   free_views(c);
+  release_batch(c->single);
+  release_batch(c->multi);
   c->prepared = false;
   c->views.resize(n_views);
   for (int i = 0; i < n_views; ++i) {
@@ -282,150 +599,28 @@ int phimvs_prepare(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int wind
                    const phimvs_params* pp) {
   if (!c) return PHIMVS_E_ARG;
   c->prepared = false;
-  const int nv = (int)c->views.size();
-  if (nv == 0) return fail(c, PHIMVS_E_STATE, "no views: call phimvs_set_views first");
-  if (ref < 0 || ref >= nv) return fail(c, PHIMVS_E_ARG, "ref out of range");
-  if (n_srcs < 1 || !srcs) return fail(c, PHIMVS_E_ARG, "need at least one source view");
-  if (n_srcs > 12) return fail(c, PHIMVS_E_UNSUPPORTED, "at most 12 source views per reference");
-  for (int i = 0; i < n_srcs; ++i) {
-    if (srcs[i] < 0 || srcs[i] >= nv) return fail(c, PHIMVS_E_ARG, "source index out of range");
-    if (srcs[i] == ref) return fail(c, PHIMVS_E_ARG, "the reference cannot be one of its sources");
-    for (int k = 0; k < i; ++k)
-      if (srcs[k] == srcs[i]) return fail(c, PHIMVS_E_ARG, "duplicate source view");
-  }
-  if (dilation < 1) return fail(c, PHIMVS_E_ARG, "dilation must be >= 1");
-  if (window < 3 || window % 2 == 0 || (window - 1) % (2 * dilation) != 0)
-    return fail(c, PHIMVS_E_ARG, "window must be odd with (window - 1) % (2 dilation) == 0");
-  const int R = (window - 1) / (2 * dilation);
-  if (R > 15) return fail(c, PHIMVS_E_UNSUPPORTED, "at most 31 taps per window side");
-  if (dilation * R > 30) return fail(c, PHIMVS_E_UNSUPPORTED, "window radius above 30 px");
-  phimvs_params p;
-  if (pp) p = *pp;
-  else phimvs_default_params(&p);
-  int rc = validate_params(c, p, n_srcs);
+  if (n_srcs < 0 || (n_srcs > 0 && !srcs)) return fail(c, PHIMVS_E_ARG, "need at least one source view");
+  Problem P = make_problem(ref, srcs, n_srcs, window, dilation, pp);
+  int rc = validate_problem(c, P);
   if (rc) return rc;
-
-  const ViewData& V0 = c->views[ref];
-  Args& A = c->args;
-  A = Args{};
-  A.W = V0.W;
-  A.H = V0.H;
-  A.Wc = (V0.W + 1) / 2;
-  A.R = R;
-  A.s = dilation;
-  A.n_src = n_srcs;
-  A.top_k = p.top_k;
-  A.bilateral = p.bilateral ? 1 : 0;
-  A.TW = 128 + 2 * dilation * R;
-  A.TH = 4 + 2 * dilation * R;
-  A.n_taps = (2 * R + 1) * (2 * R + 1);
-  double K0i[9];
-  inv33(V0.K, K0i);
-  for (int i = 0; i < 9; ++i) {
-    A.Kinv[i] = (float)K0i[i];
-    A.Kinv_d[i] = K0i[i];
-  }
-  A.d_lo = (float)V0.d_lo;
-  A.d_hi = (float)V0.d_hi;
-  A.eps_v = (float)p.eps_var;
-  A.eps_c = (float)p.eps_cost;
-  A.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
-  A.seed_hi = (uint32_t)(p.seed >> 32);
-  A.ref = V0.plain;
-  // relative poses and the plane-independent parts of the homographies (FP64)
-  double R0t[9];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) R0t[i * 3 + j] = V0.R[j * 3 + i];
-  for (int k = 0; k < n_srcs; ++k) {
-    const ViewData& Vj = c->views[srcs[k]];
-    double Rrel[9], Rt0[3], trel[3], KR[9], M[9], e[3];
-    mul33(Vj.R, R0t, Rrel);
-    mulv3(Rrel, V0.t, Rt0);
-    for (int i = 0; i < 3; ++i) trel[i] = Vj.t[i] - Rt0[i];
-    mul33(Vj.K, Rrel, KR);
-    mul33(KR, K0i, M);
-    mulv3(Vj.K, trel, e);
-    SrcDev& S = A.src[k];
-    for (int i = 0; i < 9; ++i) S.M[i] = (float)M[i];
-    for (int i = 0; i < 3; ++i) S.e[i] = (float)e[i];
-    S.W = Vj.W;
-    S.H = Vj.H;
-    S.Wm1 = (float)(Vj.W - 1);
-    S.Hm1 = (float)(Vj.H - 1);
-    S.quad = Vj.quad;
-  }
-  // bilateral weight factors: colour (|a - a_c| = 0..255) and space (tap offsets)
-  const double sc = p.sigma_color;
-  const double ss = p.sigma_spatial_px > 0 ? p.sigma_spatial_px : (double)((window - 1) / 2);
-  std::vector<float> wc(256), ws(A.n_taps);
-  for (int i = 0; i < 256; ++i) {
-    const double d = (double)i;
-    wc[i] = p.bilateral ? (float)std::exp(-(d * d) / (2.0 * sc * sc)) : 1.0f;
-  }
-  for (int k2 = -R, t = 0; k2 <= R; ++k2)
-    for (int k1 = -R; k1 <= R; ++k1, ++t) {
-      const double r2 = (double)(dilation * dilation) * (double)(k1 * k1 + k2 * k2);
-      ws[t] = p.bilateral ? (float)std::exp(-r2 / (2.0 * ss * ss)) : 1.0f;
-    }
   HIPCHECK(c, hipSetDevice(c->device));
-  if (ws != c->wsp_h || wc != c->wcol_h || !c->wcol.p || !c->wsp.p) {
-    if ((rc = ensure(c, c->wcol, 256))) return rc;
-    if ((rc = ensure(c, c->wsp, ws.size()))) return rc;
-    HIPCHECK(c, hipStreamSynchronize(c->stream));
-    HIPCHECK(c, hipMemcpy(c->wcol.p, wc.data(), 256 * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHECK(c, hipMemcpy(c->wsp.p, ws.data(), ws.size() * sizeof(float), hipMemcpyHostToDevice));
-    c->wcol_h = wc;
-    c->wsp_h = ws;
+  Batch& b = c->single;
+  const std::string key = problem_key(P) + "@" + std::to_string(c->tuning.tile_rows);
+  if (key != b.layout_key || b.jobs.size() != 1) {
+    release_graph(b);
+    b.jobs.resize(1);
+    b.state.resize(1);
+    if ((rc = setup_job(c, P, b.jobs[0], b.state[0]))) return rc;
+    layout(b, c->tuning.tile_rows);
+    b.layout_key = key;
   }
-  A.wcol = c->wcol.p;
-  A.wsp = c->wsp.p;
-  const size_t ncol = (size_t)A.Wc * A.H;
-  for (int k = 0; k < 2; ++k) {
-    if ((rc = ensure(c, c->plane[k], ncol))) return rc;
-    if ((rc = ensure(c, c->cost[k], ncol))) return rc;
-    A.plane[k] = c->plane[k].p;
-    A.cost[k] = c->cost[k].p;
-  }
-  if ((rc = ensure(c, c->cand, 8 * ncol))) return rc;
-  c->ref = ref;
-  c->srcs.assign(srcs, srcs + n_srcs);
+  Job& J = b.jobs[0];
+  J.planes_in = nullptr;
+  J.cost_out = J.per_view_out = nullptr;
+  J.valid_out = nullptr;
+  J.depth_out = J.normal_out = J.final_cost_out = J.planes_out = nullptr;
+  if ((rc = upload_jobs(c, b))) return rc;
   c->prepared = true;
-  return PHIMVS_OK;
-}
-
-// evaluate-and-select launch with the optional diagnostics around it
-static hipError_t run_select(phimvs_ctx* c, int mode, Step S) {
-  hipError_t e;
-  if (c->diag & PHIMVS_DIAG_COUNT) S.count = c->diag_count;
-  if (c->diag & PHIMVS_DIAG_TIME) {
-    hipEvent_t a, b;
-    if ((e = hipEventCreate(&a)) != hipSuccess) return e;
-    if ((e = hipEventCreate(&b)) != hipSuccess) return e;
-    c->diag_events.emplace_back(a, b);
-    if ((e = hipEventRecord(a, c->stream)) != hipSuccess) return e;
-    if ((e = launch_select(mode, c->args, S, c->stream)) != hipSuccess) return e;
-    return hipEventRecord(b, c->stream);
-  }
-  return launch_select(mode, c->args, S, c->stream);
-}
-
-static int need_prepared(phimvs_ctx* c) {
-  if (!c) return PHIMVS_E_ARG;
-  if (!c->prepared) return fail(c, PHIMVS_E_STATE, "call phimvs_prepare first");
-  return PHIMVS_OK;
-}
-
-// device pointer for an input array: either the caller's, or a staging copy of host data
-static int input_ptr(phimvs_ctx* c, DevBuf<float>& stage, const float* p, size_t n, int on_device,
-                     const float** out) {
-  if (on_device) {
-    *out = p;
-    return PHIMVS_OK;
-  }
-  int rc = ensure(c, stage, n);
-  if (rc) return rc;
-  HIPCHECK(c, hipMemcpyAsync(stage.p, p, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
-  *out = stage.p;
   return PHIMVS_OK;
 }
 
@@ -433,19 +628,27 @@ int phimvs_init_planes(phimvs_ctx* c, const float* proposal, int on_device) {
   int rc = need_prepared(c);
   if (rc) return rc;
   HIPCHECK(c, hipSetDevice(c->device));
-  Step S{};
-  S.cand = c->cand.p;
-  S.ncand = 1;
+  Batch& b = c->single;
+  const float* prop = nullptr;
   if (proposal) {
-    if ((rc = input_ptr(c, c->io_a, proposal, (size_t)c->args.W * c->args.H * 4, on_device, &S.planes_in))) return rc;
-    S.ncand = 2;
+    if ((rc = input_ptr(c, c->io_a, proposal, (size_t)b.jobs[0].A.W * b.jobs[0].A.H * 4, on_device, &prop))) return rc;
   }
+  if (b.jobs[0].planes_in != prop) {
+    b.jobs[0].planes_in = prop;
+    if ((rc = upload_jobs(c, b))) return rc;
+  }
+  Launch L = base_launch(b);
+  L.mode = 0;
+  L.ncand = prop ? 2 : 1;
   for (int colour = 0; colour < 2; ++colour) {
-    S.colour = colour;
-    HIPCHECK(c, launch_candidates(0, c->args, S, c->stream));
-    HIPCHECK(c, run_select(c, 0, S));
+    L.colour = colour;
+    HIPCHECK(c, launch_candidates(0, b.d_jobs, L, c->stream));
+    if ((rc = eval_once(c, b, L))) return rc;
   }
-  if (proposal && !on_device) HIPCHECK(c, hipStreamSynchronize(c->stream));
+  if (prop) {
+    b.jobs[0].planes_in = nullptr;
+    if ((rc = upload_jobs(c, b))) return rc;  // waits for the launches reading the proposal
+  }
   return PHIMVS_OK;
 }
 
@@ -455,32 +658,35 @@ int phimvs_step(phimvs_ctx* c, int iteration, int colour, int do_propagate, int 
   if (colour != 0 && colour != 1) return fail(c, PHIMVS_E_ARG, "colour must be 0 or 1");
   if (iteration < 1) return fail(c, PHIMVS_E_ARG, "iteration must be >= 1");
   HIPCHECK(c, hipSetDevice(c->device));
-  Step S{};
-  S.colour = colour;
-  S.iteration = iteration;
-  S.cand = c->cand.p;
+  Batch& b = c->single;
+  Launch L = base_launch(b);
+  L.colour = colour;
+  L.iteration = iteration;
+  L.mode = 1;
   if (do_propagate) {
-    S.ncand = 8;
-    HIPCHECK(c, launch_candidates(1, c->args, S, c->stream));
-    HIPCHECK(c, run_select(c, 1, S));
+    L.ncand = 8;
+    HIPCHECK(c, launch_candidates(1, b.d_jobs, L, c->stream));
+    if ((rc = eval_once(c, b, L))) return rc;
   }
   if (do_refine) {
-    S.ncand = 3;
-    HIPCHECK(c, launch_candidates(2, c->args, S, c->stream));
-    HIPCHECK(c, run_select(c, 1, S));
+    L.ncand = 3;
+    HIPCHECK(c, launch_candidates(2, b.d_jobs, L, c->stream));
+    if ((rc = eval_once(c, b, L))) return rc;
   }
   return PHIMVS_OK;
 }
 
-static int finish_outputs(phimvs_ctx* c, int on_device, std::initializer_list<std::pair<float*, DevBuf<float>*>> outs,
-                          std::initializer_list<size_t> sizes) {
-  if (on_device) return PHIMVS_OK;
-  auto sz = sizes.begin();
-  for (auto& o : outs) {
-    if (o.first) HIPCHECK(c, hipMemcpyAsync(o.first, o.second->p, *sz * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    ++sz;
-  }
-  HIPCHECK(c, hipStreamSynchronize(c->stream));
+// unpack the single job's state into the given device outputs
+static int unpack_single(phimvs_ctx* c, float* planes, float* depth, float* normal, float* cost) {
+  Batch& b = c->single;
+  Job& J = b.jobs[0];
+  J.planes_out = planes;
+  J.depth_out = depth;
+  J.normal_out = normal;
+  J.final_cost_out = cost;
+  int rc = upload_jobs(c, b);
+  if (rc) return rc;
+  HIPCHECK(c, launch_unpack(b.d_jobs, base_launch(b), c->stream));
   return PHIMVS_OK;
 }
 
@@ -488,7 +694,7 @@ int phimvs_get_state(phimvs_ctx* c, float* planes, float* cost, int on_device) {
   int rc = need_prepared(c);
   if (rc) return rc;
   HIPCHECK(c, hipSetDevice(c->device));
-  const size_t n = (size_t)c->args.W * c->args.H;
+  const size_t n = (size_t)c->single.jobs[0].A.W * c->single.jobs[0].A.H;
   float* dp = planes;
   float* dc = cost;
   if (!on_device) {
@@ -496,8 +702,13 @@ int phimvs_get_state(phimvs_ctx* c, float* planes, float* cost, int on_device) {
     dp = planes ? c->io_a.p : nullptr;
     dc = cost ? c->io_b.p : nullptr;
   }
-  HIPCHECK(c, launch_unpack(c->args, dp, nullptr, nullptr, dc, c->stream));
-  return finish_outputs(c, on_device, {{planes, &c->io_a}, {cost, &c->io_b}}, {4 * n, n});
+  if ((rc = unpack_single(c, dp, nullptr, nullptr, dc))) return rc;
+  if (!on_device) {
+    if (planes) HIPCHECK(c, hipMemcpyAsync(planes, c->io_a.p, 4 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (cost) HIPCHECK(c, hipMemcpyAsync(cost, c->io_b.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+  }
+  return PHIMVS_OK;
 }
 
 int phimvs_set_state(phimvs_ctx* c, const float* planes, const float* cost, int on_device) {
@@ -505,11 +716,12 @@ int phimvs_set_state(phimvs_ctx* c, const float* planes, const float* cost, int 
   if (rc) return rc;
   if (!planes || !cost) return fail(c, PHIMVS_E_ARG, "set_state needs planes and cost");
   HIPCHECK(c, hipSetDevice(c->device));
-  const size_t n = (size_t)c->args.W * c->args.H;
+  const Job& J = c->single.jobs[0];
+  const size_t n = (size_t)J.A.W * J.A.H;
   const float *dp, *dc;
   if ((rc = input_ptr(c, c->io_a, planes, 4 * n, on_device, &dp))) return rc;
   if ((rc = input_ptr(c, c->io_b, cost, n, on_device, &dc))) return rc;
-  HIPCHECK(c, launch_pack(c->args, dp, dc, c->stream));
+  HIPCHECK(c, launch_pack(c->single.d_jobs, J.A.W, J.A.H, dp, dc, c->stream));
   if (!on_device) HIPCHECK(c, hipStreamSynchronize(c->stream));
   return PHIMVS_OK;
 }
@@ -518,7 +730,7 @@ int phimvs_output(phimvs_ctx* c, float* depth, float* normal, float* cost, int o
   int rc = need_prepared(c);
   if (rc) return rc;
   HIPCHECK(c, hipSetDevice(c->device));
-  const size_t n = (size_t)c->args.W * c->args.H;
+  const size_t n = (size_t)c->single.jobs[0].A.W * c->single.jobs[0].A.H;
   float *dd = depth, *dn = normal, *dc = cost;
   if (!on_device) {
     if ((rc = ensure(c, c->io_a, 3 * n)) || (rc = ensure(c, c->io_b, n)) || (rc = ensure(c, c->io_c, n))) return rc;
@@ -526,8 +738,14 @@ int phimvs_output(phimvs_ctx* c, float* depth, float* normal, float* cost, int o
     dd = depth ? c->io_b.p : nullptr;
     dc = cost ? c->io_c.p : nullptr;
   }
-  HIPCHECK(c, launch_unpack(c->args, nullptr, dd, dn, dc, c->stream));
-  return finish_outputs(c, on_device, {{normal, &c->io_a}, {depth, &c->io_b}, {cost, &c->io_c}}, {3 * n, n, n});
+  if ((rc = unpack_single(c, nullptr, dd, dn, dc))) return rc;
+  if (!on_device) {
+    if (normal) HIPCHECK(c, hipMemcpyAsync(normal, c->io_a.p, 3 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (depth) HIPCHECK(c, hipMemcpyAsync(depth, c->io_b.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (cost) HIPCHECK(c, hipMemcpyAsync(cost, c->io_c.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+  }
+  return PHIMVS_OK;
 }
 
 int phimvs_eval_cost(phimvs_ctx* c, const float* planes, float* cost, float* per_view, uint8_t* valid, int on_device) {
@@ -535,32 +753,41 @@ int phimvs_eval_cost(phimvs_ctx* c, const float* planes, float* cost, float* per
   if (rc) return rc;
   if (!planes || !cost) return fail(c, PHIMVS_E_ARG, "eval_cost needs planes and cost");
   HIPCHECK(c, hipSetDevice(c->device));
-  const size_t n = (size_t)c->args.W * c->args.H;
-  const size_t nv = (size_t)c->args.n_src;
-  Step S{};
-  if ((rc = input_ptr(c, c->io_a, planes, 4 * n, on_device, &S.planes_in))) return rc;
-  S.cost_out = cost;
-  S.per_view_out = per_view;
-  S.valid_out = valid;
+  Batch& b = c->single;
+  Job& J = b.jobs[0];
+  const size_t n = (size_t)J.A.W * J.A.H;
+  const size_t nv = (size_t)J.A.n_src;
+  const float* pin;
+  if ((rc = input_ptr(c, c->io_a, planes, 4 * n, on_device, &pin))) return rc;
+  J.planes_in = pin;
+  J.cost_out = cost;
+  J.per_view_out = per_view;
+  J.valid_out = valid;
   if (!on_device) {
     if ((rc = ensure(c, c->io_b, n)) || (rc = ensure(c, c->io_c, per_view ? n * nv : 1)) ||
         (rc = ensure(c, c->io_u8, valid ? n * nv : 1)))
       return rc;
-    S.cost_out = c->io_b.p;
-    S.per_view_out = per_view ? c->io_c.p : nullptr;
-    S.valid_out = valid ? c->io_u8.p : nullptr;
+    J.cost_out = c->io_b.p;
+    J.per_view_out = per_view ? c->io_c.p : nullptr;
+    J.valid_out = valid ? c->io_u8.p : nullptr;
   }
+  if ((rc = upload_jobs(c, b))) return rc;
+  Launch L = base_launch(b);
+  L.mode = 2;
   for (int colour = 0; colour < 2; ++colour) {
-    S.colour = colour;
-    HIPCHECK(c, run_select(c, 2, S));
+    L.colour = colour;
+    if ((rc = eval_once(c, b, L))) return rc;
   }
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
   if (!on_device) {
-    HIPCHECK(c, hipMemcpyAsync(cost, c->io_b.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    if (per_view) HIPCHECK(c, hipMemcpyAsync(per_view, c->io_c.p, n * nv * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    if (valid) HIPCHECK(c, hipMemcpyAsync(valid, c->io_u8.p, n * nv, hipMemcpyDeviceToHost, c->stream));
-    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipMemcpy(cost, c->io_b.p, n * sizeof(float), hipMemcpyDeviceToHost));
+    if (per_view) HIPCHECK(c, hipMemcpy(per_view, c->io_c.p, n * nv * sizeof(float), hipMemcpyDeviceToHost));
+    if (valid) HIPCHECK(c, hipMemcpy(valid, c->io_u8.p, n * nv, hipMemcpyDeviceToHost));
   }
-  return PHIMVS_OK;
+  J.planes_in = nullptr;
+  J.cost_out = J.per_view_out = nullptr;
+  J.valid_out = nullptr;
+  return upload_jobs(c, b);
 }
 
 int phimvs_patchmatch(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, int dilation, int iters,
@@ -569,12 +796,174 @@ int phimvs_patchmatch(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int w
   if (iters < 0) return fail(c, PHIMVS_E_ARG, "iters must be >= 0");
   int rc = phimvs_prepare(c, ref, srcs, n_srcs, window, dilation, p);
   if (rc) return rc;
-  if ((rc = phimvs_init_planes(c, nullptr, 0))) return rc;
-  for (int it = 1; it <= iters; ++it)
-    for (int colour = 0; colour < 2; ++colour)
-      if ((rc = phimvs_step(c, it, colour, 1, 1))) return rc;
-  return phimvs_output(c, depth, normal, cost, out_on_device);
+  Batch& b = c->single;
+  Job& J = b.jobs[0];
+  const size_t n = (size_t)J.A.W * J.A.H;
+  if (out_on_device) {
+    J.depth_out = depth;
+    J.normal_out = normal;
+    J.final_cost_out = cost;
+  } else {
+    if ((rc = ensure(c, c->io_a, 3 * n)) || (rc = ensure(c, c->io_b, n)) || (rc = ensure(c, c->io_c, n))) return rc;
+    J.normal_out = normal ? c->io_a.p : nullptr;
+    J.depth_out = depth ? c->io_b.p : nullptr;
+    J.final_cost_out = cost ? c->io_c.p : nullptr;
+  }
+  // the table is complete before the sequence starts, so the call does not wait for it
+  if ((rc = upload_jobs(c, b))) return rc;
+  if ((rc = ensure(c, b.queues, (size_t)8 * (2 + 4 * iters)))) return rc;
+  if ((rc = issue_sequence(c, b, iters, true))) return rc;
+  if (!out_on_device) {
+    if (normal) HIPCHECK(c, hipMemcpyAsync(normal, c->io_a.p, 3 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (depth) HIPCHECK(c, hipMemcpyAsync(depth, c->io_b.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (cost) HIPCHECK(c, hipMemcpyAsync(cost, c->io_c.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+  }
+  return PHIMVS_OK;
 }
+
+// ---------------------------------------------------------------------------- batches
+
+int phimvs_patchmatch_batch(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, int iters, int use_graph) {
+  if (!c) return PHIMVS_E_ARG;
+  if (n_jobs < 1 || !jobs) return fail(c, PHIMVS_E_ARG, "need at least one job");
+  if (iters < 0) return fail(c, PHIMVS_E_ARG, "iters must be >= 0");
+  HIPCHECK(c, hipSetDevice(c->device));
+  Batch& b = c->multi;
+  std::vector<Problem> probs;
+  std::string key = std::to_string(c->tuning.tile_rows);
+  for (int i = 0; i < n_jobs; ++i) {
+    const phimvs_job& j = jobs[i];
+    if (j.n_srcs < 1 || !j.srcs) return fail(c, PHIMVS_E_ARG, "job " + std::to_string(i) + ": no source views");
+    Problem P = make_problem(j.ref, j.srcs, j.n_srcs, j.window, j.dilation, &j.params);
+    int rc = validate_problem(c, P);
+    if (rc) return fail(c, rc, "job " + std::to_string(i) + ": " + c->err);
+    probs.push_back(P);
+    key += "|" + problem_key(P);
+  }
+  int rc;
+  if (key != b.layout_key) {
+    release_graph(b);
+    b.jobs.resize(n_jobs);
+    b.state.resize(n_jobs);
+    for (int i = 0; i < n_jobs; ++i)
+      if ((rc = setup_job(c, probs[i], b.jobs[i], b.state[i]))) return rc;
+    layout(b, c->tuning.tile_rows);
+    b.layout_key = key;
+  }
+  bool changed = false;
+  for (int i = 0; i < n_jobs; ++i) {
+    Job& J = b.jobs[i];
+    changed = changed || J.depth_out != jobs[i].depth || J.normal_out != jobs[i].normal ||
+              J.final_cost_out != jobs[i].cost;
+    J.depth_out = jobs[i].depth;
+    J.normal_out = jobs[i].normal;
+    J.final_cost_out = jobs[i].cost;
+  }
+  if (changed || !b.exec) {
+    if ((rc = upload_jobs(c, b))) return rc;  // the table is read at run time, also by the graph
+  }
+  if ((rc = ensure(c, b.queues, (size_t)8 * (2 + 4 * iters)))) return rc;
+  const std::string gkey = key + "#" + std::to_string(iters) + "#" + std::to_string(c->tuning.persistent) + "#" +
+                           std::to_string(c->tuning.wgs_per_cu);
+  if (!use_graph || c->diag) return issue_sequence(c, b, iters, true);
+  if (b.exec && b.graph_key == gkey) {
+    HIPCHECK(c, hipGraphLaunch(b.exec, c->stream));
+    return PHIMVS_OK;
+  }
+  release_graph(b);
+  // record on a private stream (the caller's may be the null stream, which cannot be
+  // captured); the graph is then launched on the caller's stream, after its prior work
+  if (!c->capture_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  hipStream_t user = c->stream;
+  c->stream = c->capture_stream;
+  hipError_t eb = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) {
+    c->stream = user;
+    return fail(c, PHIMVS_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
+  }
+  rc = issue_sequence(c, b, iters, true);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+  c->stream = user;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  HIPCHECK(c, ec);
+  b.graph = g;
+  HIPCHECK(c, hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+  b.graph_key = gkey;
+  HIPCHECK(c, hipGraphLaunch(b.exec, c->stream));
+  return PHIMVS_OK;
+}
+
+int phimvs_set_tuning(phimvs_ctx* c, const phimvs_tuning* t) {
+  if (!c || !t) return PHIMVS_E_ARG;
+  if (t->tile_rows != 1 && t->tile_rows != 2 && t->tile_rows != 4)
+    return fail(c, PHIMVS_E_ARG, "tile_rows must be 1, 2 or 4");
+  if (t->persistent && (t->wgs_per_cu < 1 || t->wgs_per_cu > 16))
+    return fail(c, PHIMVS_E_ARG, "wgs_per_cu must be in [1, 16] for persistent launches");
+  HIPCHECK(c, hipSetDevice(c->device));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const bool shape = t->tile_rows != c->tuning.tile_rows;
+  c->tuning = *t;
+  c->tuning.ms = 0.0;
+  if (shape) {
+    // the tile shape changes the layout of every job: rebuild on next use
+    c->prepared = false;
+    c->single.layout_key.clear();
+    c->multi.layout_key.clear();
+  }
+  release_graph(c->multi);
+  return PHIMVS_OK;
+}
+
+int phimvs_get_tuning(phimvs_ctx* c, phimvs_tuning* t) {
+  if (!c || !t) return PHIMVS_E_ARG;
+  *t = c->tuning;
+  return PHIMVS_OK;
+}
+
+int phimvs_autotune(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, int iters, phimvs_tuning* results,
+                    int* n_results) {
+  if (!c) return PHIMVS_E_ARG;
+  HIPCHECK(c, hipSetDevice(c->device));
+  const phimvs_tuning cands[] = {{4, 0, 0, 0}, {2, 0, 0, 0}, {1, 0, 0, 0}, {4, 1, 2, 0}, {4, 1, 3, 0},
+                                 {4, 1, 4, 0}, {4, 1, 6, 0}, {2, 1, 3, 0}, {2, 1, 4, 0}, {1, 1, 4, 0}};
+  const int n = (int)(sizeof(cands) / sizeof(cands[0]));
+  phimvs_tuning best{};
+  double best_ms = 1e300;
+  int rc;
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0));
+  HIPCHECK(c, hipEventCreate(&e1));
+  for (int i = 0; i < n; ++i) {
+    if ((rc = phimvs_set_tuning(c, &cands[i]))) return rc;
+    if ((rc = phimvs_patchmatch_batch(c, n_jobs, jobs, iters, 1))) return rc;  // capture + warm
+    HIPCHECK(c, hipEventRecord(e0, c->stream));
+    if ((rc = phimvs_patchmatch_batch(c, n_jobs, jobs, iters, 1))) return rc;
+    HIPCHECK(c, hipEventRecord(e1, c->stream));
+    HIPCHECK(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
+    phimvs_tuning r = cands[i];
+    r.ms = ms;
+    if (results && n_results && i < *n_results) results[i] = r;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = r;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (n_results) *n_results = std::min(*n_results, n);
+  if ((rc = phimvs_set_tuning(c, &best))) return rc;
+  c->tuning.ms = best_ms;
+  return PHIMVS_OK;
+}
+
+// ---------------------------------------------------------------------------- diagnostics
 
 int phimvs_diag_enable(phimvs_ctx* c, int flags) {
   if (!c) return PHIMVS_E_ARG;

@@ -3,13 +3,16 @@
 //
 // Work decomposition.  The per-pixel state lives in two checkerboard-compacted
 // colour planes (red: (x + y) even, black: odd), each H x Wc with Wc = ceil(W / 2):
-// pixel (x, y) of colour c sits at column x >> 1 of its colour plane.  A workgroup is
-// 4 waves; wave w handles 64 consecutive compacted pixels of row (4 by + w), i.e. 128
-// full-resolution columns.  One lane owns one pixel and evaluates its hypotheses one
-// after the other; for each hypothesis it walks the window taps in row-major order
-// and, per tap, every source view of the current view group, so the reference-side
-// tap values (LDS) are read once per group and each view's sums are accumulated in
-// plain tap order (the oracle's order: no cross-lane reduction is needed).
+// pixel (x, y) of colour c sits at column x >> 1 of its colour plane.  A launch covers a
+// table of jobs (one reference view each, with its own sources, window and state).  The
+// evaluate kernel works on tiles of tile_rows x (256 / tile_rows) compacted pixels of one
+// colour; one lane owns one pixel and scores its hypotheses one after the other; for
+// each hypothesis it walks the window taps in row-major order and, per tap, the two
+// source views of the current pair, so the reference-side tap values (LDS) are read once
+// per pair and each view's sums are accumulated in plain tap order (the oracle's order:
+// no cross-lane reduction is needed).  Cheap candidate kernels (random initialisation,
+// red/black propagation, random refinement) write candidate planes that the evaluate
+// kernel scores and selects from.
 //
 // Arithmetic.  Every float operation below is the one the method's canonical FP32
 // statement performs, in the same order (explicit fmaf, correctly rounded division and
@@ -50,6 +53,27 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 
 __device__ __forceinline__ float u24(uint32_t v) { return (float)(v >> 8) * 0x1p-24f; }
 
+// Pointers read from the job table are generic; naming the global address space keeps
+// the accesses global loads/stores (flat ones would also hold the LDS wait counter).
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const GLOBAL T* gl(const T* p) { return (const GLOBAL T*)p; }
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gl(T* p) { return (GLOBAL T*)p; }
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4(const float4* p, size_t i) {
+  const f4v v = ((const GLOBAL f4v*)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4(float4* p, size_t i, float4 a) {
+  f4v v;
+  v.x = a.x;
+  v.y = a.y;
+  v.z = a.z;
+  v.w = a.w;
+  ((GLOBAL f4v*)p)[i] = v;
+}
+
 // ---------------------------------------------------------------------------- arithmetic helpers
 __device__ __forceinline__ float dot3f(float ax, float ay, float az, float bx, float by, float bz) {
   return __builtin_fmaf(ax, bx, __builtin_fmaf(ay, by, az * bz));
@@ -72,7 +96,7 @@ __device__ __forceinline__ float sample_quad(const uint32_t* __restrict__ quad, 
   const float fx = __builtin_amdgcn_fractf(up);
   const float fy = __builtin_amdgcn_fractf(vp);
   const uint32_t x0 = (uint32_t)up, y0 = (uint32_t)vp;
-  const uint32_t q = quad[__umul24(y0, (uint32_t)W) + x0];
+  const uint32_t q = gl(quad)[__umul24(y0, (uint32_t)W) + x0];
   const float t00 = (float)(q & 0xFFu), t01 = (float)((q >> 8) & 0xFFu);
   const float t10 = (float)((q >> 16) & 0xFFu), t11 = (float)(q >> 24);
   const float top = __builtin_fmaf(fx, t01 - t00, t00);
@@ -93,204 +117,6 @@ struct RefPix {
   bool ok;                // pixel valid and reference patch variance >= eps_v
   int tbase;              // LDS index of the window's first tap
 };
-
-// ---------------------------------------------------------------------------- plane cost
-// Per-hypothesis values shared by every view: the pixel and m = K^-T n / rho.
-struct Hyp {
-  float m[3];
-  bool ok;  // the reference patch is usable and the plane faces the camera
-};
-
-// Sums of one view group over the window taps in row-major order.  Hm holds the G
-// homographies of views J0 .. J0+G-1.  EXACT selects IEEE division for 1/w.
-template <int G, int J0, bool EXACT>
-__device__ __forceinline__ void tap_pass(const Args& A, const RefPix& rp, const float* __restrict__ tile,
-                                         const float* __restrict__ wcol, const float* __restrict__ wsp,
-                                         const float (&Hm)[G][9], const float (&bc)[G], float (&Sb)[G],
-                                         float (&Sbb)[G], float (&Sab)[G]) {
-  const int R = A.R, s = A.s, TW = A.TW;
-  const float sf = (float)s;
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-    Sb[g] = 0.0f;
-    Sbb[g] = 0.0f;
-    Sab[g] = 0.0f;
-  }
-  int t = 0;
-  for (int k2 = -R; k2 <= R; ++k2) {
-    const float Y = (float)(rp.y + s * k2);
-    float rbu[G], rbv[G], rbw[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      rbu[g] = __builtin_fmaf(Hm[g][1], Y, Hm[g][2]);
-      rbv[g] = __builtin_fmaf(Hm[g][4], Y, Hm[g][5]);
-      rbw[g] = __builtin_fmaf(Hm[g][7], Y, Hm[g][8]);
-    }
-    const float* trow = tile + rp.tbase + (k2 + R) * s * TW;
-    float X = (float)(rp.x - s * R);
-    for (int k1 = 0; k1 <= 2 * R; ++k1, ++t) {
-      const float a = trow[k1 * s] - rp.a_c;
-      float w = 1.0f;
-      if (A.bilateral) w = wcol[(int)fabsf(a)] * wsp[t];
-      const float wa = w * a;
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const SrcDev& V = A.src[J0 + g];
-        const float u = __builtin_fmaf(Hm[g][0], X, rbu[g]);
-        const float v = __builtin_fmaf(Hm[g][3], X, rbv[g]);
-        const float ww = __builtin_fmaf(Hm[g][6], X, rbw[g]);
-        const float r = EXACT ? 1.0f / ww : rcp_nr(ww);
-        const float up = clampf(u * r, V.Wm1);
-        const float vp = clampf(v * r, V.Hm1);
-        const float b = sample_quad(V.quad, V.W, up, vp) - bc[g];
-        const float tb = w * b;
-        Sb[g] = Sb[g] + tb;
-        Sbb[g] = __builtin_fmaf(tb, b, Sbb[g]);
-        Sab[g] = __builtin_fmaf(wa, b, Sab[g]);
-      }
-      X = X + sf;
-    }
-  }
-}
-
-// Views [J0, NV) in groups of G: per group, build the homographies H_j = M_j + e_j m^T,
-// apply the border rule at the window corners, take the centre sample, run the tap
-// pass and finish each view's ZNCC into cj / ok.
-template <int NV, int G, int J0>
-__device__ __forceinline__ void view_groups(const Args& A, const RefPix& rp, const Hyp& h,
-                                            const float* __restrict__ tile, const float* __restrict__ wcol,
-                                            const float* __restrict__ wsp, float (&cj)[NV], bool (&ok)[NV]) {
-  if constexpr (J0 < NV) {
-    constexpr int GG = (NV - J0 < G) ? (NV - J0) : G;
-    float Hm[GG][9], bc[GG];
-    bool fast[GG];
-    const int r = A.s * A.R;
-    const float Xmax = rp.X0 + (float)r, Ymax = rp.Y0 + (float)r;
-    bool need_exact = false, any_ok = false;
-#pragma unroll
-    for (int g = 0; g < GG; ++g) {
-      const SrcDev& V = A.src[J0 + g];
-#pragma unroll
-      for (int rr = 0; rr < 3; ++rr)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Hm[g][rr * 3 + c] = __builtin_fmaf(V.e[rr], h.m[c], V.M[rr * 3 + c]);
-      // border rule at the four window corners (IEEE division)
-      bool inside = h.ok;
-      float wmin = 3.0e38f, wmax = -3.0e38f;
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        const float X = (float)(rp.x + ((cc & 1) ? r : -r));
-        const float Y = (float)(rp.y + ((cc & 2) ? r : -r));
-        const float u = __builtin_fmaf(Hm[g][0], X, __builtin_fmaf(Hm[g][1], Y, Hm[g][2]));
-        const float v = __builtin_fmaf(Hm[g][3], X, __builtin_fmaf(Hm[g][4], Y, Hm[g][5]));
-        const float w = __builtin_fmaf(Hm[g][6], X, __builtin_fmaf(Hm[g][7], Y, Hm[g][8]));
-        const float rw = 1.0f / w;
-        const float up = u * rw, vp = v * rw;
-        inside = inside && (w > 0.0f) && (up >= 0.0f && up <= V.Wm1 && vp >= 0.0f && vp <= V.Hm1);
-        wmin = fminf(wmin, w);
-        wmax = fmaxf(wmax, w);
-      }
-      // every tap's computed w lies within 2^-22 S of the corner range (fma error bound)
-      const float S = fabsf(Hm[g][6]) * Xmax + fabsf(Hm[g][7]) * Ymax + fabsf(Hm[g][8]);
-      const float slack = S * 0x1p-22f;
-      fast[g] = (wmin - slack >= 0x1p-100f) && (wmax + slack <= 0x1p100f);
-      ok[J0 + g] = inside;
-      need_exact = need_exact || (inside && !fast[g]);
-      any_ok = any_ok || inside;
-      {
-        const float u = __builtin_fmaf(Hm[g][0], rp.X0, __builtin_fmaf(Hm[g][1], rp.Y0, Hm[g][2]));
-        const float v = __builtin_fmaf(Hm[g][3], rp.X0, __builtin_fmaf(Hm[g][4], rp.Y0, Hm[g][5]));
-        const float w = __builtin_fmaf(Hm[g][6], rp.X0, __builtin_fmaf(Hm[g][7], rp.Y0, Hm[g][8]));
-        const float rw = 1.0f / w;
-        bc[g] = sample_quad(V.quad, V.W, clampf(u * rw, V.Wm1), clampf(v * rw, V.Hm1));
-      }
-    }
-    if (__ballot(any_ok) != 0) {
-      float Sb[GG], Sbb[GG], Sab[GG];
-      if (__ballot(need_exact) != 0)
-        tap_pass<GG, J0, true>(A, rp, tile, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
-      else
-        tap_pass<GG, J0, false>(A, rp, tile, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
-#pragma unroll
-      for (int g = 0; g < GG; ++g) {
-        if (ok[J0 + g]) {
-          const float mu_b = Sb[g] / rp.S_w;
-          const float var_b = Sbb[g] / rp.S_w - mu_b * mu_b;
-          const float cov = Sab[g] / rp.S_w - rp.mu_a * mu_b;
-          if (var_b >= A.eps_v) {
-            float z = cov / __builtin_sqrtf(rp.var_a * var_b);
-            z = fminf(fmaxf(z, -1.0f), 1.0f);
-            cj[J0 + g] = 1.0f - z;
-          } else {
-            ok[J0 + g] = false;
-          }
-        }
-      }
-    }
-    view_groups<NV, G, J0 + G>(A, rp, h, tile, wcol, wsp, cj, ok);
-  }
-}
-
-// Cost (Eq. 5 over the best-K valid sources) of plane (n, d) at pixel rp; optionally the
-// per-source costs and the validity mask.
-template <int NV, int G, bool PERVIEW>
-__device__ float plane_cost(const Args& A, const RefPix& rp, const float* __restrict__ tile,
-                            const float* __restrict__ wcol, const float* __restrict__ wsp, float nx, float ny,
-                            float nz, float d, float* pv_out, uint32_t* valid_out) {
-  float cj[NV];
-  bool ok[NV];
-#pragma unroll
-  for (int j = 0; j < NV; ++j) {
-    cj[j] = kCmax;
-    ok[j] = false;
-  }
-  const float nr = dot3f(nx, ny, nz, rp.rx, rp.ry, rp.rz);
-  Hyp h;
-  h.ok = rp.ok && (nr < 0.0f);
-  if (__ballot(h.ok) != 0) {
-    const float rho = d * nr;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float kn = __builtin_fmaf(A.Kinv[0 * 3 + c], nx, __builtin_fmaf(A.Kinv[1 * 3 + c], ny, A.Kinv[2 * 3 + c] * nz));
-      h.m[c] = kn / rho;
-    }
-    view_groups<NV, G, 0>(A, rp, h, tile, wcol, wsp, cj, ok);
-  }
-  if (PERVIEW) {
-    uint32_t vm = 0;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      pv_out[j] = ok[j] ? cj[j] : kCmax;
-      vm |= ok[j] ? (1u << j) : 0u;
-    }
-    *valid_out = vm;
-  }
-  // Eq. 5 over the K lowest (C_j, j) valid sources, summed in ascending order
-  int nvalid = 0;
-#pragma unroll
-  for (int j = 0; j < NV; ++j) nvalid += ok[j] ? 1 : 0;
-  const int K = A.top_k > 0 ? (A.top_k < nvalid ? A.top_k : nvalid) : nvalid;
-  float sum = 0.0f;
-  uint32_t used = 0;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    if (i < K) {
-      float best = 0.0f;
-      int bj = -1;
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        const bool cand = ok[j] && !((used >> j) & 1u);
-        if (cand && (bj < 0 || cj[j] < best)) {
-          best = cj[j];
-          bj = j;
-        }
-      }
-      used |= 1u << bj;
-      sum = sum + 1.0f / fmaxf(best, A.eps_c);
-    }
-  }
-  return K > 0 ? (float)K / sum : kCmax;
-}
 
 // ---------------------------------------------------------------------------- plane helpers
 // viewing ray K^-1 (x, y, 1) in float
@@ -328,23 +154,255 @@ __device__ __forceinline__ bool pixel_valid(const Args& A, int x, int y) {
 // directions are rotations: down (dx, -dy), left (dy, dx), right (-dy, dx)
 __constant__ int8_t kNearUp[9][2] = {{0, -1}, {-1, -2}, {1, -2}, {0, -3}, {-2, -3}, {2, -3}, {-1, -4}, {1, -4}, {0, -5}};
 
-// ---------------------------------------------------------------------------- candidate generation
-// Candidate planes live in S.cand: slot k of compacted pixel i at S.cand[k * A.H * A.Wc + i];
-// d = NaN marks an empty slot.
+// ---------------------------------------------------------------------------- plane cost
+// Per-hypothesis values shared by every view: m = K^-T n / rho.
+struct Hyp {
+  float m[3];
+  bool ok;  // the reference patch is usable and the plane faces the camera
+};
 
-__device__ __forceinline__ bool colour_pixel(const Args& A, int colour, int& x, int& y, int& ci) {
-  y = blockIdx.y;
-  ci = blockIdx.x * blockDim.x + threadIdx.x;
-  x = 2 * ci + ((y + colour) & 1);
-  return ci < A.Wc && y < A.H && x < A.W;
+// Sums of a group of G views (J0, J0 + 1, ...) over the window taps in row-major order.
+// EXACT selects IEEE division for 1/w.
+template <int G, bool EXACT>
+__device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp, const float* __restrict__ tile,
+                                         int TW, const float* __restrict__ wcol, const float* __restrict__ wsp,
+                                         const float (&Hm)[G][9], const float (&bc)[G], float (&Sb)[G],
+                                         float (&Sbb)[G], float (&Sab)[G]) {
+  const int R = A.R, s = A.s;
+  const float sf = (float)s;
+  const uint32_t* quad[G];
+  int Wq[G];
+  float Wm1[G], Hm1[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    Sb[g] = 0.0f;
+    Sbb[g] = 0.0f;
+    Sab[g] = 0.0f;
+    quad[g] = A.src[J0 + g].quad;
+    Wq[g] = A.src[J0 + g].W;
+    Wm1[g] = A.src[J0 + g].Wm1;
+    Hm1[g] = A.src[J0 + g].Hm1;
+  }
+  const bool bil = A.bilateral != 0;
+  int t = 0;
+  for (int k2 = -R; k2 <= R; ++k2) {
+    const float Y = (float)(rp.y + s * k2);
+    float rbu[G], rbv[G], rbw[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      rbu[g] = __builtin_fmaf(Hm[g][1], Y, Hm[g][2]);
+      rbv[g] = __builtin_fmaf(Hm[g][4], Y, Hm[g][5]);
+      rbw[g] = __builtin_fmaf(Hm[g][7], Y, Hm[g][8]);
+    }
+    const float* trow = tile + rp.tbase + (k2 + R) * s * TW;
+    float X = (float)(rp.x - s * R);
+    for (int k1 = 0; k1 <= 2 * R; ++k1, ++t) {
+      const float a = trow[k1 * s] - rp.a_c;
+      float w = 1.0f;
+      if (bil) w = wcol[(int)fabsf(a)] * wsp[t];
+      const float wa = w * a;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const float u = __builtin_fmaf(Hm[g][0], X, rbu[g]);
+        const float v = __builtin_fmaf(Hm[g][3], X, rbv[g]);
+        const float ww = __builtin_fmaf(Hm[g][6], X, rbw[g]);
+        const float r = EXACT ? 1.0f / ww : rcp_nr(ww);
+        const float up = clampf(u * r, Wm1[g]);
+        const float vp = clampf(v * r, Hm1[g]);
+        const float b = sample_quad(quad[g], Wq[g], up, vp) - bc[g];
+        const float tb = w * b;
+        Sb[g] = Sb[g] + tb;
+        Sbb[g] = __builtin_fmaf(tb, b, Sbb[g]);
+        Sab[g] = __builtin_fmaf(wa, b, Sab[g]);
+      }
+      X = X + sf;
+    }
+  }
 }
+
+// Views J0 .. J0+G-1: build H_j = M_j + e_j m^T, apply the border rule at the window
+// corners, take the centre sample, run the tap pass and finish each view's ZNCC.
+// c[g] / ok[g] receive 1 - Z and the validity.
+template <int G>
+__device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& rp, const Hyp& h,
+                                           const float* __restrict__ tile, int TW, const float* __restrict__ wcol,
+                                           const float* __restrict__ wsp, float (&c)[G], bool (&ok)[G]) {
+  float Hm[G][9], bc[G];
+  const int r = A.s * A.R;
+  const float Xmax = rp.X0 + (float)r, Ymax = rp.Y0 + (float)r;
+  bool need_exact = false, any_ok = false;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const SrcDev& V = A.src[J0 + g];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) Hm[g][rr * 3 + cc] = __builtin_fmaf(V.e[rr], h.m[cc], V.M[rr * 3 + cc]);
+    // border rule at the four window corners (IEEE division)
+    bool inside = h.ok;
+    float wmin = 3.0e38f, wmax = -3.0e38f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float X = (float)(rp.x + ((k & 1) ? r : -r));
+      const float Y = (float)(rp.y + ((k & 2) ? r : -r));
+      const float u = __builtin_fmaf(Hm[g][0], X, __builtin_fmaf(Hm[g][1], Y, Hm[g][2]));
+      const float v = __builtin_fmaf(Hm[g][3], X, __builtin_fmaf(Hm[g][4], Y, Hm[g][5]));
+      const float w = __builtin_fmaf(Hm[g][6], X, __builtin_fmaf(Hm[g][7], Y, Hm[g][8]));
+      const float rw = 1.0f / w;
+      const float up = u * rw, vp = v * rw;
+      inside = inside && (w > 0.0f) && (up >= 0.0f && up <= V.Wm1 && vp >= 0.0f && vp <= V.Hm1);
+      wmin = fminf(wmin, w);
+      wmax = fmaxf(wmax, w);
+    }
+    // every tap's computed w lies within 2^-22 S of the corner range (fma error bound), so
+    // the fast reciprocal is exact for the whole window when this range stays in [2^-100, 2^100]
+    const float S = fabsf(Hm[g][6]) * Xmax + fabsf(Hm[g][7]) * Ymax + fabsf(Hm[g][8]);
+    const float slack = S * 0x1p-22f;
+    const bool fast = (wmin - slack >= 0x1p-100f) && (wmax + slack <= 0x1p100f);
+    ok[g] = inside;
+    c[g] = kCmax;
+    need_exact = need_exact || (inside && !fast);
+    any_ok = any_ok || inside;
+    {
+      const float u = __builtin_fmaf(Hm[g][0], rp.X0, __builtin_fmaf(Hm[g][1], rp.Y0, Hm[g][2]));
+      const float v = __builtin_fmaf(Hm[g][3], rp.X0, __builtin_fmaf(Hm[g][4], rp.Y0, Hm[g][5]));
+      const float w = __builtin_fmaf(Hm[g][6], rp.X0, __builtin_fmaf(Hm[g][7], rp.Y0, Hm[g][8]));
+      const float rw = 1.0f / w;
+      bc[g] = sample_quad(V.quad, V.W, clampf(u * rw, V.Wm1), clampf(v * rw, V.Hm1));
+    }
+  }
+  if (__ballot(any_ok) == 0) return;
+  float Sb[G], Sbb[G], Sab[G];
+  if (__ballot(need_exact) != 0)
+    tap_pass<G, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+  else
+    tap_pass<G, false>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (ok[g]) {
+      const float mu_b = Sb[g] / rp.S_w;
+      const float var_b = Sbb[g] / rp.S_w - mu_b * mu_b;
+      const float cov = Sab[g] / rp.S_w - rp.mu_a * mu_b;
+      if (var_b >= A.eps_v) {
+        float z = cov / __builtin_sqrtf(rp.var_a * var_b);
+        z = fminf(fmaxf(z, -1.0f), 1.0f);
+        c[g] = 1.0f - z;
+      } else {
+        ok[g] = false;
+      }
+    }
+  }
+}
+
+// keep the valid per-source costs in ascending order (equal values keep arrival order)
+__device__ __forceinline__ void topk_insert(float (&top)[kMaxTopK], float c) {
+#pragma unroll
+  for (int i = 0; i < kMaxTopK; ++i) {
+    const float t = top[i];
+    const bool lt = c < t;
+    top[i] = lt ? c : t;
+    c = lt ? t : c;
+  }
+}
+
+// Cost (Eq. 5 over the best-K valid sources) of plane (n, d) at pixel rp.  Sources are
+// scored two at a time; per_view / valid (global, optional) receive 1 - Z and the flag of
+// each source.
+__device__ float plane_cost(const Args& A, const RefPix& rp, const float* __restrict__ tile, int TW,
+                            const float* __restrict__ wcol, const float* __restrict__ wsp, float nx, float ny,
+                            float nz, float d, float* per_view, uint8_t* valid) {
+  float top[kMaxTopK];
+#pragma unroll
+  for (int i = 0; i < kMaxTopK; ++i) top[i] = __builtin_inff();
+  int nvalid = 0;
+  const int NV = A.n_src;
+  const float nr = dot3f(nx, ny, nz, rp.rx, rp.ry, rp.rz);
+  Hyp h;
+  h.ok = rp.ok && (nr < 0.0f);
+  const bool any = __ballot(h.ok) != 0;
+  if (any) {
+    const float rho = d * nr;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float kn = __builtin_fmaf(A.Kinv[0 * 3 + c], nx, __builtin_fmaf(A.Kinv[1 * 3 + c], ny, A.Kinv[2 * 3 + c] * nz));
+      h.m[c] = kn / rho;
+    }
+  }
+  for (int j0 = 0; j0 < NV; j0 += 2) {
+    float c[2] = {kCmax, kCmax};
+    bool ok[2] = {false, false};
+    const int gn = NV - j0 < 2 ? 1 : 2;
+    if (any) {
+      if (gn == 2) {
+        view_group<2>(A, j0, rp, h, tile, TW, wcol, wsp, c, ok);
+      } else {
+        float c1[1];
+        bool ok1[1];
+        view_group<1>(A, j0, rp, h, tile, TW, wcol, wsp, c1, ok1);
+        c[0] = c1[0];
+        ok[0] = ok1[0];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      if (g < gn) {
+        if (per_view) gl(per_view)[j0 + g] = ok[g] ? c[g] : kCmax;
+        if (valid) gl(valid)[j0 + g] = ok[g] ? 1 : 0;
+        if (ok[g]) {
+          topk_insert(top, c[g]);
+          ++nvalid;
+        }
+      }
+    }
+  }
+  // Eq. 5 over the K lowest valid costs, summed in ascending order
+  const int K = A.top_k > 0 ? (A.top_k < nvalid ? A.top_k : nvalid) : nvalid;
+  float sum = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kMaxTopK; ++i)
+    if (i < K) sum = sum + 1.0f / fmaxf(top[i], A.eps_c);
+  return K > 0 ? (float)K / sum : kCmax;
+}
+
+// ---------------------------------------------------------------------------- job lookup
+// The job owning global index g of a work space whose jobs start at first(j) (ascending).
+__device__ __forceinline__ int job_of_tile(const Job* __restrict__ jobs, int n_jobs, int g) {
+  int j = 0;
+  while (j + 1 < n_jobs && g >= jobs[j + 1].tile0) ++j;
+  return j;
+}
+
+__device__ __forceinline__ int job_of_cblk(const Job* __restrict__ jobs, int n_jobs, int g) {
+  int j = 0;
+  while (j + 1 < n_jobs && g >= jobs[j + 1].cblk0) ++j;
+  return j;
+}
+
+// candidate / unpack blocks: 128 consecutive compacted pixels (or 256 pixels) of one row
+__device__ __forceinline__ bool cblk_pixel(const Job* __restrict__ jobs, const Launch& L, int& jb, int& x, int& y,
+                                           int& ci) {
+  const int g = blockIdx.x;
+  jb = job_of_cblk(jobs, L.n_jobs, g);
+  const Job& J = jobs[jb];
+  const int local = g - J.cblk0;
+  y = local / J.cblk_x;
+  ci = (local - y * J.cblk_x) * 128 + (int)threadIdx.x;
+  x = 2 * ci + ((y + L.colour) & 1);
+  return ci < J.A.Wc && y < J.A.H && x < J.A.W;
+}
+
+// ---------------------------------------------------------------------------- candidate generation
+// Candidate planes live in J.cand: slot k of compacted pixel i at J.cand[k * H * Wc + i];
+// d = NaN marks an empty slot.
 
 // random initialisation (Sec. III-B): d uniform in the depth range, theta in [0, 2 pi],
 // phi in [-pi/2, pi/2], n = (cos theta sin phi, sin theta sin phi, cos phi) turned to face
 // the camera; slot 1 carries the caller's proposal, if any
-__global__ void cand_init_kernel(Args A, Step S) {
-  int x, y, ci;
-  if (!colour_pixel(A, S.colour, x, y, ci)) return;
+__global__ __launch_bounds__(128) void cand_init_kernel(const Job* __restrict__ jobs, Launch L) {
+  int jb, x, y, ci;
+  if (!cblk_pixel(jobs, L, jb, x, y, ci)) return;
+  const Job& J = jobs[jb];
+  const Args& A = J.A;
   const size_t cidx = (size_t)y * A.Wc + ci;
   const size_t plane_sz = (size_t)A.H * A.Wc;
   float4 c0 = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
@@ -359,22 +417,24 @@ __global__ void cand_init_kernel(Args A, Step S) {
     facing_normal(A, x, y, theta, phi, nx, ny, nz);
     c0 = make_float4(nx, ny, nz, d);
   }
-  S.cand[cidx] = c0;
-  if (S.planes_in) S.cand[plane_sz + cidx] = reinterpret_cast<const float4*>(S.planes_in)[(size_t)y * A.W + x];
+  J.cand[cidx] = c0;
+  if (J.planes_in) J.cand[plane_sz + cidx] = reinterpret_cast<const float4*>(J.planes_in)[(size_t)y * A.W + x];
 }
 
 // red/black propagation candidates: per region, the other colour's lowest-cost pixel q
 // (first in enumeration order on ties), its plane re-expressed at p by ray-plane
 // intersection; empty if the plane does not face p's ray or leaves the depth range
-__global__ void cand_prop_kernel(Args A, Step S) {
-  int x, y, ci;
-  if (!colour_pixel(A, S.colour, x, y, ci)) return;
+__global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ jobs, Launch L) {
+  int jb, x, y, ci;
+  if (!cblk_pixel(jobs, L, jb, x, y, ci)) return;
+  const Job& J = jobs[jb];
+  const Args& A = J.A;
   const size_t cidx = (size_t)y * A.Wc + ci;
   const size_t plane_sz = (size_t)A.H * A.Wc;
   const bool valid = pixel_valid(A, x, y);
-  const int oc = 1 - S.colour;
+  const int oc = 1 - L.colour;
   const float4* __restrict__ oplane = A.plane[oc];
-  const float* __restrict__ ocost = A.cost[oc];
+  const GLOBAL float* __restrict__ ocost = gl(A.cost[oc]);
   float rx, ry, rz;
   ray_f(A, x, y, rx, ry, rz);
   for (int g = 0; g < 8; ++g) {
@@ -399,7 +459,7 @@ __global__ void cand_prop_kernel(Args A, Step S) {
         if (qx < 0 || c < qc) { qx = xq; qy = yq; qc = c; }
       }
       if (qx >= 0) {
-        const float4 q = oplane[(size_t)qy * A.Wc + (qx >> 1)];
+        const float4 q = ld4(oplane, (size_t)qy * A.Wc + (qx >> 1));
         float rqx, rqy, rqz;
         ray_f(A, qx, qy, rqx, rqy, rqz);
         const float num = dot3f(q.x, q.y, q.z, q.w * rqx, q.w * rqy, q.w * rqz);
@@ -408,24 +468,26 @@ __global__ void cand_prop_kernel(Args A, Step S) {
         if ((den < 0.0f) && (dn >= A.d_lo && dn <= A.d_hi)) cand = make_float4(q.x, q.y, q.z, dn);
       }
     }
-    S.cand[g * plane_sz + cidx] = cand;
+    st4(J.cand, g * plane_sz + cidx, cand);
   }
 }
 
 // random refinement candidates (Sec. III-C): Delta_d in [-d_hi/4, d_hi/4], Delta_theta in
 // [-pi/2, pi/2], Delta_phi in [-pi/12, pi/12]; (d_new, n_old), (d_old, n_new), (d_new, n_new),
 // the two using d_new empty when it leaves the depth range
-__global__ void cand_refine_kernel(Args A, Step S) {
-  int x, y, ci;
-  if (!colour_pixel(A, S.colour, x, y, ci)) return;
+__global__ __launch_bounds__(128) void cand_refine_kernel(const Job* __restrict__ jobs, Launch L) {
+  int jb, x, y, ci;
+  if (!cblk_pixel(jobs, L, jb, x, y, ci)) return;
+  const Job& J = jobs[jb];
+  const Args& A = J.A;
   const size_t cidx = (size_t)y * A.Wc + ci;
   const size_t plane_sz = (size_t)A.H * A.Wc;
   const float qnan = __int_as_float(0x7fc00000);
   float4 c0 = make_float4(0.f, 0.f, 0.f, qnan), c1 = c0, c2 = c0;
   if (pixel_valid(A, x, y)) {
-    const float4 cur = A.plane[S.colour][cidx];
+    const float4 cur = A.plane[L.colour][cidx];
     const uint32_t plin = (uint32_t)((uint64_t)y * (uint64_t)A.W + (uint64_t)x);
-    const uint4 rnd = philox10(make_uint4(plin, (uint32_t)S.iteration, 1u, 0u), A.seed_lo, A.seed_hi);
+    const uint4 rnd = philox10(make_uint4(plin, (uint32_t)L.iteration, 1u, 0u), A.seed_lo, A.seed_hi);
     const float u0 = u24(rnd.x), u1 = u24(rnd.y), u2 = u24(rnd.z);
     const float dd = (2.0f * u0 - 1.0f) * (A.d_hi * 0.25f);
     const float d_new = cur.w + dd;
@@ -440,49 +502,50 @@ __global__ void cand_refine_kernel(Args A, Step S) {
     c1 = make_float4(nx, ny, nz, cur.w);
     if (d_ok) c2 = make_float4(nx, ny, nz, d_new);
   }
-  S.cand[cidx] = c0;
-  S.cand[plane_sz + cidx] = c1;
-  S.cand[2 * plane_sz + cidx] = c2;
+  J.cand[cidx] = c0;
+  J.cand[plane_sz + cidx] = c1;
+  J.cand[2 * plane_sz + cidx] = c2;
 }
 
 // ---------------------------------------------------------------------------- evaluate and select
-// MODE 0: initialisation: slot 0 (random plane) is taken, slot 1 (proposal) replaces it when
-//         its cost is not higher.
-// MODE 1: update: candidates 0..ncand-1 in order replace the current plane on a strictly
-//         lower cost (the first of equal costs wins).
-// MODE 2: cost of row-major input planes (teacher-forced evaluation), per source optional.
-template <int NV, int G, int MODE>
-__global__ __launch_bounds__(256) void select_kernel(Args A, Step S) {
-  extern __shared__ float lds[];
-  float* wcol = lds;                 // 256
-  float* wsp = lds + 256;            // (2R+1)^2
-  float* tile = wsp + A.n_taps;      // TH x TW
-  const int colour = S.colour;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+// A tile is tile_rows rows x (256 / tile_rows) compacted pixels of one colour of one job; one
+// lane per pixel.  mode 0: initialisation (slot 0, the random plane, is taken; slot 1, a
+// proposal, replaces it when not more expensive).  mode 1: update (candidates 0..ncand-1 in
+// order replace the current plane on a strictly lower cost; the first of equal costs wins).
+// mode 2: cost of row-major input planes, optionally per source.
+__device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile, float* lds) {
+  const Args& A = J.A;
+  const int TR = L.tile_rows;
+  const int TC = kBlock / TR;  // compacted columns per tile
+  const int local = tile - J.tile0;
+  const int tile_y = local / J.tiles_x;
+  const int tile_x = local - tile_y * J.tiles_x;
   const int r = A.s * A.R;
-  const int x_org = blockIdx.x * 128 - r;
-  const int y_org = blockIdx.y * 4 - r;
-
-  // stage weights and the reference tile (fp16 -> fp32) in LDS
-  for (int i = threadIdx.x; i < 256; i += 256) wcol[i] = A.wcol[i];
-  for (int i = threadIdx.x; i < A.n_taps; i += 256) wsp[i] = A.wsp[i];
-  const int tsize = A.TW * A.TH;
-  for (int i = threadIdx.x; i < tsize; i += 256) {
-    const int ty = i / A.TW, tx = i - ty * A.TW;
+  const int TW = 2 * TC + 2 * r, TH = TR + 2 * r;
+  float* wcol = lds;            // 256
+  float* wsp = lds + 256;       // n_taps
+  float* tile_lds = wsp + A.n_taps;
+  const int x_org = tile_x * 2 * TC - r;
+  const int y_org = tile_y * TR - r;
+  for (int i = threadIdx.x; i < 256; i += kBlock) wcol[i] = gl(A.wcol)[i];
+  for (int i = threadIdx.x; i < A.n_taps; i += kBlock) wsp[i] = gl(A.wsp)[i];
+  for (int i = threadIdx.x; i < TW * TH; i += kBlock) {
+    const int ty = i / TW, tx = i - ty * TW;
     const int gx = min(max(x_org + tx, 0), A.W - 1);
     const int gy = min(max(y_org + ty, 0), A.H - 1);
-    tile[i] = __half2float(A.ref[(size_t)gy * A.W + gx]);
+    const unsigned short hb = gl(reinterpret_cast<const unsigned short*>(A.ref))[(size_t)gy * A.W + gx];
+    tile_lds[i] = __half2float(__ushort_as_half(hb));
   }
   __syncthreads();
 
-  const int y = blockIdx.y * 4 + wave;
-  const int ci = blockIdx.x * 64 + lane;
+  const int row = threadIdx.x / TC, col = threadIdx.x - row * TC;
+  const int colour = L.colour;
+  const int y = tile_y * TR + row;
+  const int ci = tile_x * TC + col;
   const int par = (y + colour) & 1;
   const int x = 2 * ci + par;
-  const bool in_img = y < A.H && x < A.W && ci < A.Wc;
+  const bool in_img = y < A.H && ci < A.Wc && x < A.W;
   const bool valid = in_img && pixel_valid(A, x, y);
-  if (__ballot(in_img) == 0) return;
 
   RefPix rp;
   rp.x = x;
@@ -490,18 +553,18 @@ __global__ __launch_bounds__(256) void select_kernel(Args A, Step S) {
   rp.X0 = (float)x;
   rp.Y0 = (float)y;
   rp.ok = false;
-  rp.tbase = wave * A.TW + 2 * lane + par;  // tile position of the window's first tap (-R, -R)
+  rp.tbase = row * TW + 2 * col + par;  // tile position of the window's first tap (-R, -R)
   ray_f(A, x, y, rp.rx, rp.ry, rp.rz);
   rp.a_c = 0.0f;
   rp.S_w = 1.0f;
   rp.mu_a = 0.0f;
   rp.var_a = 0.0f;
   if (valid) {
-    rp.a_c = tile[(wave + r) * A.TW + 2 * lane + par + r];
+    rp.a_c = tile_lds[(row + r) * TW + 2 * col + par + r];
     float S_w = 0.0f, S_a = 0.0f, S_aa = 0.0f;
     int t = 0;
     for (int k2 = 0; k2 <= 2 * A.R; ++k2) {
-      const float* trow = tile + rp.tbase + k2 * A.s * A.TW;
+      const float* trow = tile_lds + rp.tbase + k2 * A.s * TW;
       for (int k1 = 0; k1 <= 2 * A.R; ++k1, ++t) {
         const float a = trow[k1 * A.s] - rp.a_c;
         float w = 1.0f;
@@ -517,25 +580,26 @@ __global__ __launch_bounds__(256) void select_kernel(Args A, Step S) {
     rp.var_a = S_aa / S_w - rp.mu_a * rp.mu_a;
     rp.ok = rp.var_a >= A.eps_v;
   }
-  if (!in_img) return;
+  const int lane = threadIdx.x & 63;
 
-  if (MODE == 2) {
-    const size_t p = (size_t)y * A.W + x;
-    float c = kCmax;
-    float pv[NV];
-    uint32_t vm = 0;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) pv[j] = kCmax;
-    if (S.count && lane == 0) atomicAdd(S.count, (unsigned long long)__popcll(__ballot(valid)));
-    if (valid) {
-      const float4 pl = reinterpret_cast<const float4*>(S.planes_in)[p];
-      c = plane_cost<NV, G, true>(A, rp, tile, wcol, wsp, pl.x, pl.y, pl.z, pl.w, pv, &vm);
+  if (L.mode == 2) {
+    if (in_img) {
+      const size_t p = (size_t)y * A.W + x;
+      if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(__ballot(valid)));
+      float c = kCmax;
+      float* pv = J.per_view_out ? J.per_view_out + p * A.n_src : nullptr;
+      uint8_t* vm = J.valid_out ? J.valid_out + p * A.n_src : nullptr;
+      if (valid) {
+        const float4 pl = ld4(reinterpret_cast<const float4*>(J.planes_in), p);
+        c = plane_cost(A, rp, tile_lds, TW, wcol, wsp, pl.x, pl.y, pl.z, pl.w, pv, vm);
+      } else {
+        for (int j = 0; j < A.n_src; ++j) {
+          if (pv) gl(pv)[j] = kCmax;
+          if (vm) gl(vm)[j] = 0;
+        }
+      }
+      gl(J.cost_out)[p] = c;
     }
-    S.cost_out[p] = c;
-    if (S.per_view_out)
-      for (int j = 0; j < NV; ++j) S.per_view_out[p * NV + j] = pv[j];
-    if (S.valid_out)
-      for (int j = 0; j < NV; ++j) S.valid_out[p * NV + j] = (uint8_t)((vm >> j) & 1u);
     return;
   }
 
@@ -543,32 +607,63 @@ __global__ __launch_bounds__(256) void select_kernel(Args A, Step S) {
   const size_t plane_sz = (size_t)A.H * A.Wc;
   float4 best = make_float4(0.f, 0.f, 0.f, 0.f);
   float bc = kCmax;
-  if (MODE == 1 && valid) {
-    best = A.plane[colour][cidx];
-    bc = A.cost[colour][cidx];
+  if (L.mode == 1 && valid) {
+    best = ld4(A.plane[colour], cidx);
+    bc = gl(A.cost[colour])[cidx];
   }
-  for (int k = 0; k < S.ncand; ++k) {
-    const float4 h = S.cand[k * plane_sz + cidx];
+  for (int k = 0; k < L.ncand; ++k) {
+    float4 h = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
+    if (valid) h = ld4(J.cand, k * plane_sz + cidx);
     const bool has = valid && !__builtin_isnan(h.w);
     const unsigned long long bal = __ballot(has);
     if (bal == 0) continue;
-    if (S.count && lane == 0) atomicAdd(S.count, (unsigned long long)__popcll(bal));
+    if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(bal));
     if (has) {
-      const float c = plane_cost<NV, G, false>(A, rp, tile, wcol, wsp, h.x, h.y, h.z, h.w, nullptr, nullptr);
-      const bool take = MODE == 0 ? (k == 0 || c <= bc) : (c < bc);
+      const float c = plane_cost(A, rp, tile_lds, TW, wcol, wsp, h.x, h.y, h.z, h.w, nullptr, nullptr);
+      const bool take = L.mode == 0 ? (k == 0 || c <= bc) : (c < bc);
       if (take) {
         bc = c;
         best = h;
       }
     }
   }
-  if (MODE == 1 && !valid) return;
+  if (!in_img || (L.mode == 1 && !valid)) return;
   if (!valid) {
     best = make_float4(0.f, 0.f, 0.f, 0.f);
     bc = kCmax;
   }
-  A.plane[colour][cidx] = best;
-  A.cost[colour][cidx] = bc;
+  st4(A.plane[colour], cidx, best);
+  gl(A.cost[colour])[cidx] = bc;
+}
+
+// Non-persistent: one workgroup per tile, tiles given to the 8 XCDs in contiguous ranges
+// (workgroup b runs on XCD b % 8), so each XCD's L2 serves a compact band of the image.
+// Persistent: a fixed grid; each workgroup pulls tiles from its XCD's queue over the same
+// contiguous range, so uneven jobs balance dynamically within an XCD.
+__global__ __launch_bounds__(kBlock) void eval_kernel(const Job* __restrict__ jobs, Launch L) {
+  extern __shared__ float lds[];
+  __shared__ int next_tile;
+  const int xcd = blockIdx.x & 7;
+  const int per = (L.total_tiles + 7) / 8;
+  const int begin = xcd * per;
+  const int end = min(L.total_tiles, begin + per);
+  if (!L.persistent) {
+    const int tile = begin + (int)(blockIdx.x >> 3);
+    if (tile >= end) return;
+    const int jb = job_of_tile(jobs, L.n_jobs, tile);
+    eval_tile(jobs[jb], L, tile, lds);
+    return;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) next_tile = begin + (int)atomicAdd(&L.queue[xcd], 1u);
+    __syncthreads();
+    const int tile = next_tile;
+    __syncthreads();
+    if (tile >= end) return;
+    const int jb = job_of_tile(jobs, L.n_jobs, tile);
+    eval_tile(jobs[jb], L, tile, lds);
+    __syncthreads();  // the next tile re-stages LDS
+  }
 }
 
 // ---------------------------------------------------------------------------- image preparation
@@ -585,40 +680,49 @@ __global__ void build_view_kernel(const uint8_t* __restrict__ img, int64_t strid
   quad[(size_t)y * W + x] = i00 | (i01 << 8) | (i10 << 16) | (i11 << 24);
 }
 
-// colour planes -> row-major planes (n, d) + cost, or depth / normal / cost
-__global__ void unpack_kernel(const float4* __restrict__ p0, const float4* __restrict__ p1, const float* __restrict__ c0,
-                              const float* __restrict__ c1, int W, int H, int Wc, float* __restrict__ planes,
-                              float* __restrict__ depth, float* __restrict__ normal, float* __restrict__ cost) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  if (x >= W || y >= H) return;
+// colour planes -> row-major outputs (planes and cost, or depth / normal / cost); blocks of
+// 256 pixels of one row (cblk_x counts 128-wide compacted blocks = 256-wide pixel blocks)
+__global__ __launch_bounds__(256) void unpack_kernel(const Job* __restrict__ jobs, Launch L) {
+  const int g = blockIdx.x;
+  const int jb = job_of_cblk(jobs, L.n_jobs, g);
+  const Job& J = jobs[jb];
+  const Args& A = J.A;
+  const int local = g - J.cblk0;
+  const int y = local / J.cblk_x;
+  const int x = (local - y * J.cblk_x) * 256 + (int)threadIdx.x;
+  if (x >= A.W || y >= A.H) return;
   const int colour = (x + y) & 1;
-  const size_t ci = (size_t)y * Wc + (x >> 1);
-  const float4 pl = colour ? p1[ci] : p0[ci];
-  const float c = colour ? c1[ci] : c0[ci];
-  const size_t p = (size_t)y * W + x;
-  if (planes) reinterpret_cast<float4*>(planes)[p] = pl;
-  if (depth) depth[p] = pl.w;
-  if (normal) {
-    normal[3 * p + 0] = pl.x;
-    normal[3 * p + 1] = pl.y;
-    normal[3 * p + 2] = pl.z;
+  const size_t ci = (size_t)y * A.Wc + (x >> 1);
+  const float4 pl = A.plane[colour][ci];
+  const float c = A.cost[colour][ci];
+  const size_t p = (size_t)y * A.W + x;
+  if (J.planes_out) reinterpret_cast<float4*>(J.planes_out)[p] = pl;
+  if (J.depth_out) J.depth_out[p] = pl.w;
+  if (J.normal_out) {
+    J.normal_out[3 * p + 0] = pl.x;
+    J.normal_out[3 * p + 1] = pl.y;
+    J.normal_out[3 * p + 2] = pl.z;
   }
-  if (cost) cost[p] = c;
+  if (J.final_cost_out) J.final_cost_out[p] = c;
 }
 
-__global__ void pack_kernel(const float* __restrict__ planes, const float* __restrict__ cost, int W, int H, int Wc,
-                            float4* __restrict__ p0, float4* __restrict__ p1, float* __restrict__ c0,
-                            float* __restrict__ c1) {
+// row-major planes + cost -> the colour planes of job 0
+__global__ __launch_bounds__(256) void pack_kernel(const Job* __restrict__ jobs, const float* __restrict__ planes,
+                                                   const float* __restrict__ cost) {
+  const Args& A = jobs[0].A;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= W || y >= H) return;
+  if (x >= A.W || y >= A.H) return;
   const int colour = (x + y) & 1;
-  const size_t ci = (size_t)y * Wc + (x >> 1);
-  const size_t p = (size_t)y * W + x;
-  const float4 pl = reinterpret_cast<const float4*>(planes)[p];
-  if (colour) { p1[ci] = pl; c1[ci] = cost[p]; }
-  else { p0[ci] = pl; c0[ci] = cost[p]; }
+  const size_t ci = (size_t)y * A.Wc + (x >> 1);
+  const size_t p = (size_t)y * A.W + x;
+  A.plane[colour][ci] = reinterpret_cast<const float4*>(planes)[p];
+  A.cost[colour][ci] = cost[p];
+}
+
+__global__ void zero_kernel(unsigned int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 // exhaustive check of rcp_nr against the correctly rounded reciprocal on a range of bit patterns
@@ -640,58 +744,52 @@ __global__ void rcp_check_kernel(uint32_t first, uint32_t count, unsigned long l
 // ---------------------------------------------------------------------------- launchers
 namespace phimvs_internal {
 
-template <int NV>
-static hipError_t launch_nv(int mode, const Args& A, const Step& S, dim3 grid, size_t lds, hipStream_t st) {
-  constexpr int G = NV < 2 ? NV : 2;  // two views per pass over the taps (occupancy)
-  if (mode == 0) hipLaunchKernelGGL((pmk::select_kernel<NV, G, 0>), grid, dim3(256), lds, st, A, S);
-  else if (mode == 1) hipLaunchKernelGGL((pmk::select_kernel<NV, G, 1>), grid, dim3(256), lds, st, A, S);
-  else hipLaunchKernelGGL((pmk::select_kernel<NV, G, 2>), grid, dim3(256), lds, st, A, S);
+size_t eval_lds_bytes(int tile_rows, int max_radius_px, int max_taps) {
+  const int TC = kBlock / tile_rows;
+  const size_t tw = 2 * TC + 2 * max_radius_px, th = tile_rows + 2 * max_radius_px;
+  return sizeof(float) * (256 + (size_t)max_taps + tw * th);
+}
+
+hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds, hipStream_t st) {
+  // tiles above 64 KiB of LDS (one-row tiles with wide windows) need the opt-in limit
+  static bool raised = false;
+  if (lds > 65536 && !raised) {
+    const hipError_t e = hipFuncSetAttribute((const void*)pmk::eval_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+    if (e != hipSuccess) return e;
+    raised = true;
+  }
+  if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pmk::eval_kernel, dim3(grid), dim3(kBlock), lds, st, d_jobs, L);
   return hipGetLastError();
 }
 
-hipError_t launch_select(int mode, const Args& A, const Step& S, hipStream_t st) {
-  const dim3 grid((A.Wc + 63) / 64, (A.H + 3) / 4, 1);
-  const size_t lds = sizeof(float) * (256 + A.n_taps + A.TW * A.TH);
-  switch (A.n_src) {
-    case 1: return launch_nv<1>(mode, A, S, grid, lds, st);
-    case 2: return launch_nv<2>(mode, A, S, grid, lds, st);
-    case 3: return launch_nv<3>(mode, A, S, grid, lds, st);
-    case 4: return launch_nv<4>(mode, A, S, grid, lds, st);
-    case 5: return launch_nv<5>(mode, A, S, grid, lds, st);
-    case 6: return launch_nv<6>(mode, A, S, grid, lds, st);
-    case 7: return launch_nv<7>(mode, A, S, grid, lds, st);
-    case 8: return launch_nv<8>(mode, A, S, grid, lds, st);
-    case 9: return launch_nv<9>(mode, A, S, grid, lds, st);
-    case 10: return launch_nv<10>(mode, A, S, grid, lds, st);
-    case 11: return launch_nv<11>(mode, A, S, grid, lds, st);
-    case 12: return launch_nv<12>(mode, A, S, grid, lds, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_candidates(int kind, const Job* d_jobs, const Launch& L, hipStream_t st) {
+  const dim3 grid(L.total_cblk);
+  if (kind == 0) hipLaunchKernelGGL(pmk::cand_init_kernel, grid, dim3(128), 0, st, d_jobs, L);
+  else if (kind == 1) hipLaunchKernelGGL(pmk::cand_prop_kernel, grid, dim3(128), 0, st, d_jobs, L);
+  else hipLaunchKernelGGL(pmk::cand_refine_kernel, grid, dim3(128), 0, st, d_jobs, L);
+  return hipGetLastError();
 }
 
-hipError_t launch_candidates(int kind, const Args& A, const Step& S, hipStream_t st) {
-  const dim3 grid((A.Wc + 127) / 128, A.H);
-  if (kind == 0) hipLaunchKernelGGL(pmk::cand_init_kernel, grid, dim3(128), 0, st, A, S);
-  else if (kind == 1) hipLaunchKernelGGL(pmk::cand_prop_kernel, grid, dim3(128), 0, st, A, S);
-  else hipLaunchKernelGGL(pmk::cand_refine_kernel, grid, dim3(128), 0, st, A, S);
+hipError_t launch_unpack(const Job* d_jobs, const Launch& L, hipStream_t st) {
+  hipLaunchKernelGGL(pmk::unpack_kernel, dim3(L.total_cblk), dim3(256), 0, st, d_jobs, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const Job* d_jobs, int W, int H, const float* planes, const float* cost, hipStream_t st) {
+  hipLaunchKernelGGL(pmk::pack_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, d_jobs, planes, cost);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(unsigned int* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(pmk::zero_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 
 hipError_t launch_build_view(const uint8_t* img, int64_t stride, int W, int H, __half* plain, uint32_t* quad,
                              hipStream_t st) {
   hipLaunchKernelGGL(pmk::build_view_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, img, stride, W, H, plain, quad);
-  return hipGetLastError();
-}
-
-hipError_t launch_unpack(const Args& A, float* planes, float* depth, float* normal, float* cost, hipStream_t st) {
-  hipLaunchKernelGGL(pmk::unpack_kernel, dim3((A.W + 255) / 256, A.H), dim3(256), 0, st, A.plane[0], A.plane[1],
-                     A.cost[0], A.cost[1], A.W, A.H, A.Wc, planes, depth, normal, cost);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack(const Args& A, const float* planes, const float* cost, hipStream_t st) {
-  hipLaunchKernelGGL(pmk::pack_kernel, dim3((A.W + 255) / 256, A.H), dim3(256), 0, st, planes, cost, A.W, A.H, A.Wc,
-                     A.plane[0], A.plane[1], A.cost[0], A.cost[1]);
   return hipGetLastError();
 }
 

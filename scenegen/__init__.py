@@ -347,13 +347,16 @@ class _World:
         return top + sv * (bot - top)
 
 
-def _render(world: _World, K, R_m, C_m, w, h, view_key, noise_sigma, seed, chunk_rows=None):
-    """Render one camera (pose in the master frame: X_cam = R_m (X - C_m))."""
+def _render(world: _World, K, R_m, C_m, w, h, view_key, noise_sigma, seed, chunk_rows=None, want_depth=False):
+    """Render one camera (pose in the master frame: X_cam = R_m (X - C_m)); optionally also
+    the camera-Z depth of the surface seen through each pixel centre."""
     d = world.device
     Kinv = torch.linalg.inv(torch.tensor(K, dtype=_DT, device=d))
     Rt = torch.tensor(R_m, dtype=_DT, device=d).T
     C = torch.tensor(C_m, dtype=_DT, device=d)
     img = torch.empty((h, w), dtype=_DT, device=d)
+    depth = torch.empty((h, w), dtype=_DT, device=d) if want_depth else None
+    Rm = torch.tensor(R_m, dtype=_DT, device=d)
     if chunk_rows is None:
         budget = 4_000_000 if str(d).startswith("cuda") else 1_000_000
         chunk_rows = max(1, int(budget // w))
@@ -370,6 +373,11 @@ def _render(world: _World, K, R_m, C_m, w, h, view_key, noise_sigma, seed, chunk
                 pid, hit = world.trace(C, dirs)
                 acc += world.shade(pid, hit).reshape(y1 - y0, w)
         img[y0:y1] = acc * 0.25
+        if want_depth:
+            Y, X = torch.meshgrid(ys, xs, indexing="ij")
+            dirs = _World._rays(Kinv, X, Y).reshape(-1, 3) @ Rt.T
+            _, hit = world.trace(C, dirs)
+            depth[y0:y1] = ((hit - C[None, :]) @ Rm.T)[:, 2].reshape(y1 - y0, w)
     # Gaussian noise from hash uniforms (Box-Muller), round half to even, clamp
     Y, X = torch.meshgrid(torch.arange(h, device=d, dtype=torch.int64),
                           torch.arange(w, device=d, dtype=torch.int64), indexing="ij")
@@ -378,7 +386,10 @@ def _render(world: _World, K, R_m, C_m, w, h, view_key, noise_sigma, seed, chunk
     g = torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * math.pi * u2)
     img = img + noise_sigma * g
     img = torch.round(img).clamp(0, 255)  # torch.round is half-to-even
-    return img.to(torch.uint8).cpu().numpy()
+    out = img.to(torch.uint8).cpu().numpy()
+    if want_depth:
+        return out, depth.cpu().numpy()
+    return out
 
 
 def _ground_truth(world: _World):
@@ -450,6 +461,92 @@ def crop_reference(scene: Scene, width: int, height: int) -> Scene:
                  scene.gt_normal[y0:y0 + height, x0:x0 + width].copy(),
                  scene.gt_plane[y0:y0 + height, x0:x0 + width].copy(),
                  scene.textured, scene.seed, meta=dict(scene.meta, crop=(x0, y0, width, height)))
+
+
+@dataclass
+class MultiViewScene:
+    """Many cameras around one scene; some of them are references with their own sources."""
+    images: List[np.ndarray]
+    cams: List[Camera]
+    depth_ranges: np.ndarray  # (n, 2) per camera
+    refs: List[int]
+    sources: List[List[int]]
+    windows: List[tuple]  # (window, dilation) per reference
+    seed: int = 0
+
+    @property
+    def K(self):
+        return np.stack([c.K for c in self.cams])
+
+    @property
+    def R(self):
+        return np.stack([c.R for c in self.cams])
+
+    @property
+    def t(self):
+        return np.stack([c.t for c in self.cams])
+
+
+#: reference size classes of the batched workload: (width, height, window, dilation)
+BATCH_CLASSES = [(3200, 2130, 31, 3), (1600, 1066, 21, 2), (960, 640, 11, 1)]
+
+
+def make_multiview_scene(seed: int = 4, grid=(5, 8), az_deg=20.0, el_deg=8.0, n_planes=30,
+                         textureless_frac=0.3, refs_per_class=8, classes=None, other_size=(1600, 1066),
+                         n_src_range=(6, 12), site_depth=(2.0, 12.0), device=None,
+                         master_size=(1600, 1066)) -> MultiViewScene:
+    """A grid of cameras (elevations x azimuths, all looking at the centre of the scene);
+    `refs_per_class` references per size class, each with 6-12 nearest cameras as sources.
+    Class windows keep 11x11 taps: 31x31 at dilation 3, 21x21 at 2, 11x11 at 1."""
+    device = _default_device(device)
+    classes = BATCH_CLASSES if classes is None else classes
+    mw, mh = master_size
+    K0 = _intrinsics(mw, mh)
+    ntl = int(round(textureless_frac * n_planes))
+    world = _World(seed, K0, mw, mh, n_planes, ntl, site_depth[0], site_depth[1], 50.0, device)
+    gt0, _, _ = _ground_truth(world)
+    dmed = float(np.median(gt0))
+    L = np.array([0.0, 0.0, dmed])
+    n_el, n_az = grid
+    rng = np.random.default_rng([seed, 0xB47C])
+    n_cams = n_el * n_az
+    n_refs = refs_per_class * len(classes)
+    order = rng.permutation(n_cams)
+    ref_ids = sorted(order[:n_refs].tolist())
+    sizes = {}
+    windows = {}
+    for k, cam in enumerate(ref_ids):
+        cls = classes[k % len(classes)]
+        sizes[cam] = (cls[0], cls[1])
+        windows[cam] = (cls[2], cls[3])
+    dirs = []
+    for ei, el in enumerate(np.linspace(-el_deg, el_deg, n_el)):
+        for ai, az in enumerate(np.linspace(-az_deg, az_deg, n_az)):
+            dirs.append((math.radians(az), math.radians(el)))
+    Q = _random_rotation(rng)
+    q = rng.uniform(-5, 5, 3)
+    images, cams, dranges = [], [], []
+    for ci, (az, el) in enumerate(dirs):
+        w, h = sizes.get(ci, other_size)
+        K = _intrinsics(w, h)
+        Rrot = _rot_y(az) @ _rot_x(el)           # camera axes in the master frame
+        Rm = Rrot.T
+        Cm = L + Rrot @ np.array([0.0, 0.0, -dmed])
+        img, dep = _render(world, K, Rm, Cm, w, h, ci, 2.0, seed, want_depth=True)
+        images.append(img)
+        good = np.isfinite(dep) & (dep > 0)
+        dranges.append((0.9 * float(dep[good].min()), 1.1 * float(dep[good].max())))
+        cams.append(Camera(K, Rm @ Q.T, -Rm @ (Q.T @ q + Cm), w, h))
+    # sources: the nearest cameras by viewing direction, 6-12 of them
+    centers = np.array([[math.sin(az) * math.cos(el), math.sin(el), math.cos(az) * math.cos(el)] for az, el in dirs])
+    sources, wins = [], []
+    for cam in ref_ids:
+        nsrc = int(rng.integers(n_src_range[0], n_src_range[1] + 1))
+        ang = np.arccos(np.clip(centers @ centers[cam], -1, 1))
+        ang[cam] = np.inf
+        sources.append(np.argsort(ang, kind="stable")[:nsrc].tolist())
+        wins.append(windows[cam])
+    return MultiViewScene(images, cams, np.array(dranges), ref_ids, sources, wins, seed)
 
 
 def workload_scene(name: str, device=None, seed: Optional[int] = None) -> Scene:
