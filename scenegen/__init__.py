@@ -148,6 +148,13 @@ class Scene:
 
 
 # ----------------------------------------------------------------------------- geometry helpers
+def _apply3(M: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """M (3x3) applied to points X (..., 3), written out (no BLAS call per chunk)."""
+    return torch.stack([M[0, 0] * X[..., 0] + M[0, 1] * X[..., 1] + M[0, 2] * X[..., 2],
+                        M[1, 0] * X[..., 0] + M[1, 1] * X[..., 1] + M[1, 2] * X[..., 2],
+                        M[2, 0] * X[..., 0] + M[2, 1] * X[..., 1] + M[2, 2] * X[..., 2]], -1)
+
+
 def _intrinsics(w: int, h: int) -> np.ndarray:
     f = 0.9 * w
     return np.array([[f, 0.0, (w - 1) / 2.0], [0.0, f, (h - 1) / 2.0], [0.0, 0.0, 1.0]])
@@ -276,7 +283,7 @@ class _World:
 
     def lookup_label(self, X):
         """Cell id of master-frame points X (..., 3) by projecting into the master view."""
-        p = X @ self.K0.T
+        p = _apply3(self.K0, X)
         px = p[..., 0] / p[..., 2]
         py = p[..., 1] / p[..., 2]
         ix = torch.nan_to_num(torch.round(px) - self.lx0, nan=0.0).clamp(0, self.lw - 1).long()
@@ -289,8 +296,9 @@ class _World:
         best_t = torch.full((m,), float("inf"), dtype=_DT, device=self.device)
         best_i = torch.full((m,), self.P, dtype=torch.long, device=self.device)
         for i in range(self.P):
-            den = dirs @ self.n[i]
-            num = self.offs[i] - origin @ self.n[i]
+            ni = self.n[i]
+            den = dirs[:, 0] * ni[0] + dirs[:, 1] * ni[1] + dirs[:, 2] * ni[2]
+            num = self.offs[i] - origin @ ni
             t = num / den
             hit = origin[None, :] + t[:, None] * dirs
             ok = (t > 1e-9) & (hit[:, 2] > 1e-9) & torch.isfinite(t)
@@ -300,7 +308,7 @@ class _World:
             best_i = torch.where(ok, torch.full_like(best_i, i), best_i)
         # backdrop for rays with no accepted piece
         nb = self.n[self.P]
-        tb = (self.offs[self.P] - origin @ nb) / (dirs @ nb)
+        tb = (self.offs[self.P] - origin @ nb) / (dirs[:, 0] * nb[0] + dirs[:, 1] * nb[1] + dirs[:, 2] * nb[2])
         none = best_i == self.P
         best_t = torch.where(none, tb, best_t)
         hit = origin[None, :] + best_t[:, None] * dirs
@@ -358,7 +366,7 @@ def _render(world: _World, K, R_m, C_m, w, h, view_key, noise_sigma, seed, chunk
     depth = torch.empty((h, w), dtype=_DT, device=d) if want_depth else None
     Rm = torch.tensor(R_m, dtype=_DT, device=d)
     if chunk_rows is None:
-        budget = 4_000_000 if str(d).startswith("cuda") else 1_000_000
+        budget = 16_000_000 if str(d).startswith("cuda") else 1_000_000
         chunk_rows = max(1, int(budget // w))
     xs = torch.arange(w, dtype=_DT, device=d)
     for y0 in range(0, h, chunk_rows):
@@ -369,15 +377,16 @@ def _render(world: _World, K, R_m, C_m, w, h, view_key, noise_sigma, seed, chunk
             for ox in (-0.25, 0.25):
                 Y, X = torch.meshgrid(ys + oy, xs + ox, indexing="ij")
                 rc = _World._rays(Kinv, X, Y).reshape(-1, 3)
-                dirs = rc @ Rt.T
+                dirs = _apply3(Rt, rc)
                 pid, hit = world.trace(C, dirs)
                 acc += world.shade(pid, hit).reshape(y1 - y0, w)
         img[y0:y1] = acc * 0.25
         if want_depth:
             Y, X = torch.meshgrid(ys, xs, indexing="ij")
-            dirs = _World._rays(Kinv, X, Y).reshape(-1, 3) @ Rt.T
+            dirs = _apply3(Rt, _World._rays(Kinv, X, Y).reshape(-1, 3))
             _, hit = world.trace(C, dirs)
-            depth[y0:y1] = ((hit - C[None, :]) @ Rm.T)[:, 2].reshape(y1 - y0, w)
+            rel = hit - C[None, :]
+            depth[y0:y1] = (rel[:, 0] * Rm[2, 0] + rel[:, 1] * Rm[2, 1] + rel[:, 2] * Rm[2, 2]).reshape(y1 - y0, w)
     # Gaussian noise from hash uniforms (Box-Muller), round half to even, clamp
     Y, X = torch.meshgrid(torch.arange(h, device=d, dtype=torch.int64),
                           torch.arange(w, device=d, dtype=torch.int64), indexing="ij")
