@@ -32,6 +32,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_file: str, profile: str):
+    """HBM bytes per launch of the evaluate kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration), or None
+    when the kernel source has changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
+        src = open(os.path.join(ROOT, "paper_2104_06165_amd", "csrc", kernel_file), "rb").read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(" "))
+    digest = fields.get("kernel_source_sha256", "").split()[0] if fields.get("kernel_source_sha256") else ""
+    if digest != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def nominal_tap_views(valid_px, n_src, taps, iters):
     # 1 initial hypothesis + per iteration 8 propagation + 3 refinement candidates
     return valid_px * (1 + 11 * iters) * n_src * taps
@@ -228,6 +248,7 @@ def main():
     flops_per_step = float(n_hyp) * n_src * taps * FLOPS_PER_TAP_VIEW
     avg_launch_ms = kernel_ms / launches
     achieved = flops_per_step / launches_per_step / (avg_launch_ms * 1e-3) / 1e12
+    traffic = measured_traffic("phimvs_kernels.hip", "eval_kernel_highres_hbm.md") if wl == "highres" else None
     depth, normal, cost = out
     d = depth.cpu().numpy()
     c = cost.cpu().numpy()
@@ -257,8 +278,9 @@ def main():
                    "dilation": solver["dilation"], "top_k": solver["top_k"], "iters": solver["iters"],
                    "planes": cfg.n_planes, "images": "fp16 in HBM", "cost": "fp32"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "kernel": "select_kernel (evaluate-and-select)", "avg_launch_ms": avg_launch_ms,
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "kernel": "eval_kernel (evaluate-and-select)", "avg_launch_ms": avg_launch_ms,
                      "launches_per_step": launches_per_step,
                      "kernel_share_of_step": kernel_ms / (elapsed * 1e3)},
         "hypotheses_per_step": n_hyp,
