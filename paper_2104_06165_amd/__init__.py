@@ -29,7 +29,12 @@ EXPORTS = ("phimvs_default_params", "phimvs_create", "phimvs_destroy", "phimvs_l
            "phimvs_sync", "phimvs_set_views", "phimvs_patchmatch", "phimvs_prepare", "phimvs_init_planes",
            "phimvs_step", "phimvs_get_state", "phimvs_set_state", "phimvs_output", "phimvs_eval_cost",
            "phimvs_patchmatch_batch", "phimvs_set_tuning", "phimvs_get_tuning", "phimvs_autotune",
-           "phimvs_diag_enable", "phimvs_diag_read", "phimvs_check_reciprocal")
+           "phimvs_diag_enable", "phimvs_diag_read", "phimvs_check_reciprocal",
+           # learned initial-plane proposal (include/phimvs_net.h)
+           "phimvs_net_create", "phimvs_net_destroy", "phimvs_net_last_error", "phimvs_net_set_stream",
+           "phimvs_net_param_count", "phimvs_net_set_params", "phimvs_net_get_params", "phimvs_net_forward",
+           "phimvs_net_loss_grad", "phimvs_net_adam", "phimvs_net_inputs", "phimvs_net_propose",
+           "phimvs_net_decode", "phimvs_net_targets", "phimvs_patchmatch_proposal")
 DIAG_COUNT = 1
 DIAG_TIME = 2
 
@@ -123,10 +128,30 @@ def lib():
         L.phimvs_diag_read.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
         L.phimvs_check_reciprocal.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64),
                                               C.POINTER(C.c_uint32)]
+        L.phimvs_net_create.argtypes = [C.POINTER(vp), ip, vp]
+        L.phimvs_net_destroy.argtypes = [vp]
+        L.phimvs_net_destroy.restype = None
+        L.phimvs_net_last_error.argtypes = [vp]
+        L.phimvs_net_last_error.restype = C.c_char_p
+        L.phimvs_net_set_stream.argtypes = [vp, vp]
+        L.phimvs_net_param_count.argtypes = []
+        L.phimvs_net_set_params.argtypes = [vp, fp, ip]
+        L.phimvs_net_get_params.argtypes = [vp, fp, ip]
+        L.phimvs_net_forward.argtypes = [vp, ip, ip, ip, fp, fp]
+        L.phimvs_net_loss_grad.argtypes = [vp, ip, ip, ip, fp, fp, fp, fp, C.c_float, dp, fp]
+        L.phimvs_net_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
+        L.phimvs_net_inputs.argtypes = [vp, vp, ip, C.POINTER(C.c_int), ip, fp]
+        L.phimvs_net_propose.argtypes = [vp, vp, ip, C.POINTER(C.c_int), ip, fp]
+        L.phimvs_net_decode.argtypes = [vp, vp, ip, fp, fp]
+        L.phimvs_net_targets.argtypes = [vp, ip, ip, fp, fp, fp, C.c_float, fp, fp]
+        L.phimvs_patchmatch_proposal.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip, ip, ip, C.POINTER(_Params),
+                                                 fp, fp, fp, fp, ip]
         for name in EXPORTS:
             f = getattr(L, name)
-            if name not in ("phimvs_default_params", "phimvs_destroy", "phimvs_last_error"):
+            if name not in ("phimvs_default_params", "phimvs_destroy", "phimvs_last_error", "phimvs_net_destroy",
+                            "phimvs_net_last_error"):
                 f.restype = C.c_int
+        L.phimvs_net_param_count.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -228,6 +253,57 @@ class Context:
         self._check(lib().phimvs_patchmatch(self.h, ref, sa, len(srcs), window, dilation, iters, C.byref(p),
                                             out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), 1))
         return out
+
+    def patchmatch_proposal(self, ref: int, srcs: Sequence[int], window: int, dilation: int, iters: int,
+                            proposal, params: Optional[Params] = None, out=None):
+        """``patchmatch`` with the random initialisation gated by proposal planes (H, W, 4) on the device."""
+        torch = self.torch
+        self._sync_stream()
+        H, W = self.views[ref] if 0 <= ref < len(self.views) else (1, 1)
+        if out is None:
+            out = (torch.empty((H, W), dtype=torch.float32, device=self.device),
+                   torch.empty((H, W, 3), dtype=torch.float32, device=self.device),
+                   torch.empty((H, W), dtype=torch.float32, device=self.device))
+        if proposal.dtype != torch.float32 or not proposal.is_contiguous() or proposal.numel() != H * W * 4:
+            raise ValueError("proposal must be a contiguous float32 (H, W, 4) tensor")
+        sa = (C.c_int * len(srcs))(*srcs)
+        p = (params or default_params())._c()
+        self._check(lib().phimvs_patchmatch_proposal(self.h, ref, sa, len(srcs), window, dilation, iters, C.byref(p),
+                                                     proposal.data_ptr(), out[0].data_ptr(), out[1].data_ptr(),
+                                                     out[2].data_ptr(), 1))
+        return out
+
+    # ------------------------------------------------------------------ learned proposal
+    def net_inputs(self, net: "Net", ref: int, srcs: Sequence[int]):
+        """Network input (h, w, 5) of reference ``ref``; h, w = ceil(H/4), ceil(W/4)."""
+        torch = self.torch
+        self._sync_stream()
+        net._sync_stream()
+        H, W = self.views[ref] if 0 <= ref < len(self.views) else (4, 4)
+        x = torch.empty(((H + 3) // 4, (W + 3) // 4, 5), dtype=torch.float32, device=self.device)
+        sa = (C.c_int * len(srcs))(*srcs)
+        self._check(lib().phimvs_net_inputs(self.h, net.h, ref, sa, len(srcs), x.data_ptr()))
+        return x
+
+    def net_decode(self, net: "Net", ref: int, output):
+        torch = self.torch
+        self._sync_stream()
+        H, W = self.views[ref] if 0 <= ref < len(self.views) else (1, 1)
+        if output.dtype != torch.float32 or not output.is_contiguous() or output.numel() != ((H + 3) // 4) * ((W + 3) // 4) * 4:
+            raise ValueError("output must be a contiguous float32 (ceil(H/4), ceil(W/4), 4) tensor")
+        planes = torch.empty((H, W, 4), dtype=torch.float32, device=self.device)
+        self._check(lib().phimvs_net_decode(self.h, net.h, ref, output.data_ptr(), planes.data_ptr()))
+        return planes
+
+    def propose(self, net: "Net", ref: int, srcs: Sequence[int], out=None):
+        """Proposal planes (H, W, 4) of reference ``ref`` from the network."""
+        torch = self.torch
+        self._sync_stream()
+        H, W = self.views[ref] if 0 <= ref < len(self.views) else (1, 1)
+        planes = out if out is not None else torch.empty((H, W, 4), dtype=torch.float32, device=self.device)
+        sa = (C.c_int * len(srcs))(*srcs)
+        self._check(lib().phimvs_net_propose(self.h, net.h, ref, sa, len(srcs), planes.data_ptr()))
+        return planes
 
     # ------------------------------------------------------------------ step-wise
     def prepare(self, ref: int, srcs: Sequence[int], window: int, dilation: int, params: Optional[Params] = None):
@@ -356,3 +432,116 @@ class Context:
         e = C.c_uint32()
         self._check(lib().phimvs_check_reciprocal(self.h, first_bits, count, C.byref(m), C.byref(e)))
         return int(m.value), int(e.value)
+
+
+class Net:
+    """The learned initial-plane proposal network (include/phimvs_net.h) on one GPU,
+    issuing work on torch's current stream."""
+
+    IN, OUT, WIDTH, LAYERS = 5, 4, 32, 5
+    #: (cin, cout) of each 3x3 convolution
+    SHAPES = ((5, 32), (32, 32), (32, 32), (32, 32), (32, 4))
+
+    def __init__(self, device: int = 0, params=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        torch.cuda.init()
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = lib().phimvs_net_create(C.byref(h), device, C.c_void_p(stream))
+        if rc != PHIMVS_OK:
+            raise PhimvsError(rc, "phimvs_net_create failed")
+        self.h = h
+        self.n_params = int(lib().phimvs_net_param_count())
+        if params is not None:
+            self.set_params(params)
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().phimvs_net_param_count())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().phimvs_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != PHIMVS_OK:
+            raise PhimvsError(rc, lib().phimvs_net_last_error(self.h).decode())
+
+    def _sync_stream(self):
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        self._check(lib().phimvs_net_set_stream(self.h, C.c_void_p(s)))
+
+    def set_params(self, params):
+        """params: flat float32 vector (numpy or a device tensor) in the layout of phimvs_net.h."""
+        self._sync_stream()
+        if isinstance(params, np.ndarray):
+            a = np.ascontiguousarray(params, dtype=np.float32)
+            if a.size != self.n_params:
+                raise ValueError(f"expected {self.n_params} parameters, got {a.size}")
+            self._check(lib().phimvs_net_set_params(self.h, a.ctypes.data, 0))
+        else:
+            if params.dtype != self.torch.float32 or not params.is_contiguous() or params.numel() != self.n_params:
+                raise ValueError("params must be a contiguous float32 tensor of param_count() values")
+            self._check(lib().phimvs_net_set_params(self.h, params.data_ptr(), 1))
+
+    def get_params(self) -> np.ndarray:
+        self._sync_stream()
+        a = np.empty(self.n_params, dtype=np.float32)
+        self._check(lib().phimvs_net_get_params(self.h, a.ctypes.data, 0))
+        return a
+
+    def forward(self, x):
+        """x: (B, h, w, 5) or (h, w, 5) float32 device tensor -> raw outputs (..., 4)."""
+        torch = self.torch
+        self._sync_stream()
+        xb = x if x.dim() == 4 else x.unsqueeze(0)
+        if xb.dtype != torch.float32 or xb.shape[-1] != self.IN:
+            raise ValueError("input must be float32 with 5 channels")
+        xb = xb.contiguous()
+        B, h, w, _ = xb.shape
+        out = torch.empty((B, h, w, self.OUT), dtype=torch.float32, device=self.device)
+        self._check(lib().phimvs_net_forward(self.h, B, h, w, xb.data_ptr(), out.data_ptr()))
+        return out if x.dim() == 4 else out[0]
+
+    def loss_grad(self, x, target, mask, depth_range, normal_weight: float = 1.0, want_loss: bool = True,
+                  want_grad: bool = False):
+        """Loss and parameter gradient (kept for ``adam``) -> (loss or None, grad tensor or None)."""
+        torch = self.torch
+        self._sync_stream()
+        B, h, w, _ = x.shape
+        for t, shape in ((x, (B, h, w, 5)), (target, (B, h, w, 4)), (mask, (B, h, w)), (depth_range, (B, 2))):
+            if t.dtype != torch.float32 or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"expected a contiguous float32 tensor of shape {shape}")
+        loss = C.c_double(0.0)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device) if want_grad else None
+        self._check(lib().phimvs_net_loss_grad(self.h, B, h, w, x.data_ptr(), target.data_ptr(), mask.data_ptr(),
+                                               depth_range.data_ptr(), float(normal_weight),
+                                               C.byref(loss) if want_loss else None, _dptr(grad)))
+        return (loss.value if want_loss else None), grad
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self._sync_stream()
+        self._check(lib().phimvs_net_adam(self.h, lr, beta1, beta2, eps))
+
+    def targets(self, depth, normal, cost, max_cost: float):
+        """Training targets (h, w, 4) and mask (h, w) from a full-resolution result."""
+        torch = self.torch
+        self._sync_stream()
+        H, W = depth.shape
+        h, w = (H + 3) // 4, (W + 3) // 4
+        tgt = torch.empty((h, w, 4), dtype=torch.float32, device=self.device)
+        mask = torch.empty((h, w), dtype=torch.float32, device=self.device)
+        self._check(lib().phimvs_net_targets(self.h, W, H, depth.contiguous().data_ptr(), normal.contiguous().data_ptr(),
+                                             cost.contiguous().data_ptr(), float(max_cost), tgt.data_ptr(),
+                                             mask.data_ptr()))
+        return tgt, mask

@@ -73,7 +73,7 @@ struct phimvs_ctx {
   Batch single;                   // the step-wise interface's job
   Batch multi;                    // phimvs_patchmatch_batch
   phimvs_tuning tuning{4, 0, 0, 0.0};
-  DevBuf<float> io_a, io_b, io_c;  // staging for host inputs / outputs
+  DevBuf<float> io_a, io_b, io_c, io_d;  // staging for host inputs / outputs
   DevBuf<uint8_t> io_u8;
   // diagnostics
   int diag = 0;
@@ -399,7 +399,9 @@ hipError_t run_eval(phimvs_ctx* c, Batch& b, Launch L, unsigned int* queue) {
 // the launch sequence of init + iters x (red, black) x (propagate, refine) (+ unpack);
 // each evaluate launch gets its own 8 queue counters from b.queues, zeroed first by a
 // kernel (no memset node, so the sequence replays correctly from a graph)
-int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack) {
+// with_proposal: the jobs carry proposal planes (planes_in) that compete with the random
+// initial plane (kept when not costlier)
+int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack, bool with_proposal = false) {
   const int n_eval = 2 + 4 * iters;
   if (b.queues.n < (size_t)8 * n_eval) return fail(c, PHIMVS_E_STATE, "queue counters not allocated");
   HIPCHECK(c, launch_zero(b.queues.p, 8 * n_eval, c->stream));
@@ -408,7 +410,7 @@ int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack) {
   for (int colour = 0; colour < 2; ++colour) {
     L.colour = colour;
     L.mode = 0;
-    L.ncand = 1;
+    L.ncand = with_proposal ? 2 : 1;
     HIPCHECK(c, launch_candidates(0, b.d_jobs, L, c->stream));
     HIPCHECK(c, run_eval(c, b, L, b.queues.p + 8 * q++));
   }
@@ -467,7 +469,80 @@ Problem make_problem(int ref, const int* srcs, int n_srcs, int window, int dilat
   return P;
 }
 
+// one depth map through the single-job batch: prepare, then the whole launch sequence;
+// proposal (planes layout, optional) gates the random initialisation
+int run_single(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, int dilation, int iters,
+               const phimvs_params* p, const float* proposal, float* depth, float* normal, float* cost,
+               int on_device) {
+  if (!c) return PHIMVS_E_ARG;
+  if (iters < 0) return fail(c, PHIMVS_E_ARG, "iters must be >= 0");
+  int rc = phimvs_prepare(c, ref, srcs, n_srcs, window, dilation, p);
+  if (rc) return rc;
+  Batch& b = c->single;
+  Job& J = b.jobs[0];
+  const size_t n = (size_t)J.A.W * J.A.H;
+  const float* prop = nullptr;
+  if (proposal) {
+    if (on_device) {
+      prop = proposal;
+    } else {
+      if ((rc = ensure(c, c->io_d, 4 * n))) return rc;
+      HIPCHECK(c, hipMemcpyAsync(c->io_d.p, proposal, 4 * n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+      prop = c->io_d.p;
+    }
+  }
+  if (on_device) {
+    J.depth_out = depth;
+    J.normal_out = normal;
+    J.final_cost_out = cost;
+  } else {
+    if ((rc = ensure(c, c->io_a, 3 * n)) || (rc = ensure(c, c->io_b, n)) || (rc = ensure(c, c->io_c, n))) return rc;
+    J.normal_out = normal ? c->io_a.p : nullptr;
+    J.depth_out = depth ? c->io_b.p : nullptr;
+    J.final_cost_out = cost ? c->io_c.p : nullptr;
+  }
+  J.planes_in = prop;
+  // the table is complete before the sequence starts, so the call does not wait for it
+  rc = upload_jobs(c, b);
+  J.planes_in = nullptr;  // the next upload drops the caller's pointer
+  if (rc) return rc;
+  if ((rc = ensure(c, b.queues, (size_t)8 * (2 + 4 * iters)))) return rc;
+  if ((rc = issue_sequence(c, b, iters, true, prop != nullptr))) return rc;
+  if (!on_device) {
+    if (normal) HIPCHECK(c, hipMemcpyAsync(normal, c->io_a.p, 3 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (depth) HIPCHECK(c, hipMemcpyAsync(depth, c->io_b.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    if (cost) HIPCHECK(c, hipMemcpyAsync(cost, c->io_c.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+  }
+  return PHIMVS_OK;
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------------------- internal accessors
+
+namespace phimvs_internal {
+
+int view_info(phimvs_ctx* c, int idx, ViewInfo* out) {
+  if (!c) return PHIMVS_E_ARG;
+  if (idx < 0 || idx >= (int)c->views.size()) return fail(c, PHIMVS_E_ARG, "view index out of range");
+  const ViewData& v = c->views[idx];
+  out->W = v.W;
+  out->H = v.H;
+  for (int i = 0; i < 9; ++i) out->K[i] = v.K[i], out->R[i] = v.R[i];
+  for (int i = 0; i < 3; ++i) out->t[i] = v.t[i];
+  out->d_lo = v.d_lo;
+  out->d_hi = v.d_hi;
+  out->plain = v.plain;
+  out->quad = v.quad;
+  return PHIMVS_OK;
+}
+
+int ctx_device(const phimvs_ctx* c) { return c->device; }
+hipStream_t ctx_stream(const phimvs_ctx* c) { return c->stream; }
+int ctx_fail(phimvs_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
+
+}  // namespace phimvs_internal
 
 extern "C" {
 
@@ -518,6 +593,7 @@ void phimvs_destroy(phimvs_ctx* c) {
   release(c->io_a);
   release(c->io_b);
   release(c->io_c);
+  release(c->io_d);
   release(c->io_u8);
   if (c->diag_count) (void)hipFree(c->diag_count);
   for (auto& e : c->diag_events) {
@@ -792,34 +868,15 @@ int phimvs_eval_cost(phimvs_ctx* c, const float* planes, float* cost, float* per
 
 int phimvs_patchmatch(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, int dilation, int iters,
                       const phimvs_params* p, float* depth, float* normal, float* cost, int out_on_device) {
+  return run_single(c, ref, srcs, n_srcs, window, dilation, iters, p, nullptr, depth, normal, cost, out_on_device);
+}
+
+int phimvs_patchmatch_proposal(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, int dilation,
+                               int iters, const phimvs_params* p, const float* proposal, float* depth, float* normal,
+                               float* cost, int on_device) {
   if (!c) return PHIMVS_E_ARG;
-  if (iters < 0) return fail(c, PHIMVS_E_ARG, "iters must be >= 0");
-  int rc = phimvs_prepare(c, ref, srcs, n_srcs, window, dilation, p);
-  if (rc) return rc;
-  Batch& b = c->single;
-  Job& J = b.jobs[0];
-  const size_t n = (size_t)J.A.W * J.A.H;
-  if (out_on_device) {
-    J.depth_out = depth;
-    J.normal_out = normal;
-    J.final_cost_out = cost;
-  } else {
-    if ((rc = ensure(c, c->io_a, 3 * n)) || (rc = ensure(c, c->io_b, n)) || (rc = ensure(c, c->io_c, n))) return rc;
-    J.normal_out = normal ? c->io_a.p : nullptr;
-    J.depth_out = depth ? c->io_b.p : nullptr;
-    J.final_cost_out = cost ? c->io_c.p : nullptr;
-  }
-  // the table is complete before the sequence starts, so the call does not wait for it
-  if ((rc = upload_jobs(c, b))) return rc;
-  if ((rc = ensure(c, b.queues, (size_t)8 * (2 + 4 * iters)))) return rc;
-  if ((rc = issue_sequence(c, b, iters, true))) return rc;
-  if (!out_on_device) {
-    if (normal) HIPCHECK(c, hipMemcpyAsync(normal, c->io_a.p, 3 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    if (depth) HIPCHECK(c, hipMemcpyAsync(depth, c->io_b.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    if (cost) HIPCHECK(c, hipMemcpyAsync(cost, c->io_c.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    HIPCHECK(c, hipStreamSynchronize(c->stream));
-  }
-  return PHIMVS_OK;
+  if (!proposal) return fail(c, PHIMVS_E_ARG, "proposal planes required");
+  return run_single(c, ref, srcs, n_srcs, window, dilation, iters, p, proposal, depth, normal, cost, on_device);
 }
 
 // ---------------------------------------------------------------------------- batches

@@ -84,4 +84,17 @@ hipError_t launch_build_view(const uint8_t* img, int64_t stride, int W, int H, _
 hipError_t launch_rcp_check(uint32_t first, uint32_t count, unsigned long long* mism, uint32_t* example,
                             hipStream_t st);
 
+// a view of a context's scene, for the proposal network's host code
+struct ViewInfo {
+  int W, H;
+  double K[9], R[9], t[3];
+  double d_lo, d_hi;
+  const __half* plain;     // grey values H*W
+  const uint32_t* quad;    // texel quads H*W
+};
+int view_info(phimvs_ctx* c, int idx, ViewInfo* out);
+int ctx_device(const phimvs_ctx* c);
+hipStream_t ctx_stream(const phimvs_ctx* c);
+int ctx_fail(phimvs_ctx* c, int code, const char* msg);
+
 }  // namespace phimvs_internal

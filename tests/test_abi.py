@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every entry point include/phimvs.h declares
+"""The C-ABI library loads and exports every entry point include/*.h declares
 (no GPU needed: only symbol lookup and the argument checks that fail before any HIP call)."""
 import ctypes
 import os
@@ -12,7 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "phimvs.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(phimvs_[a-z_]+)\s*\(", text)))
 
@@ -45,3 +46,8 @@ def test_default_params_and_null_context_errors():
     out = ctypes.c_void_p()
     rc = L.phimvs_create(ctypes.byref(out), -1, None)
     assert rc in (-3,)  # no such device
+    assert L.phimvs_net_param_count() == 9 * 5 * 32 + 32 + 3 * (9 * 32 * 32 + 32) + 9 * 32 * 4 + 4
+    assert L.phimvs_net_forward(None, 1, 4, 4, None, None) == -1
+    assert L.phimvs_net_adam(None, 1e-3, 0.9, 0.999, 1e-8) == -1
+    assert L.phimvs_net_last_error(None) == b"null network"
+    assert L.phimvs_net_create(ctypes.byref(out), -1, None) == -3

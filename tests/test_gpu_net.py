@@ -1,0 +1,287 @@
+"""GPU parity of the learned initial-plane proposal: every kernel of the network
+(forward, loss and gradients, Adam, input builder, decode, training targets) through the
+C ABI against the float64 oracle in ``oracle/cnn.py``, and the gated initialisation and
+the proposal-seeded search against the PatchMatch oracle.
+
+Tolerances: the GPU stores weights, activations and back-propagated gradients in
+bfloat16 and accumulates in FP32; the oracle is run with the same roundings
+(``like_gpu``), so what remains is FP32 summation order (relative ~1e-6) plus the rare
+activation whose bfloat16 rounding flips by one unit (2^-8 relative) because of it."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2104_06165_amd as pm  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rand_params(seed, scale=1.0):
+    r = np.random.default_rng(seed)
+    layers = [(r.normal(0, scale * np.sqrt(2.0 / (9 * ci)), (9, ci, co)), r.normal(0, 0.1, co))
+              for ci, co in cnn.SHAPES]
+    return cnn.pack(layers).astype(np.float32)
+
+
+def rand_batch(seed, B, h, w):
+    r = np.random.default_rng(seed)
+    x = r.normal(0, 1, (B, h, w, 5)).astype(np.float32)
+    drange = np.tile(np.array([[1.5, 9.0]], np.float32), (B, 1))
+    drange[-1] = [2.0, 5.0]
+    lo, hi = drange[:, :1, None], drange[:, 1:, None]
+    tgt = np.zeros((B, h, w, 4), np.float32)
+    tgt[..., 0] = (lo + (hi - lo) * r.uniform(0.05, 0.95, (B, h, w))).astype(np.float32)
+    n = r.normal(size=(B, h, w, 3))
+    n[..., 2] = -np.abs(n[..., 2]) - 0.3
+    tgt[..., 1:] = (n / np.linalg.norm(n, axis=-1, keepdims=True)).astype(np.float32)
+    mask = (r.uniform(size=(B, h, w)) < 0.85).astype(np.float32)
+    return x, tgt, mask, drange
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def net():
+    n = pm.Net(0)
+    yield n
+    n.close()
+
+
+@pytest.mark.parametrize("B,h,w", [(1, 5, 7), (2, 21, 37), (1, 34, 16), (3, 1, 1), (1, 40, 100)])
+def test_forward_parity(net, B, h, w):
+    """Ragged sizes: columns not a multiple of the 16-pixel fragment, single pixel, one row."""
+    p = rand_params(1 + h)
+    x, *_ = rand_batch(2 + w, B, h, w)
+    net.set_params(p)
+    out = net.forward(dev(x)).cpu().numpy()
+    ref, _ = cnn.forward(p.astype(np.float64), x, like_gpu=True)
+    err = np.abs(out - ref)
+    scale = np.abs(ref).max()
+    say(f"forward {B}x{h}x{w}: max|ref| {scale:.3g}, max err {err.max():.3g}, mean err {err.mean():.3g}")
+    # FP32 summation order alone gives ~1e-7; an activation whose bfloat16 rounding flips
+    # (probability ~1e-4 each) moves the outputs of its receptive field by about one
+    # bfloat16 unit (2^-8) times the downstream gain
+    assert err.max() <= 2e-2 * scale + 1e-6
+    assert err.mean() <= 1e-4 * scale + 1e-7
+    assert (err <= 1e-5 * scale + 1e-6).mean() >= 0.95
+    assert (err <= 2 ** -8 * scale).mean() >= 0.999
+
+
+def test_forward_zero_params_gives_zero(net):
+    net.set_params(np.zeros(net.n_params, np.float32))
+    x, *_ = rand_batch(3, 2, 9, 11)
+    assert torch.count_nonzero(net.forward(dev(x))).item() == 0
+
+
+@pytest.mark.parametrize("B,h,w", [(2, 13, 21), (1, 32, 48)])
+def test_loss_and_gradient_parity(net, B, h, w):
+    p = rand_params(10 + B)
+    x, tgt, mask, drange = rand_batch(11 + B, B, h, w)
+    net.set_params(p)
+    loss, g = net.loss_grad(dev(x), dev(tgt), dev(mask), dev(drange), normal_weight=0.5, want_grad=True)
+    g = g.cpu().numpy().astype(np.float64)
+    rl, rg = cnn.loss_grad(p.astype(np.float64), x.astype(np.float64), tgt.astype(np.float64),
+                           mask.astype(np.float64), drange.astype(np.float64), 0.5, like_gpu=True)
+    say(f"loss gpu {loss:.8g} oracle {rl:.8g}")
+    assert abs(loss - rl) <= 1e-4 * abs(rl) + 1e-7
+    offs = np.cumsum([0] + [9 * ci * co + co for ci, co in cnn.SHAPES])
+    for l in range(5):
+        a, b = g[offs[l]:offs[l + 1]], rg[offs[l]:offs[l + 1]]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        say(f"  layer {l + 1}: |grad| {np.linalg.norm(b):.4g}, relative error {rel:.3g}")
+        assert rel <= 1e-2
+    # and against the pure float64 gradient (no bfloat16 anywhere): the price of the storage format
+    _, g64 = cnn.loss_grad(p.astype(np.float64), x, tgt, mask, drange, 0.5)
+    rel64 = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    say(f"  whole gradient vs float64 oracle (no bf16): relative error {rel64:.3g}")
+    assert rel64 <= 0.1
+
+
+def test_adam_steps_match_the_oracle(net):
+    p = rand_params(20)
+    x, tgt, mask, drange = rand_batch(21, 2, 9, 17)
+    net.set_params(p)
+    cur = p.astype(np.float64)
+    m = np.zeros_like(cur)
+    v = np.zeros_like(cur)
+    for t in (1, 2, 3):
+        _, g = net.loss_grad(dev(x), dev(tgt), dev(mask), dev(drange), want_loss=False, want_grad=True)
+        g = g.cpu().numpy().astype(np.float64)
+        net.adam(1e-3, 0.9, 0.999, 1e-8)
+        cur, m, v = cnn.adam(cur, g, m, v, t, 1e-3, 0.9, 0.999, 1e-8)
+        got = net.get_params().astype(np.float64)
+        err = np.abs(got - cur).max()
+        say(f"adam step {t}: max |param - oracle| {err:.3g}")
+        assert err <= 1e-6 * max(1.0, np.abs(cur).max())
+        cur = got  # continue from the GPU's FP32 weights
+
+
+def test_training_reduces_the_loss(net):
+    p = rand_params(30, scale=0.5)
+    x, tgt, mask, drange = rand_batch(31, 4, 16, 24)
+    net.set_params(p)
+    X, T, M, D = dev(x), dev(tgt), dev(mask), dev(drange)
+    first, _ = net.loss_grad(X, T, M, D)
+    for _ in range(60):
+        net.loss_grad(X, T, M, D, want_loss=False)
+        net.adam(3e-3)
+    last, _ = net.loss_grad(X, T, M, D)
+    say(f"loss {first:.5f} -> {last:.5f} after 60 Adam steps")
+    assert last < 0.7 * first
+
+
+def test_net_argument_errors(net):
+    x, tgt, mask, drange = rand_batch(40, 1, 4, 4)
+    with pytest.raises(ValueError):
+        net.set_params(np.zeros(5, np.float32))
+    fresh = pm.Net(0)
+    try:
+        with pytest.raises(pm.PhimvsError):
+            fresh.adam(1e-3)  # no gradient yet
+    finally:
+        fresh.close()
+    with pytest.raises(pm.PhimvsError):
+        net.loss_grad(dev(x), dev(tgt), dev(mask), dev(drange), normal_weight=-1.0)
+
+
+# ----------------------------------------------------------------------------- proposal path
+@pytest.fixture(scope="module")
+def tiny():
+    return sg.workload_scene("tiny", device="cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx(tiny):
+    c = pm.Context(0)
+    c.set_scene(tiny)
+    yield c
+    c.close()
+
+
+def test_proposal_inputs_parity(ctx, net, tiny):
+    srcs = list(range(1, len(tiny.images)))
+    x = ctx.net_inputs(net, 0, srcs).cpu().numpy()
+    n = len(tiny.images)
+    ref = cnn.proposal_inputs([im.astype(np.float64) for im in tiny.images], tiny.K, tiny.R, tiny.t,
+                              tiny.depth_range, 0, srcs)
+    assert x.shape == ref.shape == (30, 40, 5)
+    err = np.abs(x - ref)
+    close = err <= 5e-4
+    say(f"proposal inputs: {close.mean():.6f} within 5e-4, max err {err.max():.3g} (views {n})")
+    assert close[..., 0].all()
+    assert close.mean() >= 0.999  # a sample exactly on a source border may fall either side
+
+
+def test_decode_parity(ctx, net, tiny):
+    H, W = tiny.images[0].shape
+    r = np.random.default_rng(50)
+    out = r.normal(0, 1.5, ((H + 3) // 4, (W + 3) // 4, 4)).astype(np.float32)
+    planes = ctx.net_decode(net, 0, dev(out)).cpu().numpy()
+    ref = cnn.decode(out.astype(np.float64), tiny.K[0], tiny.depth_range, H, W)
+    derr = np.abs(planes[..., 3] - ref[..., 3]) / ref[..., 3]
+    nerr = np.abs(planes[..., :3] - ref[..., :3]).max(-1)
+    say(f"decode: depth max rel err {derr.max():.3g}, normal max err {np.sort(nerr)[-5:]}")
+    assert derr.max() <= 1e-5
+    assert (nerr <= 1e-5).mean() >= 0.999  # a normal almost perpendicular to its ray may flip
+    assert np.allclose(np.linalg.norm(planes[..., :3], axis=-1), 1.0, atol=1e-5)
+
+
+def test_targets_parity(ctx, net, tiny):
+    srcs = list(range(1, len(tiny.images)))
+    d, n, c = ctx.patchmatch(0, srcs, 11, 1, 3, pm.Params(top_k=len(srcs), sigma_spatial_px=5.0))
+    tgt, mask = net.targets(d, n, c, 0.4)
+    rt, rm = cnn.targets(d.cpu().numpy(), n.cpu().numpy(), c.cpu().numpy(), 0.4)
+    assert np.array_equal(mask.cpu().numpy(), rm)
+    keep = rm > 0
+    say(f"targets: {keep.mean():.3f} of blocks kept")
+    assert keep.mean() > 0.2
+    np.testing.assert_allclose(tgt.cpu().numpy()[keep], rt[keep], rtol=1e-5, atol=1e-6)
+
+
+def _oracle_problem(scene, top_k):
+    return oracle.Problem.from_scene(scene, 11, 1, top_k=top_k, bilateral=True, sigma_s=5.0, sigma_c=12.0,
+                                     seed=0x5EED)
+
+
+def _proposal(ctx, net, scene):
+    net.set_params(rand_params(60, scale=0.7))
+    srcs = list(range(1, len(scene.images)))
+    return ctx.propose(net, 0, srcs), srcs
+
+
+def test_propose_equals_its_stages(ctx, net, tiny):
+    planes, srcs = _proposal(ctx, net, tiny)
+    staged = ctx.net_decode(net, 0, net.forward(ctx.net_inputs(net, 0, srcs)).contiguous())
+    assert torch.equal(planes, staged)
+
+
+def test_gated_initialisation_parity(ctx, net, tiny):
+    """Each pixel keeps the proposal iff its cost is not higher than the random plane's;
+    the result equals the oracle's random initialisation gated the same way."""
+    planes, srcs = _proposal(ctx, net, tiny)
+    params = pm.Params(top_k=len(srcs), sigma_spatial_px=5.0)
+    ctx.prepare(0, srcs, 11, 1, params)
+    ctx.init_planes()
+    rp, rc = [t.cpu().numpy() for t in ctx.get_state()]
+    ctx.init_planes(planes)
+    gp, gc = [t.cpu().numpy() for t in ctx.get_state()]
+    pb = _oracle_problem(tiny, len(srcs))
+    m = pb.valid_mask()
+    assert np.all(gc[m] <= rc[m])  # the gate never raises the initial cost
+    op, oc = oracle.init(pb)
+    pc, _, _ = oracle.eval_cost(pb, planes.cpu().numpy().astype(np.float64))
+    take = pc <= oc
+    exp_c = np.where(take, pc, oc)
+    exp_p = np.where(take[..., None], planes.cpu().numpy(), op)
+    bit = (gc[m] == exp_c[m].astype(np.float32)).mean()
+    same_plane = np.all(gp[m] == exp_p[m].astype(np.float32), axis=-1).mean()
+    say(f"gated init: proposal kept on {take[m].mean():.3f} of pixels; cost bitwise {bit:.6f}, planes {same_plane:.6f}")
+    assert bit >= 0.999 and same_plane >= 0.999
+
+
+def test_patchmatch_with_proposal_parity(ctx, net, tiny):
+    planes, srcs = _proposal(ctx, net, tiny)
+    params = pm.Params(top_k=len(srcs), sigma_spatial_px=5.0)
+    iters = 2
+    d, n, c = ctx.patchmatch_proposal(0, srcs, 11, 1, iters, planes, params)
+    pb = _oracle_problem(tiny, len(srcs))
+    op, oc = oracle.init(pb)
+    pc, _, _ = oracle.eval_cost(pb, planes.cpu().numpy().astype(np.float64))
+    take = pc <= oc
+    P = np.where(take[..., None], planes.cpu().numpy().astype(np.float64), op)
+    Cc = np.where(take, pc, oc)
+    for it in range(1, iters + 1):
+        for colour in (0, 1):
+            P, Cc = oracle.halfsweep(pb, P, Cc, it, colour)
+    m = pb.valid_mask()
+    gc, gd = c.cpu().numpy(), d.cpu().numpy()
+    ok = (np.abs(gc - Cc) <= 1e-4) & (np.abs(gd - P[..., 3]) <= 1e-3 * P[..., 3])
+    say(f"patchmatch with proposal vs oracle: {ok[m].mean():.6f} within tolerance, "
+        f"cost bitwise {(gc[m] == Cc[m].astype(np.float32)).mean():.6f}")
+    assert ok[m].mean() >= 0.999
+
+
+def test_proposal_argument_errors(ctx, net, tiny):
+    H, W = tiny.images[0].shape
+    with pytest.raises(ValueError):
+        ctx.patchmatch_proposal(0, [1, 2], 11, 1, 1, torch.zeros((H, W, 3), device="cuda"))
+    with pytest.raises(pm.PhimvsError):
+        ctx.propose(net, 9, [1, 2])
+    with pytest.raises(pm.PhimvsError):
+        ctx.net_inputs(net, 0, [0, 1])  # reference among its sources
