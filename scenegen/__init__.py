@@ -342,9 +342,16 @@ class _World:
         fv = v - j0
         i0 = i0.long()
         j0 = j0.long()
+        # _mix(seed, pid, octave, i, j) with the shared stages hashed once: the
+        # (seed, pid, octave) prefix per plane, the i and j stages per lattice line
+        planes = torch.arange(int(pid.max().item()) + 1 if pid.numel() else 1, device=pid.device)
+        prefix = _mix(self.seed, planes, octave)[pid]
+        hi = [_hash32(((i0 + di) & M32) + 0x632BE5AB) for di in (0, 1)]
+        hj = [_hash32(((j0 + dj) & M32) + 0x632BE5AB) for dj in (0, 1)]
+        row = [_hash32(prefix ^ h) for h in hi]
 
         def lat(di, dj):
-            return _unit(_mix(self.seed, pid, octave, i0 + di, j0 + dj))
+            return _unit(_hash32(row[di] ^ hj[dj]))
 
         def fade(t):
             return t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
