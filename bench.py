@@ -162,6 +162,71 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, random_ms, reps=3):
+    """Learned-proposal initialisation against random initialisation at equal final cost:
+    the mean cost (valid pixels) after k = 0..iters iterations of both, the fewest
+    iterations at which the learned run reaches the random run's final mean cost within
+    1%, and the end-to-end time of that run (proposal network included) against the
+    random run's full time."""
+    import torch
+
+    iters = solver["iters"]
+    win, dil = solver["window"], solver["dilation"]
+    gt = scene.gt_depth
+
+    def stats(d, c):
+        d = d.cpu().numpy()
+        c = c.cpu().numpy()
+        rel = np.abs(d - gt) / gt
+        return {"mean_cost": float(c[valid].mean()),
+                "depth_within_1pct": float((rel[valid] < 0.01).mean()),
+                "depth_within_1pct_textured": float((rel[valid & textured] < 0.01).mean()),
+                "mean_abs_rel_depth_error": float(rel[valid].mean())}
+
+    rand, learned = [], []
+    for k in range(iters + 1):
+        d, n, c = ctx.patchmatch(0, srcs, win, dil, k, params)
+        rand.append(stats(d, c))
+    proposal = ctx.propose(net, 0, srcs)
+    for k in range(iters + 1):
+        d, n, c = ctx.patchmatch_proposal(0, srcs, win, dil, k, proposal, params)
+        learned.append(stats(d, c))
+    # pixels whose initial plane is the proposal: the gated initial cost is below the random one's
+    c_rand0 = ctx.patchmatch(0, srcs, win, dil, 0, params)[2]
+    c_learn0 = ctx.patchmatch_proposal(0, srcs, win, dil, 0, proposal, params)[2]
+    vt = torch.from_numpy(valid).to(c_rand0.device)
+    kept = float(((c_learn0 < c_rand0) & vt).sum().item() / max(int(vt.sum().item()), 1))
+    target = 1.01 * rand[iters]["mean_cost"]
+    k_rand = next(k for k in range(iters + 1) if rand[k]["mean_cost"] <= target)
+    k_learned = next((k for k in range(iters + 1) if learned[k]["mean_cost"] <= target), None)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    out = {"target_mean_cost": target, "random_iters_to_target": k_rand, "learned_iters_to_target": k_learned,
+           "random_ms": random_ms, "proposal_kept_fraction": kept,
+           "per_iteration": {"random": rand, "learned": learned}}
+    out["proposal_ms"] = timed(lambda: ctx.propose(net, 0, srcs, out=proposal))
+    if k_learned is not None:
+        def run():
+            ctx.propose(net, 0, srcs, out=proposal)
+            ctx.patchmatch_proposal(0, srcs, win, dil, k_learned, proposal, params)
+        out["learned_ms"] = timed(run)
+        out["speedup"] = random_ms / out["learned_ms"]
+        # the same comparison against the random run stopped as soon as it reaches the target
+        out["random_ms_at_target"] = timed(lambda: ctx.patchmatch(0, srcs, win, dil, k_rand, params))
+        out["speedup_at_equal_cost"] = out["random_ms_at_target"] / out["learned_ms"]
+        out["learned_at_target"] = learned[k_learned]
+        out["random_final"] = rand[iters]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +235,9 @@ def main():
     ap.add_argument("--workload", default="highres", choices=["highres", "mid", "mid_dense", "tiny", "batched"])
     ap.add_argument("--cpu-iters", type=int, default=1, help="iterations of the oracle's bounded sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy"),
+                    help="parameters of the proposal network for the learned-versus-random comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-versus-random comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration) and exit")
     args = ap.parse_args()
@@ -290,6 +358,18 @@ def main():
                     "depth_within_1pct": float((rel[valid] < 0.01).mean()),
                     "depth_within_1pct_textured": float((rel[valid & textured] < 0.01).mean())},
     }
+    if not args.no_learned and wl == "highres" and os.path.exists(args.weights):
+        log("[bench] learned proposal versus random initialisation")
+        net = pm.Net(0, np.load(args.weights))
+        lv = learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, ms_per_step)
+        line["learned_vs_random"] = {k: v for k, v in lv.items() if k != "per_iteration"}
+        line["learned_vs_random"]["weights"] = os.path.relpath(args.weights, ROOT)
+        for key in ("mean_cost", "depth_within_1pct", "mean_abs_rel_depth_error"):
+            line["learned_vs_random"][key + "_per_iteration"] = {
+                "random": [r[key] for r in lv["per_iteration"]["random"]],
+                "learned": [r[key] for r in lv["per_iteration"]["learned"]]}
+        log("[bench] " + json.dumps(line["learned_vs_random"]))
+        net.close()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on its bounded sample")
         line["cpu_baseline"] = cpu_baseline(scene, solver, args.cpu_iters)

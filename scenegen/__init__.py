@@ -98,6 +98,8 @@ CONFIGS = {
     "mid": SceneConfig(1600, 1066, 9, 12, 0.30, 2.0, 8.0),
     # 1 ref + 10 sources, 3200x2130, 25 planes (35% texture-less), depth 1-20 m
     "highres": SceneConfig(3200, 2130, 10, 25, 0.35, 1.0, 20.0),
+    # training scenes of the learned proposal: the high-resolution recipe at 1600x1066
+    "proposal_train": SceneConfig(1600, 1066, 10, 25, 0.35, 1.0, 20.0),
 }
 
 #: window side, dilation, top-K, iterations per workload
@@ -106,9 +108,12 @@ SOLVER = {
     "mid": dict(window=21, dilation=2, top_k=4, iters=8),
     "mid_dense": dict(window=21, dilation=1, top_k=4, iters=8),
     "highres": dict(window=31, dilation=3, top_k=5, iters=8),
+    "proposal_train": dict(window=21, dilation=2, top_k=5, iters=8),
 }
 
 SCENE_SEEDS = {"tiny": 1, "mid": 2, "highres": 3, "batched": 4}
+#: seeds of the proposal network's training scenes (disjoint from the workloads above)
+PROPOSAL_TRAIN_SEEDS = range(100000, 102000)
 PM_SEED = 0x5EED
 
 
@@ -374,19 +379,21 @@ def _render(world: _World, K, R_m, C_m, w, h, view_key, noise_sigma, seed, chunk
     Rm = torch.tensor(R_m, dtype=_DT, device=d)
     if chunk_rows is None:
         budget = 16_000_000 if str(d).startswith("cuda") else 1_000_000
-        chunk_rows = max(1, int(budget // w))
+        chunk_rows = max(1, int(budget // (4 * w)))
     xs = torch.arange(w, dtype=_DT, device=d)
+    offsets = ((-0.25, -0.25), (-0.25, 0.25), (0.25, -0.25), (0.25, 0.25))  # (oy, ox)
     for y0 in range(0, h, chunk_rows):
         y1 = min(h, y0 + chunk_rows)
         ys = torch.arange(y0, y1, dtype=_DT, device=d)
+        # the four sub-pixel samples of every pixel of the chunk in one pass
+        Y = torch.stack([torch.meshgrid(ys + oy, xs + ox, indexing="ij")[0] for oy, ox in offsets])
+        X = torch.stack([torch.meshgrid(ys + oy, xs + ox, indexing="ij")[1] for oy, ox in offsets])
+        dirs = _apply3(Rt, _World._rays(Kinv, X, Y).reshape(-1, 3))
+        pid, hit = world.trace(C, dirs)
+        sub = world.shade(pid, hit).reshape(4, y1 - y0, w)
         acc = torch.zeros((y1 - y0, w), dtype=_DT, device=d)
-        for oy in (-0.25, 0.25):
-            for ox in (-0.25, 0.25):
-                Y, X = torch.meshgrid(ys + oy, xs + ox, indexing="ij")
-                rc = _World._rays(Kinv, X, Y).reshape(-1, 3)
-                dirs = _apply3(Rt, rc)
-                pid, hit = world.trace(C, dirs)
-                acc += world.shade(pid, hit).reshape(y1 - y0, w)
+        for k in range(4):
+            acc += sub[k]
         img[y0:y1] = acc * 0.25
         if want_depth:
             Y, X = torch.meshgrid(ys, xs, indexing="ij")
