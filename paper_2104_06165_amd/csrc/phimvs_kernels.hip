@@ -162,16 +162,21 @@ struct Hyp {
 };
 
 // Sums of a group of G views (J0, J0 + 1, ...) over the window taps in row-major order.
-// EXACT selects IEEE division for 1/w.
+// EXACT selects IEEE division for 1/w.  The loop is software-pipelined by one tap with
+// two alternating register sets: the texel loads of tap t + 1 are issued before tap t's
+// texels are interpolated and accumulated, so each gather's latency overlaps a tap of
+// arithmetic.  Every tap's arithmetic and the order of accumulation are unchanged.  The
+// weight tables hold 1.0 when the weights are off, so w = 1 exactly then.
 template <int G, bool EXACT>
 __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp, const float* __restrict__ tile,
                                          int TW, const float* __restrict__ wcol, const float* __restrict__ wsp,
                                          const float (&Hm)[G][9], const float (&bc)[G], float (&Sb)[G],
                                          float (&Sbb)[G], float (&Sab)[G]) {
   const int R = A.R, s = A.s;
-  const float sf = (float)s;
+  const int n = 2 * R + 1;
+  const int T = n * n;
   const uint32_t* quad[G];
-  int Wq[G];
+  uint32_t Wq[G];
   float Wm1[G], Hm1[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -179,45 +184,90 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
     Sbb[g] = 0.0f;
     Sab[g] = 0.0f;
     quad[g] = A.src[J0 + g].quad;
-    Wq[g] = A.src[J0 + g].W;
+    Wq[g] = (uint32_t)A.src[J0 + g].W;
     Wm1[g] = A.src[J0 + g].Wm1;
     Hm1[g] = A.src[J0 + g].Hm1;
   }
-  const bool bil = A.bilateral != 0;
-  int t = 0;
-  for (int k2 = -R; k2 <= R; ++k2) {
-    const float Y = (float)(rp.y + s * k2);
-    float rbu[G], rbv[G], rbw[G];
+
+  // bases of the row being issued: (H[1] Y + H[2], H[4] Y + H[5], H[7] Y + H[8])
+  float rbu[G], rbv[G], rbw[G];
+  auto row_bases = [&](int k2) {
+    const float Y = (float)(rp.y + s * (k2 - R));
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       rbu[g] = __builtin_fmaf(Hm[g][1], Y, Hm[g][2]);
       rbv[g] = __builtin_fmaf(Hm[g][4], Y, Hm[g][5]);
       rbw[g] = __builtin_fmaf(Hm[g][7], Y, Hm[g][8]);
     }
-    const float* trow = tile + rp.tbase + (k2 + R) * s * TW;
-    float X = (float)(rp.x - s * R);
-    for (int k1 = 0; k1 <= 2 * R; ++k1, ++t) {
-      const float a = trow[k1 * s] - rp.a_c;
-      float w = 1.0f;
-      if (bil) w = wcol[(int)fabsf(a)] * wsp[t];
-      const float wa = w * a;
+  };
+  // warp column k1 of the row whose bases are loaded and issue its texel loads
+  auto issue = [&](int k1, uint32_t (&qo)[G], float (&fxo)[G], float (&fyo)[G]) {
+    const float X = (float)(rp.x + s * (k1 - R));
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const float u = __builtin_fmaf(Hm[g][0], X, rbu[g]);
-        const float v = __builtin_fmaf(Hm[g][3], X, rbv[g]);
-        const float ww = __builtin_fmaf(Hm[g][6], X, rbw[g]);
-        const float r = EXACT ? 1.0f / ww : rcp_nr(ww);
-        const float up = clampf(u * r, Wm1[g]);
-        const float vp = clampf(v * r, Hm1[g]);
-        const float b = sample_quad(quad[g], Wq[g], up, vp) - bc[g];
-        const float tb = w * b;
-        Sb[g] = Sb[g] + tb;
-        Sbb[g] = __builtin_fmaf(tb, b, Sbb[g]);
-        Sab[g] = __builtin_fmaf(wa, b, Sab[g]);
-      }
-      X = X + sf;
+    for (int g = 0; g < G; ++g) {
+      const float u = __builtin_fmaf(Hm[g][0], X, rbu[g]);
+      const float v = __builtin_fmaf(Hm[g][3], X, rbv[g]);
+      const float ww = __builtin_fmaf(Hm[g][6], X, rbw[g]);
+      const float r = EXACT ? 1.0f / ww : rcp_nr(ww);
+      const float up = clampf(u * r, Wm1[g]);
+      const float vp = clampf(v * r, Hm1[g]);
+      // up, vp >= 0: fract(u) = u - floor(u) exactly
+      fxo[g] = __builtin_amdgcn_fractf(up);
+      fyo[g] = __builtin_amdgcn_fractf(vp);
+      const uint32_t x0 = (uint32_t)up, y0 = (uint32_t)vp;
+      qo[g] = gl(quad[g])[__umul24(y0, Wq[g]) + x0];
     }
+  };
+  // interpolate and accumulate tap (row trow, column k1, index t)
+  auto process = [&](const float* trow, int k1, int t, const uint32_t (&qi)[G], const float (&fxi)[G],
+                     const float (&fyi)[G]) {
+    const float a = trow[k1 * s] - rp.a_c;
+    const float w = wcol[(int)fabsf(a)] * wsp[t];
+    const float wa = w * a;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const float t00 = (float)(qi[g] & 0xFFu), t01 = (float)((qi[g] >> 8) & 0xFFu);
+      const float t10 = (float)((qi[g] >> 16) & 0xFFu), t11 = (float)(qi[g] >> 24);
+      const float top = __builtin_fmaf(fxi[g], t01 - t00, t00);
+      const float bot = __builtin_fmaf(fxi[g], t11 - t10, t10);
+      const float b = __builtin_fmaf(fyi[g], bot - top, top) - bc[g];
+      const float tb = w * b;
+      Sb[g] = Sb[g] + tb;
+      Sbb[g] = __builtin_fmaf(tb, b, Sbb[g]);
+      Sab[g] = __builtin_fmaf(wa, b, Sab[g]);
+    }
+  };
+  // one row: column 0 is in flight in (QA); columns alternate between the two register
+  // sets (n is odd, so the last column lands in QA again); the next row's column 0 is
+  // issued into QB before the last column is processed
+  auto row = [&](int k2, uint32_t (&qA)[G], float (&fxA)[G], float (&fyA)[G], uint32_t (&qB)[G], float (&fxB)[G],
+                 float (&fyB)[G]) {
+    const float* trow = tile + rp.tbase + k2 * s * TW;
+    const int t0 = k2 * n;
+    for (int c = 0; c + 1 < n; c += 2) {
+      issue(c + 1, qB, fxB, fyB);
+      process(trow, c, t0 + c, qA, fxA, fyA);
+      issue(c + 2, qA, fxA, fyA);
+      process(trow, c + 1, t0 + c + 1, qB, fxB, fyB);
+    }
+    if (k2 + 1 < n) {
+      row_bases(k2 + 1);
+      issue(0, qB, fxB, fyB);
+    }
+    process(trow, n - 1, t0 + n - 1, qA, fxA, fyA);
+  };
+
+  uint32_t qa[G], qb[G];
+  float fxa[G], fya[G], fxb[G], fyb[G];
+  row_bases(0);
+  issue(0, qa, fxa, fya);
+  // rows alternate which register set holds their column 0 (n is odd)
+  int k2 = 0;
+  for (; k2 + 1 < n; k2 += 2) {
+    row(k2, qa, fxa, fya, qb, fxb, fyb);
+    row(k2 + 1, qb, fxb, fyb, qa, fxa, fya);
   }
+  row(k2, qa, fxa, fya, qb, fxb, fyb);
 }
 
 // Views J0 .. J0+G-1: build H_j = M_j + e_j m^T, apply the border rule at the window

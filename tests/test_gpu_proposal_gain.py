@@ -1,0 +1,87 @@
+"""What the trained proposal network gains over the method without it.
+
+On a held-out scene of the training recipe (seed 3, not among the training seeds
+100000-101999), the search is run from the random initialisation and from the gated
+learned proposal for k = 0..ITERS iterations with the same random draws.  Reported: the
+mean cost and depth accuracy after each iteration for both, the share of pixels whose
+initial plane is the proposal, and the iterations each needs to come within 1% of the
+random run's final mean cost.  Asserted: the gate never raises a pixel's initial cost,
+the learned start is better than the random start, and the learned run never ends
+worse than the random run by more than the 1% margin."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2104_06165_amd as pm  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy")
+ITERS = 6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("no trained weights committed")
+    cfg = sg.CONFIGS["proposal_train"]
+    scene = sg.make_scene(sg.SCENE_SEEDS["highres"], cfg, device="cuda")
+    ctx = pm.Context(0)
+    ctx.set_scene(scene)
+    net = pm.Net(0, np.load(WEIGHTS))
+    yield scene, ctx, net
+    net.close()
+    ctx.close()
+
+
+def test_learned_proposal_gain(setup):
+    scene, ctx, net = setup
+    sol = sg.SOLVER["proposal_train"]
+    win, dil = sol["window"], sol["dilation"]
+    params = pm.Params(top_k=sol["top_k"], sigma_spatial_px=(win - 1) / 2.0, seed=sg.PM_SEED)
+    srcs = list(range(1, len(scene.images)))
+    H, W = scene.images[0].shape
+    r = dil * ((win - 1) // (2 * dil))
+    valid = np.zeros((H, W), bool)
+    valid[r:H - r, r:W - r] = True
+    gt = scene.gt_depth
+    proposal = ctx.propose(net, 0, srcs)
+
+    def stats(d, c):
+        c = c.cpu().numpy()
+        rel = np.abs(d.cpu().numpy() - gt) / gt
+        return float(c[valid].mean()), float((rel[valid] < 0.01).mean())
+
+    rand, learned = [], []
+    for k in range(ITERS + 1):
+        rand.append(stats(*ctx.patchmatch(0, srcs, win, dil, k, params)[::2]))
+        learned.append(stats(*ctx.patchmatch_proposal(0, srcs, win, dil, k, proposal, params)[::2]))
+    c_r0 = ctx.patchmatch(0, srcs, win, dil, 0, params)[2]
+    c_l0 = ctx.patchmatch_proposal(0, srcs, win, dil, 0, proposal, params)[2]
+    vt = torch.from_numpy(valid).cuda()
+    kept = float(((c_l0 < c_r0) & vt).sum()) / float(vt.sum())
+    target = 1.01 * rand[-1][0]
+    k_r = next(k for k in range(ITERS + 1) if rand[k][0] <= target)
+    k_l = next((k for k in range(ITERS + 1) if learned[k][0] <= target), None)
+    say(f"proposal taken on {kept:.3f} of valid pixels")
+    for k in range(ITERS + 1):
+        say(f"  it {k}: mean cost random {rand[k][0]:.5f} learned {learned[k][0]:.5f} | "
+            f"depth within 1% random {rand[k][1]:.4f} learned {learned[k][1]:.4f}")
+    say(f"iterations to within 1% of the random run's final mean cost: random {k_r}, learned {k_l}")
+    assert bool(((c_l0 <= c_r0) | ~vt).all())  # the gate never raises the initial cost
+    assert learned[0][0] < rand[0][0]  # the learned start is better
+    assert learned[-1][0] <= target  # and the learned run ends within the 1% margin
