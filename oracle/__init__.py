@@ -81,7 +81,11 @@ def lib():
         L.oracle_bilinear.restype = C.c_double
         L.oracle_aggregate.argtypes = [dp, ip, C.c_int, C.c_int, C.c_double, C.c_int]
         L.oracle_aggregate.restype = C.c_double
-        for f in ("oracle_patchmatch", "oracle_init", "oracle_halfsweep", "oracle_eval_cost", "oracle_homography"):
+        L.oracle_consistency.argtypes = [C.c_int, ip, ip, dp, dp, dp, C.POINTER(fp), C.POINTER(fp), C.c_int, ip,
+                                         C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, fp, fp,
+                                         C.POINTER(C.c_uint8)]
+        for f in ("oracle_patchmatch", "oracle_init", "oracle_halfsweep", "oracle_eval_cost", "oracle_homography",
+                  "oracle_consistency"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -215,3 +219,39 @@ def aggregate(cj, valid, top_k: int = 0, eps_c: float = 1e-4, fp64: bool = True)
     c = np.ascontiguousarray(cj, dtype=np.float64)
     v = np.ascontiguousarray(valid, dtype=np.int32)
     return lib().oracle_aggregate(_ptr(c, C.c_double), _ptr(v, C.c_int32), len(c), top_k, eps_c, int(fp64))
+
+
+def consistency(depths, normals, K, R, t, ref: int, nbrs, tau_d: float = 0.02, tau_n_deg: float = 30.0,
+                tau_r: float = 1.0, min_consistent: int = 2):
+    """Geometric-consistency filter of view ``ref`` (Sec. III-D).  depths / normals: dicts
+    view -> (H, W) / (H, W, 3) float32 maps; K, R: (n, 3, 3), t: (n, 3) for all n views.
+    -> (depth, normal, count) of the reference: kept values or zeros, consistent neighbours."""
+    n = len(K)
+    W = np.zeros(n, np.int32)
+    H = np.zeros(n, np.int32)
+    keep = []
+    dptr = (C.POINTER(C.c_float) * n)()
+    nptr = (C.POINTER(C.c_float) * n)()
+    for v in range(n):
+        if v in depths:
+            d = np.ascontiguousarray(depths[v], dtype=np.float32)
+            nm = np.ascontiguousarray(normals[v], dtype=np.float32)
+            keep += [d, nm]
+            H[v], W[v] = d.shape
+            dptr[v] = _ptr(d, C.c_float)
+            nptr[v] = _ptr(nm, C.c_float)
+    Kd = np.ascontiguousarray(np.asarray(K, np.float64).reshape(n, 9))
+    Rd = np.ascontiguousarray(np.asarray(R, np.float64).reshape(n, 9))
+    td = np.ascontiguousarray(np.asarray(t, np.float64).reshape(n, 3))
+    nb = np.ascontiguousarray(nbrs, dtype=np.int32)
+    Hr, Wr = int(H[ref]), int(W[ref])
+    od = np.zeros((Hr, Wr), np.float32)
+    on = np.zeros((Hr, Wr, 3), np.float32)
+    oc = np.zeros((Hr, Wr), np.uint8)
+    rc = lib().oracle_consistency(n, _ptr(W, C.c_int32), _ptr(H, C.c_int32), _ptr(Kd, C.c_double),
+                                  _ptr(Rd, C.c_double), _ptr(td, C.c_double), dptr, nptr, ref, _ptr(nb, C.c_int32),
+                                  len(nb), tau_d, tau_n_deg, tau_r, min_consistent, _ptr(od, C.c_float),
+                                  _ptr(on, C.c_float), _ptr(oc, C.c_uint8))
+    if rc != 0:
+        raise ValueError("oracle_consistency failed (bad view, neighbour or camera)")
+    return od, on, oc

@@ -614,6 +614,89 @@ int run_eval(const oracle_problem* pb, const double* planes, double* cost_out, d
   return 0;
 }
 
+// ---------------------------------------------------------------- geometric-consistency filter
+// Sec. III-D: pixel x of reference view i with depth d_x and normal n_x is projected into
+// neighbour view j with its depth (X = d_x K_i^-1 (x, y, 1) in camera i, then world, then
+// camera j, then K_j).  There d' is the bilinear interpolation of view j's depth map and n'
+// view j's normal at the rounded position.  The pair is consistent when the depths agree
+// (|z_j(X) - d'| < tau_d d', X's depth in camera j against d'), the normals agree (angle
+// below tau_n, compared in world coordinates as n . n' > cos tau_n) and the point of view
+// j at d' re-projects into view i within tau_r pixels of x.  A pixel is kept when it is
+// consistent with at least min_consistent neighbours (the paper: more than one).
+// Readings: relative depth difference in view j; the neighbour is unusable (not
+// consistent) when the position leaves [0, W-1] x [0, H-1], lies behind camera j, or any
+// of the four depth texels is not positive; rounding is floor(u + 1/2); the re-projected
+// point must lie in front of camera i.  Everything is FP64, one step at a time.
+struct CamD {
+  double K[9], Kinv[9], R[9], t[3];
+};
+
+bool cam_setup(const double* K, const double* R, const double* t, CamD& c) {
+  for (int i = 0; i < 9; ++i) c.K[i] = K[i], c.R[i] = R[i];
+  for (int i = 0; i < 3; ++i) c.t[i] = t[i];
+  return mat3_inverse(c.K, c.Kinv);
+}
+
+// camera frame -> world: R^T (X - t)
+void cam_to_world(const CamD& c, const double* X, double* Xw) {
+  const double d0 = X[0] - c.t[0], d1 = X[1] - c.t[1], d2 = X[2] - c.t[2];
+  for (int i = 0; i < 3; ++i) Xw[i] = c.R[i] * d0 + c.R[3 + i] * d1 + c.R[6 + i] * d2;
+}
+
+// world -> camera frame: R Xw + t
+void world_to_cam(const CamD& c, const double* Xw, double* X) {
+  for (int i = 0; i < 3; ++i) X[i] = c.R[3 * i] * Xw[0] + c.R[3 * i + 1] * Xw[1] + c.R[3 * i + 2] * Xw[2] + c.t[i];
+}
+
+// world-frame normal: R^T n
+void normal_to_world(const CamD& c, const float* n, double* nw) {
+  for (int i = 0; i < 3; ++i) nw[i] = c.R[i] * (double)n[0] + c.R[3 + i] * (double)n[1] + c.R[6 + i] * (double)n[2];
+}
+
+bool consistent_with(const CamD& ci, const CamD& cj, int Wj, int Hj, const float* Dj, const float* Nj, int x, int y,
+                     double d, const float* n, double tau_d, double cos_n, double tau_r) {
+  const double pix[3] = {(double)x, (double)y, 1.0};
+  double ray[3], Xi[3], Xw[3], Xj[3], p[3];
+  mat3_vec(ci.Kinv, pix, ray);
+  for (int k = 0; k < 3; ++k) Xi[k] = d * ray[k];
+  cam_to_world(ci, Xi, Xw);
+  world_to_cam(cj, Xw, Xj);
+  mat3_vec(cj.K, Xj, p);
+  if (!(p[2] > 0.0)) return false;
+  const double u = p[0] / p[2], v = p[1] / p[2];
+  if (!(u >= 0.0 && u <= (double)(Wj - 1) && v >= 0.0 && v <= (double)(Hj - 1))) return false;
+  // bilinear depth of view j
+  const int x0 = (int)std::floor(u), y0 = (int)std::floor(v);
+  const int x1 = std::min(x0 + 1, Wj - 1), y1 = std::min(y0 + 1, Hj - 1);
+  const double fx = u - x0, fy = v - y0;
+  const double d00 = Dj[(size_t)y0 * Wj + x0], d01 = Dj[(size_t)y0 * Wj + x1];
+  const double d10 = Dj[(size_t)y1 * Wj + x0], d11 = Dj[(size_t)y1 * Wj + x1];
+  if (!(d00 > 0.0 && d01 > 0.0 && d10 > 0.0 && d11 > 0.0)) return false;
+  const double top = d00 + fx * (d01 - d00), bot = d10 + fx * (d11 - d10);
+  const double dj = top + fy * (bot - top);
+  // depth test in camera j
+  if (!(std::fabs(Xj[2] - dj) < tau_d * dj)) return false;
+  // normal test at the rounded position, in world coordinates
+  const int xr = std::min((int)std::floor(u + 0.5), Wj - 1), yr = std::min((int)std::floor(v + 0.5), Hj - 1);
+  const float* nj = Nj + 3 * ((size_t)yr * Wj + xr);
+  double ni_w[3], nj_w[3];
+  normal_to_world(ci, n, ni_w);
+  normal_to_world(cj, nj, nj_w);
+  const double dot = ni_w[0] * nj_w[0] + ni_w[1] * nj_w[1] + ni_w[2] * nj_w[2];
+  if (!(dot > cos_n)) return false;
+  // re-projection of view j's point into view i
+  const double pj[3] = {u, v, 1.0};
+  double rj[3], Yj[3], Yw[3], Yi[3], q[3];
+  mat3_vec(cj.Kinv, pj, rj);
+  for (int k = 0; k < 3; ++k) Yj[k] = dj * rj[k];
+  cam_to_world(cj, Yj, Yw);
+  world_to_cam(ci, Yw, Yi);
+  mat3_vec(ci.K, Yi, q);
+  if (!(q[2] > 0.0)) return false;
+  const double ex = q[0] / q[2] - (double)x, ey = q[1] / q[2] - (double)y;
+  return std::sqrt(ex * ex + ey * ey) < tau_r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -675,6 +758,43 @@ double oracle_bilinear(const float* img, int W, int H, double u, double v, int f
   Solver<float> S;
   S.pb = &pb;
   return (double)S.sample(1, (float)u, (float)v);
+}
+
+// Geometric-consistency filter of reference view `ref` against `n_nbrs` neighbour views
+// (Sec. III-D).  Cameras: K, R (9 doubles each), t (3) per view; depth / normal maps per
+// view (row-major H x W and H x W x 3 float; NULL for views without a map).  Outputs
+// (reference size): depth and normal kept or zeroed, and the number of consistent
+// neighbours per pixel (pixels with depth <= 0 get 0 and are zeroed).
+int oracle_consistency(int n_views, const int32_t* width, const int32_t* height, const double* K, const double* R,
+                       const double* t, const float* const* depth, const float* const* normal, int ref,
+                       const int32_t* nbrs, int n_nbrs, double tau_d, double tau_n_deg, double tau_r,
+                       int min_consistent, float* out_depth, float* out_normal, uint8_t* out_count) {
+  if (ref < 0 || ref >= n_views || !depth[ref] || !normal[ref]) return -1;
+  std::vector<CamD> cams(n_views);
+  for (int v = 0; v < n_views; ++v)
+    if (!cam_setup(K + 9 * v, R + 9 * v, t + 3 * v, cams[v])) return -1;
+  for (int k = 0; k < n_nbrs; ++k)
+    if (nbrs[k] < 0 || nbrs[k] >= n_views || nbrs[k] == ref || !depth[nbrs[k]] || !normal[nbrs[k]]) return -1;
+  const double cos_n = std::cos(tau_n_deg * 3.14159265358979323846 / 180.0);
+  const int W = width[ref], H = height[ref];
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      const size_t p = (size_t)y * W + x;
+      const double d = depth[ref][p];
+      const float* n = normal[ref] + 3 * p;
+      int count = 0;
+      if (d > 0.0)
+        for (int k = 0; k < n_nbrs; ++k) {
+          const int j = nbrs[k];
+          count += consistent_with(cams[ref], cams[j], width[j], height[j], depth[j], normal[j], x, y, d, n, tau_d,
+                                   cos_n, tau_r);
+        }
+      const bool keep = d > 0.0 && count >= min_consistent;
+      out_count[p] = (uint8_t)std::min(count, 255);
+      out_depth[p] = keep ? depth[ref][p] : 0.0f;
+      for (int c = 0; c < 3; ++c) out_normal[3 * p + c] = keep ? n[c] : 0.0f;
+    }
+  return 0;
 }
 
 // Eq. 5 over the best-K valid views, for hand-set per-view costs.

@@ -1,0 +1,125 @@
+"""Pins of the geometric-consistency filter oracle (Sec. III-D) against closed forms on
+analytic scenes: a neighbour that is the reference camera itself (depth ratio, normal
+angle and counting thresholds exactly), a rectified pair looking at a fronto-parallel
+plane (re-projection error f b (1/Z' - 1/Z) in closed form, rounding of the normal
+lookup), and the cases that make a neighbour unusable."""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def cam(f, W, H, tx=0.0, yaw=0.0):
+    K = np.array([[f, 0.0, (W - 1) / 2.0], [0.0, f, (H - 1) / 2.0], [0.0, 0.0, 1.0]])
+    c, s = np.cos(yaw), np.sin(yaw)
+    R = np.array([[c, 0.0, -s], [0.0, 1.0, 0.0], [s, 0.0, c]])
+    t = -R @ np.array([tx, 0.0, 0.0])
+    return K, R, t
+
+
+def stack(cams):
+    return (np.stack([c[0] for c in cams]), np.stack([c[1] for c in cams]), np.stack([c[2] for c in cams]))
+
+
+def plane_maps(W, H, Z):
+    return np.full((H, W), Z, np.float32), np.broadcast_to(np.array([0.0, 0.0, -1.0], np.float32), (H, W, 3)).copy()
+
+
+W, H, F = 64, 48, 100.0
+
+
+def test_identical_neighbours_are_consistent():
+    K, R, t = stack([cam(F, W, H)] * 3)
+    d, n = plane_maps(W, H, 4.0)
+    od, on, oc = oracle.consistency({0: d, 1: d, 2: d}, {0: n, 1: n, 2: n}, K, R, t, 0, [1, 2])
+    assert np.all(oc == 2)
+    assert np.array_equal(od, d) and np.array_equal(on, n)
+
+
+@pytest.mark.parametrize("eps,ok", [(0.0200, True), (0.0203, True), (0.0206, False), (0.05, False), (-0.0195, True),
+                                    (-0.0205, False)])
+def test_depth_ratio_threshold(eps, ok):
+    """Same camera, neighbour depth (1 + eps) d: consistent iff |eps| / (1 + eps) < 0.02."""
+    K, R, t = stack([cam(F, W, H)] * 2)
+    d, n = plane_maps(W, H, 4.0)
+    dn = (d.astype(np.float64) * (1 + eps)).astype(np.float32)
+    _, _, oc = oracle.consistency({0: d, 1: dn}, {0: n, 1: n}, K, R, t, 0, [1], min_consistent=1)
+    assert np.all(oc == (1 if ok else 0))
+    assert (abs(eps) / (1 + eps) < 0.02) == ok
+
+
+@pytest.mark.parametrize("deg,ok", [(29.0, True), (29.9, True), (30.1, False), (45.0, False)])
+def test_normal_angle_threshold(deg, ok):
+    K, R, t = stack([cam(F, W, H)] * 2)
+    d, n = plane_maps(W, H, 4.0)
+    a = np.radians(deg)
+    nr = np.broadcast_to(np.array([np.sin(a), 0.0, -np.cos(a)], np.float32), (H, W, 3)).copy()
+    _, _, oc = oracle.consistency({0: d, 1: d}, {0: n, 1: nr}, K, R, t, 0, [1], min_consistent=1)
+    assert np.all(oc == (1 if ok else 0))
+
+
+@pytest.mark.parametrize("b,ok", [(3.9, True), (4.03, True), (4.15, False), (6.0, False)])
+def test_reprojection_error_closed_form(b, ok):
+    """Rectified pair, baseline b, plane at Z on the reference and Z' = 1.01 Z on the
+    neighbour: depth and normal tests pass; the neighbour's point re-projects
+    f b (1/Z - 1/Z') pixels away from x."""
+    Wb = 400
+    K, R, t = stack([cam(F, Wb, H), cam(F, Wb, H, tx=b)])
+    Z = 4.0
+    d, n = plane_maps(Wb, H, Z)
+    d2, _ = plane_maps(Wb, H, Z * 1.01)
+    _, _, oc = oracle.consistency({0: d, 1: d2}, {0: n, 1: n}, K, R, t, 0, [1], min_consistent=1)
+    err = F * b * (1 / Z - 1 / (Z * 1.01))
+    assert (err < 1.0) == ok
+    disp = F * b / Z
+    xs = np.arange(Wb)
+    seen = (xs - disp >= 0) & (xs - disp <= Wb - 2)  # the bilinear cell stays inside
+    assert np.all(oc[:, seen] == (1 if ok else 0))
+    assert np.all(oc[:, xs - disp < 0] == 0)  # projects left of the neighbour's image
+
+
+@pytest.mark.parametrize("disp,parity", [(2.4, 0), (2.6, 1)])
+def test_normal_taken_at_the_rounded_position(disp, parity):
+    """The neighbour's normal is read at floor(u + 1/2): with disparity 2.4 the rounded
+    column has x's parity, with 2.6 the other one."""
+    Wb = 80
+    Z = 4.0
+    b = disp * Z / F
+    K, R, t = stack([cam(F, Wb, H), cam(F, Wb, H, tx=b)])
+    d, n = plane_maps(Wb, H, Z)
+    nb = n.copy()
+    a = np.radians(40.0)
+    nb[:, 1::2] = [np.sin(a), 0.0, -np.cos(a)]  # odd columns fail the normal test
+    _, _, oc = oracle.consistency({0: d, 1: d}, {0: n, 1: nb}, K, R, t, 0, [1], min_consistent=1)
+    xs = np.arange(Wb)
+    u = xs - disp
+    inside = (u >= 0) & (u <= Wb - 1)
+    rounded_even = (np.floor(u + 0.5).astype(int) % 2) == 0
+    assert np.all(oc[:, inside & rounded_even] == 1)
+    assert np.all(oc[:, inside & ~rounded_even] == 0)
+    # the rounded column keeps x's parity for 2.4 (x - 2) and flips it for 2.6 (x - 3)
+    assert np.all(rounded_even[inside] == ((xs[inside] + parity) % 2 == 0))
+
+
+def test_unusable_neighbours_and_minimum_count():
+    K0, R0, t0 = cam(F, W, H)
+    K1, R1, t1 = cam(F, W, H, yaw=np.pi)  # looks the other way: everything behind it
+    K, R, t = stack([(K0, R0, t0), (K0, R0, t0), (K1, R1, t1), (K0, R0, t0)])
+    d, n = plane_maps(W, H, 4.0)
+    holes = d.copy()
+    holes[10:20, 10:20] = 0.0  # invalid texels
+    maps = {0: d, 1: d, 2: d, 3: holes}
+    norms = {0: n, 1: n, 2: n, 3: n}
+    od, on, oc = oracle.consistency(maps, norms, K, R, t, 0, [1, 2, 3])
+    # view 1 always consistent, view 2 never (behind), view 3 except where its texels are holes
+    near_hole = np.zeros((H, W), bool)
+    near_hole[9:20, 9:20] = True  # a bilinear cell touching the hole
+    assert np.all(oc[~near_hole] == 2) and np.all(oc[10:20, 10:20] == 1)
+    # min 2: the pixels with a single consistent neighbour are dropped
+    assert np.all(od[10:20, 10:20] == 0) and np.all(on[10:20, 10:20] == 0)
+    assert np.all(od[~near_hole] == 4.0)
+    # a reference pixel without depth is never kept and counts nothing
+    d0 = d.copy()
+    d0[0, 0] = 0.0
+    od2, _, oc2 = oracle.consistency({0: d0, 1: d, 3: d}, {0: n, 1: n, 3: n}, K, R, t, 0, [1, 3])
+    assert oc2[0, 0] == 0 and od2[0, 0] == 0 and oc2[1, 1] == 2
