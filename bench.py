@@ -143,6 +143,7 @@ def bench_batched(args):
         pixels += H * W
         tap_views += nominal_tap_views(valid, len(j["srcs"]), (2 * R + 1) ** 2, iters)
     achieved = tap_views * FLOPS_PER_TAP_VIEW / (ms_batch * 1e-3) / 1e12
+    filt = bench_filter(ctx, mv, jobs, outs)
     line = {
         "metric": "ms per batch of 24 mixed-size depth maps (8 it)", "value": ms_batch, "unit": "ms",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch,
@@ -157,9 +158,45 @@ def bench_batched(args):
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
                      "note": "whole-sequence time; nominal tap-views (all 11 candidates per iteration)"},
         "autotune": [r.__dict__ for r in allr],
+        "consistency_filter": filt,
     }
     ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def bench_filter(ctx, mv, jobs, outs, reps=5):
+    """Geometric-consistency filter of the batch's 24 depth maps, each against the other
+    references among its sources (Sec. III-D).  Algorithmic HBM bytes per reference pixel:
+    its depth, normal and the three outputs (4 + 12 + 4 + 12 + 1), plus per neighbour the
+    four depth texels and one normal (16 + 12)."""
+    import torch
+
+    import paper_2104_06165_amd as pm
+
+    maps = [(j["ref"], o["depth"], o["normal"]) for j, o in zip(jobs, outs)]
+    index = {j["ref"]: i for i, j in enumerate(jobs)}
+    plan = [(i, [index[v] for v in j["srcs"] if v in index]) for i, j in enumerate(jobs)]
+    params = pm.FilterParams()
+
+    def run():
+        return [ctx.filter(maps, i, nb, params) for i, nb in plan]
+
+    res = run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    pixels = sum(int(mv.images[j["ref"]].size) for j in jobs)
+    nbr_pixels = sum(int(mv.images[jobs[i]["ref"]].size) * len(nb) for i, nb in plan)
+    algo_bytes = pixels * 33 + nbr_pixels * 28
+    kept = sum(int((r[0] > 0).sum()) for r in res)
+    return {"ms_per_batch": ms, "references": len(plan), "neighbour_maps_per_reference": nbr_pixels / max(pixels, 1),
+            "kept_fraction": kept / pixels,
+            "roofline": {"bound": "hbm", "achieved": algo_bytes / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": algo_bytes / (ms * 1e-3) / 1e9 / 8000.0, "traffic": None,
+                         "note": "whole-batch time over 24 launches (host launch gaps included)"}}
 
 
 def learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, random_ms, reps=3):
@@ -316,6 +353,13 @@ def main():
     flops_per_step = float(n_hyp) * n_src * taps * FLOPS_PER_TAP_VIEW
     avg_launch_ms = kernel_ms / launches
     achieved = flops_per_step / launches_per_step / (avg_launch_ms * 1e-3) / 1e12
+    # the same depth map with the 8-bit images handed over from host memory (upload included)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.set_scene(scene)
+    run()
+    torch.cuda.synchronize()
+    pcie_ms = (time.perf_counter() - t0) * 1e3
     traffic = measured_traffic("phimvs_kernels.hip", "eval_kernel_highres_hbm.md") if wl == "highres" else None
     depth, normal, cost = out
     d = depth.cpu().numpy()
@@ -351,6 +395,7 @@ def main():
                      "kernel": "eval_kernel (evaluate-and-select)", "avg_launch_ms": avg_launch_ms,
                      "launches_per_step": launches_per_step,
                      "kernel_share_of_step": kernel_ms / (elapsed * 1e3)},
+        "pcie_inclusive_ms": pcie_ms,
         "hypotheses_per_step": n_hyp,
         "cost_evals_per_s": n_hyp * n_src / (ms_per_step * 1e-3),
         "tap_views_per_s": n_hyp * n_src * taps / (ms_per_step * 1e-3),

@@ -179,6 +179,43 @@ int phimvs_get_tuning(phimvs_ctx* ctx, phimvs_tuning* t);
 int phimvs_autotune(phimvs_ctx* ctx, int n_jobs, const phimvs_job* jobs, int iters, phimvs_tuning* results,
                     int* n_results);
 
+/* ---- geometric-consistency filter ---- */
+
+/* A depth-map result of one view of the context's scene (device arrays of that view's
+ * size: depth H*W, normal H*W*3; depth <= 0 marks a pixel without depth). */
+typedef struct {
+  int32_t view;
+  const float* depth;
+  const float* normal;
+} phimvs_depth_map;
+
+/* Thresholds of the consistency test (Sec. III-D): relative depth difference, normal
+ * angle (degrees), re-projection error (pixels), and the number of consistent
+ * neighbours a pixel needs to be kept (the paper: more than one).  Defaults 0.02, 30, 1, 2. */
+typedef struct {
+  double max_rel_depth;
+  double max_angle_deg;
+  double max_reproj_px;
+  int32_t min_consistent;
+} phimvs_filter_params;
+
+void phimvs_default_filter_params(phimvs_filter_params* p);
+
+/* Geometric-consistency filter of maps[ref_map] against the maps listed in nbrs (indices
+ * into maps, at most PHIMVS_MAX_SOURCES, none equal to ref_map), Sec. III-D: each pixel
+ * x with depth d is back-projected, projected into every neighbour view j and compared
+ * with view j's map there: the depths agree when |z_j(X) - d'| < max_rel_depth d' (d' the
+ * bilinear depth of view j, z_j(X) the point's depth in camera j), the normals when the
+ * angle between them (world frame; view j's normal at the rounded position) is below
+ * max_angle_deg, and view j's point at d' must re-project within max_reproj_px of x.  A
+ * neighbour is not consistent when the projection leaves its image, lies behind it or
+ * touches a texel without depth.  Outputs (device, reference size): depth and normal
+ * kept or zeroed, and the count of consistent neighbours per pixel (uint8).  All
+ * arithmetic is FP64.  p = NULL uses the defaults. */
+int phimvs_filter(phimvs_ctx* ctx, int n_maps, const phimvs_depth_map* maps, int ref_map, const int32_t* nbrs,
+                  int n_nbrs, const phimvs_filter_params* p, float* depth_out, float* normal_out,
+                  uint8_t* count_out);
+
 /* ---- diagnostics ---- */
 
 /* flags: PHIMVS_DIAG_COUNT counts the (pixel, hypothesis) pairs the evaluate-and-select

@@ -30,6 +30,7 @@ EXPORTS = ("phimvs_default_params", "phimvs_create", "phimvs_destroy", "phimvs_l
            "phimvs_step", "phimvs_get_state", "phimvs_set_state", "phimvs_output", "phimvs_eval_cost",
            "phimvs_patchmatch_batch", "phimvs_set_tuning", "phimvs_get_tuning", "phimvs_autotune",
            "phimvs_diag_enable", "phimvs_diag_read", "phimvs_check_reciprocal",
+           "phimvs_default_filter_params", "phimvs_filter",
            # learned initial-plane proposal (include/phimvs_net.h)
            "phimvs_net_create", "phimvs_net_destroy", "phimvs_net_last_error", "phimvs_net_set_stream",
            "phimvs_net_param_count", "phimvs_net_set_params", "phimvs_net_get_params", "phimvs_net_forward",
@@ -64,6 +65,24 @@ class _Job(C.Structure):
 
 class _Tuning(C.Structure):
     _fields_ = [("tile_rows", C.c_int32), ("persistent", C.c_int32), ("wgs_per_cu", C.c_int32), ("ms", C.c_double)]
+
+
+class _DepthMap(C.Structure):
+    _fields_ = [("view", C.c_int32), ("depth", C.c_void_p), ("normal", C.c_void_p)]
+
+
+class _FilterParams(C.Structure):
+    _fields_ = [("max_rel_depth", C.c_double), ("max_angle_deg", C.c_double), ("max_reproj_px", C.c_double),
+                ("min_consistent", C.c_int32)]
+
+
+@dataclass
+class FilterParams:
+    """Thresholds of the geometric-consistency filter (include/phimvs.h)."""
+    max_rel_depth: float = 0.02
+    max_angle_deg: float = 30.0
+    max_reproj_px: float = 1.0
+    min_consistent: int = 2
 
 
 @dataclass
@@ -128,6 +147,10 @@ def lib():
         L.phimvs_diag_read.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
         L.phimvs_check_reciprocal.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64),
                                               C.POINTER(C.c_uint32)]
+        L.phimvs_default_filter_params.argtypes = [C.POINTER(_FilterParams)]
+        L.phimvs_default_filter_params.restype = None
+        L.phimvs_filter.argtypes = [vp, ip, C.POINTER(_DepthMap), ip, C.POINTER(C.c_int32), ip,
+                                    C.POINTER(_FilterParams), fp, fp, vp]
         L.phimvs_net_create.argtypes = [C.POINTER(vp), ip, vp]
         L.phimvs_net_destroy.argtypes = [vp]
         L.phimvs_net_destroy.restype = None
@@ -149,7 +172,7 @@ def lib():
         for name in EXPORTS:
             f = getattr(L, name)
             if name not in ("phimvs_default_params", "phimvs_destroy", "phimvs_last_error", "phimvs_net_destroy",
-                            "phimvs_net_last_error"):
+                            "phimvs_net_last_error", "phimvs_default_filter_params"):
                 f.restype = C.c_int
         L.phimvs_net_param_count.restype = C.c_int64
         _lib = L
@@ -272,6 +295,29 @@ class Context:
                                                      proposal.data_ptr(), out[0].data_ptr(), out[1].data_ptr(),
                                                      out[2].data_ptr(), 1))
         return out
+
+    # ------------------------------------------------------------------ consistency filter
+    def filter(self, maps, ref_map: int, nbrs: Sequence[int], params: Optional[FilterParams] = None):
+        """Geometric-consistency filter of maps[ref_map] against maps[nbrs].  maps: list of
+        (view, depth (H, W), normal (H, W, 3)) device tensors.  -> (depth, normal, count)."""
+        torch = self.torch
+        self._sync_stream()
+        arr = (_DepthMap * len(maps))()
+        for i, (v, d, n) in enumerate(maps):
+            if d.dtype != torch.float32 or n.dtype != torch.float32 or not d.is_contiguous() or not n.is_contiguous():
+                raise ValueError("depth / normal maps must be contiguous float32 tensors")
+            arr[i] = _DepthMap(int(v), d.data_ptr(), n.data_ptr())
+        v0 = maps[ref_map][0] if 0 <= ref_map < len(maps) else -1
+        H, W = self.views[v0] if 0 <= v0 < len(self.views) else (1, 1)
+        od = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        on = torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        oc = torch.empty((H, W), dtype=torch.uint8, device=self.device)
+        nb = (C.c_int32 * max(len(nbrs), 1))(*nbrs)
+        fp_ = params or FilterParams()
+        cp = _FilterParams(fp_.max_rel_depth, fp_.max_angle_deg, fp_.max_reproj_px, fp_.min_consistent)
+        self._check(lib().phimvs_filter(self.h, len(maps), arr, ref_map, nb, len(nbrs), C.byref(cp), od.data_ptr(),
+                                        on.data_ptr(), oc.data_ptr()))
+        return od, on, oc
 
     # ------------------------------------------------------------------ learned proposal
     def net_inputs(self, net: "Net", ref: int, srcs: Sequence[int]):

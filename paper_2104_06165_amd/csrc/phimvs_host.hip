@@ -74,6 +74,8 @@ struct phimvs_ctx {
   Batch multi;                    // phimvs_patchmatch_batch
   phimvs_tuning tuning{4, 0, 0, 0.0};
   DevBuf<float> io_a, io_b, io_c, io_d;  // staging for host inputs / outputs
+  DevBuf<FilterNbr> filter_nbrs;          // neighbour table of the consistency filter
+  std::vector<FilterNbr> filter_host;
   DevBuf<uint8_t> io_u8;
   // diagnostics
   int diag = 0;
@@ -594,6 +596,7 @@ void phimvs_destroy(phimvs_ctx* c) {
   release(c->io_b);
   release(c->io_c);
   release(c->io_d);
+  release(c->filter_nbrs);
   release(c->io_u8);
   if (c->diag_count) (void)hipFree(c->diag_count);
   for (auto& e : c->diag_events) {
@@ -877,6 +880,79 @@ int phimvs_patchmatch_proposal(phimvs_ctx* c, int ref, const int* srcs, int n_sr
   if (!c) return PHIMVS_E_ARG;
   if (!proposal) return fail(c, PHIMVS_E_ARG, "proposal planes required");
   return run_single(c, ref, srcs, n_srcs, window, dilation, iters, p, proposal, depth, normal, cost, on_device);
+}
+
+// ---------------------------------------------------------------------------- consistency filter
+
+void phimvs_default_filter_params(phimvs_filter_params* p) {
+  if (!p) return;
+  p->max_rel_depth = 0.02;
+  p->max_angle_deg = 30.0;
+  p->max_reproj_px = 1.0;
+  p->min_consistent = 2;
+}
+
+int phimvs_filter(phimvs_ctx* c, int n_maps, const phimvs_depth_map* maps, int ref_map, const int32_t* nbrs,
+                  int n_nbrs, const phimvs_filter_params* pp, float* depth_out, float* normal_out,
+                  uint8_t* count_out) {
+  if (!c) return PHIMVS_E_ARG;
+  if (n_maps < 1 || !maps || ref_map < 0 || ref_map >= n_maps) return fail(c, PHIMVS_E_ARG, "invalid map list");
+  if (n_nbrs < 0 || n_nbrs > PHIMVS_MAX_SOURCES || (n_nbrs > 0 && !nbrs))
+    return fail(c, PHIMVS_E_ARG, "between 0 and PHIMVS_MAX_SOURCES neighbours");
+  if (!depth_out || !normal_out || !count_out) return fail(c, PHIMVS_E_ARG, "null output");
+  phimvs_filter_params p;
+  phimvs_default_filter_params(&p);
+  if (pp) p = *pp;
+  if (!(p.max_rel_depth > 0) || !(p.max_angle_deg > 0 && p.max_angle_deg <= 180) || !(p.max_reproj_px > 0) ||
+      p.min_consistent < 0)
+    return fail(c, PHIMVS_E_ARG, "invalid filter thresholds");
+  auto view_ok = [&](const phimvs_depth_map& m) {
+    return m.view >= 0 && m.view < (int)c->views.size() && m.depth && m.normal;
+  };
+  const phimvs_depth_map& R0 = maps[ref_map];
+  if (!view_ok(R0)) return fail(c, PHIMVS_E_ARG, "reference map: invalid view or null arrays");
+  HIPCHECK(c, hipSetDevice(c->device));
+  const ViewData& V0 = c->views[R0.view];
+  FilterArgs a{};
+  a.W = V0.W;
+  a.H = V0.H;
+  for (int i = 0; i < 9; ++i) a.K[i] = V0.K[i], a.R[i] = V0.R[i];
+  for (int i = 0; i < 3; ++i) a.t[i] = V0.t[i];
+  if (!inv33(V0.K, a.Kinv)) return fail(c, PHIMVS_E_ARG, "singular K");
+  a.depth = R0.depth;
+  a.normal = R0.normal;
+  a.tau_d = p.max_rel_depth;
+  a.cos_n = std::cos(p.max_angle_deg * 3.14159265358979323846 / 180.0);
+  a.tau_r = p.max_reproj_px;
+  a.min_consistent = p.min_consistent;
+  a.depth_out = depth_out;
+  a.normal_out = normal_out;
+  a.count_out = count_out;
+  // the previous call's table may still be in use by its launch
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->filter_host.assign(std::max(n_nbrs, 1), FilterNbr{});
+  for (int k = 0; k < n_nbrs; ++k) {
+    if (nbrs[k] < 0 || nbrs[k] >= n_maps || nbrs[k] == ref_map || !view_ok(maps[nbrs[k]]))
+      return fail(c, PHIMVS_E_ARG, "neighbour " + std::to_string(k) + ": invalid map index, view or arrays");
+    const phimvs_depth_map& M = maps[nbrs[k]];
+    const ViewData& V = c->views[M.view];
+    FilterNbr& nb = c->filter_host[k];
+    for (int i = 0; i < 9; ++i) nb.K[i] = V.K[i], nb.R[i] = V.R[i];
+    for (int i = 0; i < 3; ++i) nb.t[i] = V.t[i];
+    if (!inv33(V.K, nb.Kinv)) return fail(c, PHIMVS_E_ARG, "singular K");
+    nb.W = V.W;
+    nb.H = V.H;
+    nb.depth = M.depth;
+    nb.normal = M.normal;
+  }
+  int rc;
+  if ((rc = ensure(c, c->filter_nbrs, c->filter_host.size()))) return rc;
+  HIPCHECK(c, hipMemcpyAsync(c->filter_nbrs.p, c->filter_host.data(), c->filter_host.size() * sizeof(FilterNbr),
+                             hipMemcpyHostToDevice, c->stream));
+  a.n_nbrs = n_nbrs;
+  a.nbrs = c->filter_nbrs.p;
+  HIPCHECK(c, launch_filter(a, c->stream));
+  return PHIMVS_OK;
 }
 
 // ---------------------------------------------------------------------------- batches

@@ -84,6 +84,28 @@ hipError_t launch_build_view(const uint8_t* img, int64_t stride, int W, int H, _
 hipError_t launch_rcp_check(uint32_t first, uint32_t count, unsigned long long* mism, uint32_t* example,
                             hipStream_t st);
 
+// geometric-consistency filter: one neighbour view and the launch
+struct FilterNbr {
+  double K[9], Kinv[9], R[9], t[3];
+  int W, H;
+  const float* depth;
+  const float* normal;
+};
+struct FilterArgs {
+  int W, H;
+  double K[9], Kinv[9], R[9], t[3];
+  const float* depth;
+  const float* normal;
+  int n_nbrs;
+  const FilterNbr* nbrs;  // device array of n_nbrs
+  double tau_d, cos_n, tau_r;
+  int min_consistent;
+  float* depth_out;
+  float* normal_out;
+  uint8_t* count_out;
+};
+hipError_t launch_filter(const FilterArgs& a, hipStream_t st);
+
 // a view of a context's scene, for the proposal network's host code
 struct ViewInfo {
   int W, H;
