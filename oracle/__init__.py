@@ -84,8 +84,14 @@ def lib():
         L.oracle_consistency.argtypes = [C.c_int, ip, ip, dp, dp, dp, C.POINTER(fp), C.POINTER(fp), C.c_int, ip,
                                          C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, fp, fp,
                                          C.POINTER(C.c_uint8)]
+        L.oracle_phi_hypotheses.argtypes = [fp, C.c_int, C.c_int, fp]
+        L.oracle_phi_hypotheses.restype = None
+        L.oracle_phi_map_bruteforce.argtypes = [fp, fp, fp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                                C.c_double, ip]
+        L.oracle_phi_map_bruteforce.restype = C.c_double
+        L.oracle_phi_normals.argtypes = [fp, C.c_int, C.c_int, dp, fp]
         for f in ("oracle_patchmatch", "oracle_init", "oracle_halfsweep", "oracle_eval_cost", "oracle_homography",
-                  "oracle_consistency"):
+                  "oracle_consistency", "oracle_phi_normals"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -255,3 +261,35 @@ def consistency(depths, normals, K, R, t, ref: int, nbrs, tau_d: float = 0.02, t
     if rc != 0:
         raise ValueError("oracle_consistency failed (bad view, neighbour or camera)")
     return od, on, oc
+
+
+def phi_hypotheses(depth):
+    """Plane-hypothesis depths (Sec. III-E) of the pixels without depth: (H, W, 4), 0 = none."""
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    H, W = d.shape
+    hyp = np.zeros((H, W, 4), np.float32)
+    lib().oracle_phi_hypotheses(_ptr(d, C.c_float), W, H, _ptr(hyp, C.c_float))
+    return hyp
+
+
+def phi_map_bruteforce(depth, hyp, cost, k1: float, k2: float, k3: float, cmax: float = CMAX):
+    """Exact MAP labelling of the pairwise model of Sec. III-E on a tiny grid -> (labels (H, W), log potential)."""
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    h = np.ascontiguousarray(hyp, dtype=np.float32)
+    c = np.ascontiguousarray(cost, dtype=np.float32)
+    H, W = d.shape
+    lab = np.zeros((H, W), np.int32)
+    e = lib().oracle_phi_map_bruteforce(_ptr(d, C.c_float), _ptr(h, C.c_float), _ptr(c, C.c_float), W, H, k1, k2, k3,
+                                        cmax, _ptr(lab, C.c_int32))
+    return lab, e
+
+
+def phi_normals(depth, K):
+    """Normals of Eq. 10 from a depth map (H, W) and intrinsics K -> (H, W, 3), 0 where undefined."""
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    Kd = np.ascontiguousarray(np.asarray(K, np.float64).reshape(9))
+    H, W = d.shape
+    n = np.zeros((H, W, 3), np.float32)
+    if lib().oracle_phi_normals(_ptr(d, C.c_float), W, H, _ptr(Kd, C.c_double), _ptr(n, C.c_float)) != 0:
+        raise ValueError("singular K")
+    return n

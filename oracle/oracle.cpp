@@ -697,6 +697,52 @@ bool consistent_with(const CamD& ci, const CamD& cj, int Wj, int Hj, const float
   return std::sqrt(ex * ex + ey * ey) < tau_r;
 }
 
+// ---------------------------------------------------------------- plane hypothesis inference
+// Sec. III-E.  Hypotheses: every pixel without depth gets one depth per direction
+// (horizontal, vertical, 45 degrees below, 45 degrees above), the value at the pixel of
+// the straight line fitted (least squares, depth against step index s) to the six
+// closest pixels with depth along that direction (both sides; by |s|, the negative side
+// first on ties; fewer if the line leaves the image; none below two points or when the
+// fitted depth is not positive).  FP64, sums in collection order.
+const int kPhiDir[4][2] = {{1, 0}, {0, 1}, {1, 1}, {1, -1}};
+
+double phi_line_fit(const float* depth, int W, int H, int x, int y, int dx, int dy) {
+  double S0 = 0, S1 = 0, S2 = 0, T0 = 0, T1 = 0;
+  int n = 0;
+  for (int s = 1; n < 6; ++s) {
+    bool any_inside = false;
+    for (int side = -1; side <= 1 && n < 6; side += 2) {
+      const int xs = x + side * s * dx, ys = y + side * s * dy;
+      if (xs < 0 || xs >= W || ys < 0 || ys >= H) continue;
+      any_inside = true;
+      const double d = depth[(size_t)ys * W + xs];
+      if (!(d > 0.0)) continue;
+      const double si = (double)(side * s);
+      S0 = S0 + 1.0;
+      S1 = S1 + si;
+      S2 = S2 + si * si;
+      T0 = T0 + d;
+      T1 = T1 + si * d;
+      ++n;
+    }
+    if (!any_inside) break;
+  }
+  if (n < 2) return 0.0;
+  const double det = S0 * S2 - S1 * S1;
+  const double a = (S2 * T0 - S1 * T1) / det;
+  return a > 0.0 ? a : 0.0;
+}
+
+// MAP labelling of a 4-connected grid by exhaustive search (tiny grids only): node i has
+// n_lab[i] states with unary potentials un[i * 4 + k] > 0; an edge between nodes i and j
+// (right and down neighbours) multiplies by pw(h_i, h_j).  Maximises the product (sum of
+// logs).  Returns the label per node.
+double phi_pairwise(double h1, double h2, double k3) {
+  const double rel = h1 > h2 ? (h1 - h2) / h2 : (h2 - h1) / h1;
+  const double m = rel < 1.0 ? rel : 1.0;
+  return (k3 - m) * (k3 - m);
+}
+
 }  // namespace
 
 extern "C" {
@@ -793,6 +839,111 @@ int oracle_consistency(int n_views, const int32_t* width, const int32_t* height,
       out_count[p] = (uint8_t)std::min(count, 255);
       out_depth[p] = keep ? depth[ref][p] : 0.0f;
       for (int c = 0; c < 3; ++c) out_normal[3 * p + c] = keep ? n[c] : 0.0f;
+    }
+  return 0;
+}
+
+// Plane-hypothesis depths (Sec. III-E) of every pixel without depth: hyp (H*W*4), 0 = none.
+void oracle_phi_hypotheses(const float* depth, int W, int H, float* hyp) {
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      const size_t p = (size_t)y * W + x;
+      for (int k = 0; k < 4; ++k)
+        hyp[4 * p + k] = depth[p] > 0.0f ? 0.0f : (float)phi_line_fit(depth, W, H, x, y, kPhiDir[k][0], kPhiDir[k][1]);
+    }
+}
+
+// Exact MAP of the pairwise model of Sec. III-E on a tiny grid (W*H nodes, at most 4
+// states each, brute force over all labellings).  depth[i] > 0 makes node i a fixed
+// single-state node with that depth and potential 1; otherwise its states are the
+// non-zero hyp[4 i + k] with unary (C_max - cost[4 i + k]) / k1 + k2.  Edge potential
+// [k3 - min(1, relative difference)]^2 (Eq. 8).  label[i] receives the chosen k (or -1
+// for fixed nodes / nodes without a state); returns the maximal log-potential.
+double oracle_phi_map_bruteforce(const float* depth, const float* hyp, const float* cost, int W, int H, double k1,
+                                 double k2, double k3, double cmax, int32_t* label) {
+  const int N = W * H;
+  std::vector<std::vector<int>> states(N);
+  std::vector<std::vector<double>> val(N), logu(N);
+  for (int i = 0; i < N; ++i) {
+    if (depth[i] > 0.0f) {
+      states[i].push_back(-1);
+      val[i].push_back(depth[i]);
+      logu[i].push_back(0.0);
+      continue;
+    }
+    for (int k = 0; k < 4; ++k)
+      if (hyp[4 * i + k] > 0.0f) {
+        states[i].push_back(k);
+        val[i].push_back(hyp[4 * i + k]);
+        logu[i].push_back(std::log((cmax - (double)cost[4 * i + k]) / k1 + k2));
+      }
+    if (states[i].empty()) {  // no state: isolated from the model
+      states[i].push_back(-1);
+      val[i].push_back(0.0);
+      logu[i].push_back(0.0);
+    }
+  }
+  std::vector<int> cur(N, 0), best(N, 0);
+  double best_e = -1e300;
+  for (;;) {
+    double e = 0.0;
+    for (int i = 0; i < N; ++i) e += logu[i][cur[i]];
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        const int i = y * W + x;
+        const double hi = val[i][cur[i]];
+        if (!(hi > 0.0)) continue;
+        if (x + 1 < W && val[i + 1][cur[i + 1]] > 0.0) e += std::log(phi_pairwise(hi, val[i + 1][cur[i + 1]], k3));
+        if (y + 1 < H && val[i + W][cur[i + W]] > 0.0) e += std::log(phi_pairwise(hi, val[i + W][cur[i + W]], k3));
+      }
+    if (e > best_e) {
+      best_e = e;
+      best = cur;
+    }
+    int i = 0;
+    while (i < N && ++cur[i] == (int)states[i].size()) cur[i++] = 0;
+    if (i == N) break;
+  }
+  for (int i = 0; i < N; ++i) label[i] = states[i][best[i]];
+  return best_e;
+}
+
+// Normals of Eq. 10 (with the norm, not its square): n = (X_u - X_d) x (X_l - X_r),
+// normalised and turned to face the camera, X the back-projection d K^-1 (x, y, 1) of the
+// 4-connected neighbours (up = y - 1, left = x - 1).  Pixels without depth, or with a
+// neighbour without depth or outside the image, get 0.  FP64.
+int oracle_phi_normals(const float* depth, int W, int H, const double* K, float* normal) {
+  double Ki[9];
+  if (!mat3_inverse(K, Ki)) return -1;
+  auto back = [&](int x, int y, double* X) {
+    const double pix[3] = {(double)x, (double)y, 1.0};
+    double r[3];
+    mat3_vec(Ki, pix, r);
+    const double d = depth[(size_t)y * W + x];
+    for (int k = 0; k < 3; ++k) X[k] = d * r[k];
+  };
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      float* n = normal + 3 * ((size_t)y * W + x);
+      n[0] = n[1] = n[2] = 0.0f;
+      if (x < 1 || y < 1 || x + 1 >= W || y + 1 >= H) continue;
+      const size_t p = (size_t)y * W + x;
+      if (!(depth[p] > 0.0f && depth[p - W] > 0.0f && depth[p + W] > 0.0f && depth[p - 1] > 0.0f &&
+            depth[p + 1] > 0.0f))
+        continue;
+      double Xu[3], Xd[3], Xl[3], Xr[3], C[3];
+      back(x, y - 1, Xu);
+      back(x, y + 1, Xd);
+      back(x - 1, y, Xl);
+      back(x + 1, y, Xr);
+      back(x, y, C);
+      const double a[3] = {Xu[0] - Xd[0], Xu[1] - Xd[1], Xu[2] - Xd[2]};
+      const double b[3] = {Xl[0] - Xr[0], Xl[1] - Xr[1], Xl[2] - Xr[2]};
+      double c[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+      const double len = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+      if (!(len > 0.0)) continue;
+      if (c[0] * C[0] + c[1] * C[1] + c[2] * C[2] > 0.0) c[0] = -c[0], c[1] = -c[1], c[2] = -c[2];
+      for (int k = 0; k < 3; ++k) n[k] = (float)(c[k] / len);
     }
   return 0;
 }
