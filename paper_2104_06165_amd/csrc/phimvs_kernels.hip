@@ -162,12 +162,13 @@ struct Hyp {
 };
 
 // Sums of a group of G views (J0, J0 + 1, ...) over the window taps in row-major order.
-// EXACT selects IEEE division for 1/w.  The loop is software-pipelined by one tap with
+// EXACT selects IEEE division for 1/w; CLAMP clamps every sample position into the image
+// (without it the caller has proved every position inside).  The loop is software-pipelined by one tap with
 // two alternating register sets: the texel loads of tap t + 1 are issued before tap t's
 // texels are interpolated and accumulated, so each gather's latency overlaps a tap of
 // arithmetic.  Every tap's arithmetic and the order of accumulation are unchanged.  The
 // weight tables hold 1.0 when the weights are off, so w = 1 exactly then.
-template <int G, bool EXACT>
+template <int G, bool EXACT, bool CLAMP>
 __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp, const float* __restrict__ tile,
                                          int TW, const float* __restrict__ wcol, const float* __restrict__ wsp,
                                          const float (&Hm)[G][9], const float (&bc)[G], float (&Sb)[G],
@@ -202,15 +203,15 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
   };
   // warp column k1 of the row whose bases are loaded and issue its texel loads
   auto issue = [&](int k1, uint32_t (&qo)[G], float (&fxo)[G], float (&fyo)[G]) {
-    const float X = (float)(rp.x + s * (k1 - R));
+    const float X = rp.X0 + (float)(s * (k1 - R));  // exact: integers below 2^24
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const float u = __builtin_fmaf(Hm[g][0], X, rbu[g]);
       const float v = __builtin_fmaf(Hm[g][3], X, rbv[g]);
       const float ww = __builtin_fmaf(Hm[g][6], X, rbw[g]);
       const float r = EXACT ? 1.0f / ww : rcp_nr(ww);
-      const float up = clampf(u * r, Wm1[g]);
-      const float vp = clampf(v * r, Hm1[g]);
+      const float up = CLAMP ? clampf(u * r, Wm1[g]) : u * r;
+      const float vp = CLAMP ? clampf(v * r, Hm1[g]) : v * r;
       // up, vp >= 0: fract(u) = u - floor(u) exactly
       fxo[g] = __builtin_amdgcn_fractf(up);
       fyo[g] = __builtin_amdgcn_fractf(vp);
@@ -280,7 +281,7 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
   float Hm[G][9], bc[G];
   const int r = A.s * A.R;
   const float Xmax = rp.X0 + (float)r, Ymax = rp.Y0 + (float)r;
-  bool need_exact = false, any_ok = false;
+  bool need_exact = false, need_clamp = false, any_ok = false;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const SrcDev& V = A.src[J0 + g];
@@ -291,6 +292,7 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
     // border rule at the four window corners (IEEE division)
     bool inside = h.ok;
     float wmin = 3.0e38f, wmax = -3.0e38f;
+    float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const float X = (float)(rp.x + ((k & 1) ? r : -r));
@@ -303,12 +305,32 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
       inside = inside && (w > 0.0f) && (up >= 0.0f && up <= V.Wm1 && vp >= 0.0f && vp <= V.Hm1);
       wmin = fminf(wmin, w);
       wmax = fmaxf(wmax, w);
+      umin = fminf(umin, up);
+      umax = fmaxf(umax, up);
+      vmin = fminf(vmin, vp);
+      vmax = fmaxf(vmax, vp);
     }
     // every tap's computed w lies within 2^-22 S of the corner range (fma error bound), so
     // the fast reciprocal is exact for the whole window when this range stays in [2^-100, 2^100]
     const float S = fabsf(Hm[g][6]) * Xmax + fabsf(Hm[g][7]) * Ymax + fabsf(Hm[g][8]);
     const float slack = S * 0x1p-22f;
     const bool fast = (wmin - slack >= 0x1p-100f) && (wmax + slack <= 0x1p100f);
+    // Clamp-free taps: a computed tap position differs from the exact one by at most
+    // mu = (2^-23 S_u + W 2^-23 S) / w_low + 2^-22 W (two fma roundings in u and w, the
+    // reciprocal and the product), doubled here for safety; exact tap positions lie in the
+    // convex image of the window (w > 0), so corners at least 2 mu inside put every
+    // computed tap inside, where the clamp changes nothing.
+    if (inside && fast) {
+      const float Su = fabsf(Hm[g][0]) * Xmax + fabsf(Hm[g][1]) * Ymax + fabsf(Hm[g][2]);
+      const float Sv = fabsf(Hm[g][3]) * Xmax + fabsf(Hm[g][4]) * Ymax + fabsf(Hm[g][5]);
+      const float wlow = wmin - slack;
+      const float Wf = V.Wm1 + 1.0f, Hf = V.Hm1 + 1.0f;
+      const float mu_u = 2.0f * ((Su + Wf * S) * 0x1p-23f / wlow + Wf * 0x1p-22f);
+      const float mu_v = 2.0f * ((Sv + Hf * S) * 0x1p-23f / wlow + Hf * 0x1p-22f);
+      const bool safe = umin >= 2.0f * mu_u && umax <= V.Wm1 - 2.0f * mu_u && vmin >= 2.0f * mu_v &&
+                        vmax <= V.Hm1 - 2.0f * mu_v;
+      need_clamp = need_clamp || !safe;
+    }
     ok[g] = inside;
     c[g] = kCmax;
     need_exact = need_exact || (inside && !fast);
@@ -320,13 +342,22 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
       const float rw = 1.0f / w;
       bc[g] = sample_quad(V.quad, V.W, clampf(u * rw, V.Wm1), clampf(v * rw, V.Hm1));
     }
+    // a lane whose view is invalid walks the constant map to texel (0, 0): its sums are
+    // discarded, and its loads stay in bounds and in cache
+    if (!inside) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Hm[g][e] = 0.0f;
+      Hm[g][8] = 1.0f;
+    }
   }
   if (__ballot(any_ok) == 0) return;
   float Sb[G], Sbb[G], Sab[G];
   if (__ballot(need_exact) != 0)
-    tap_pass<G, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+    tap_pass<G, true, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+  else if (__ballot(need_clamp) != 0)
+    tap_pass<G, false, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
   else
-    tap_pass<G, false>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+    tap_pass<G, false, false>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     if (ok[g]) {
@@ -690,7 +721,7 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
 // (workgroup b runs on XCD b % 8), so each XCD's L2 serves a compact band of the image.
 // Persistent: a fixed grid; each workgroup pulls tiles from its XCD's queue over the same
 // contiguous range, so uneven jobs balance dynamically within an XCD.
-__global__ __launch_bounds__(kBlock) void eval_kernel(const Job* __restrict__ jobs, Launch L) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void eval_kernel(const Job* __restrict__ jobs, Launch L) {
   extern __shared__ float lds[];
   __shared__ int next_tile;
   const int xcd = blockIdx.x & 7;
