@@ -216,6 +216,59 @@ int phimvs_filter(phimvs_ctx* ctx, int n_maps, const phimvs_depth_map* maps, int
                   int n_nbrs, const phimvs_filter_params* p, float* depth_out, float* normal_out,
                   uint8_t* count_out);
 
+/* ---- plane hypothesis inference (Sec. III-E) ----
+ * Depth hypotheses for the pixels a filtered depth map leaves empty, their matching
+ * costs, the selection of one hypothesis per pixel through a pairwise graph model (the
+ * part the paper runs on the CPU, here too), and normals for the filled pixels. */
+
+/* Four hypotheses per pixel without depth (depth <= 0): for each direction (horizontal,
+ * vertical, 45 degrees below (1, 1), 45 degrees above (1, -1)) the value at the pixel of
+ * the straight line fitted by least squares (depth against step index) to the six
+ * pixels with depth closest along that line (both sides, fewer if the image ends; none
+ * below two points or when the fitted depth is not positive).  depth: device H*W;
+ * hyp: device, planar 4*H*W (hypothesis k of pixel p at hyp[k * H * W + p]), 0 = none.
+ * FP64 fit. */
+int phimvs_phi_hypotheses(phimvs_ctx* ctx, int width, int height, const float* depth, float* hyp);
+
+/* Matching cost (Eq. 5, the prepared problem's cost) of every hypothesis: the fronto-
+ * parallel plane at the hypothesis depth, i.e. every window point back-projected at that
+ * depth and projected into the sources.  Needs phimvs_prepare of the same reference.
+ * hyp, cost: device planar 4*H*W; cost of an empty hypothesis is PHIMVS_COST_MAX. */
+int phimvs_phi_costs(phimvs_ctx* ctx, const float* hyp, float* cost);
+
+typedef struct {
+  double k1, k2, k3;   /* potentials of Eq. 7 and Eq. 8 (defaults 1, 0.1, 2)              */
+  int32_t iterations;  /* message-passing sweeps of the decoder (default 8)                */
+} phimvs_phi_params;
+
+void phimvs_default_phi_params(phimvs_phi_params* p);
+
+/* Selection (Sec. III-E): the hypothesis maps are subsampled to half size (node (X, Y)
+ * takes pixel (2X, 2Y)), the graph model (node states = hypotheses with potential
+ * (C_max - C) / k1 + k2, pixels with depth = fixed states, 4-connected edges with
+ * [k3 - min(1, relative depth difference)]^2) is decoded on the host by sequential
+ * tree-reweighted message passing, the decoded half-size depth is brought back to full
+ * size (pixel (x, y) takes node (x / 2, y / 2)) as the reference map, and each pixel
+ * without depth takes its hypothesis closest to the reference (lowest k on ties; stays
+ * empty without hypothesis or reference).  Pixels with depth keep it.  depth, depth_out:
+ * device H*W; hyp, cost: device planar 4*H*W.  Synchronises the stream. */
+int phimvs_phi_select(phimvs_ctx* ctx, int width, int height, const float* depth, const float* hyp,
+                      const float* cost, const phimvs_phi_params* p, float* depth_out);
+
+/* The graph-model decoder of phimvs_phi_select on host arrays (CPU only): depth H*W
+ * (> 0: fixed node), hyp and cost planar 4*H*W; label_out receives the chosen hypothesis
+ * (-1: fixed or no state) and depth_out its depth (0: no state).  Returns PHIMVS_OK or
+ * PHIMVS_E_ARG. */
+int phimvs_phi_decode_host(int width, int height, const float* depth, const float* hyp, const float* cost,
+                           double k1, double k2, double k3, double cost_max, int iterations, int32_t* label_out,
+                           float* depth_out);
+
+/* Normals of Eq. 10 (normalised by the norm): n = (X_up - X_down) x (X_left - X_right)
+ * of the back-projected 4-connected neighbours, turned to face the camera; 0 where the
+ * pixel or a neighbour has no depth or lies on the border.  view: the view whose K the
+ * depth map belongs to; depth device H*W, normal_out device H*W*3.  FP64. */
+int phimvs_phi_normals(phimvs_ctx* ctx, int view, const float* depth, float* normal_out);
+
 /* ---- diagnostics ---- */
 
 /* flags: PHIMVS_DIAG_COUNT counts the (pixel, hypothesis) pairs the evaluate-and-select

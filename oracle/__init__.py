@@ -293,3 +293,45 @@ def phi_normals(depth, K):
     if lib().oracle_phi_normals(_ptr(d, C.c_float), W, H, _ptr(Kd, C.c_double), _ptr(n, C.c_float)) != 0:
         raise ValueError("singular K")
     return n
+
+
+def phi_select(depth, hyp, cost, k1: float = 1.0, k2: float = 0.1, k3: float = 2.0, cmax: float = CMAX):
+    """Selection step of Sec. III-E for tiny maps (exact MAP by enumeration): the hypothesis
+    maps (H, W, 4) are subsampled to half size (node (X, Y) <- pixel (2X, 2Y)), the graph
+    model is decoded exactly, the decoded depth is brought back to full size (pixel (x, y)
+    <- node (x // 2, y // 2)) as the reference map, and each pixel without depth takes
+    its hypothesis closest to the reference (lowest k on ties; none without hypothesis or
+    reference).  -> depth (H, W) float32."""
+    d = np.asarray(depth, np.float32)
+    h = np.asarray(hyp, np.float32)
+    c = np.asarray(cost, np.float32)
+    d2, h2, c2 = d[::2, ::2], h[::2, ::2], c[::2, ::2]
+    lab, _ = phi_map_bruteforce(d2, h2, c2, k1, k2, k3, cmax)
+    H2, W2 = d2.shape
+    dec = np.zeros((H2, W2), np.float64)
+    for Y in range(H2):
+        for X in range(W2):
+            if d2[Y, X] > 0:
+                dec[Y, X] = d2[Y, X]
+            elif lab[Y, X] >= 0:
+                dec[Y, X] = h2[Y, X, lab[Y, X]]
+    H, W = d.shape
+    out = np.zeros((H, W), np.float32)
+    for y in range(H):
+        for x in range(W):
+            if d[y, x] > 0:
+                out[y, x] = d[y, x]
+                continue
+            ref = float(np.float32(dec[y // 2, x // 2]))
+            if not ref > 0:
+                continue
+            best, bd = 0.0, 0.0
+            for k in range(4):
+                hk = float(h[y, x, k])
+                if not hk > 0:
+                    continue
+                e = abs(hk - ref)
+                if best == 0.0 or e < bd:
+                    best, bd = hk, e
+            out[y, x] = best
+    return out

@@ -31,6 +31,8 @@ EXPORTS = ("phimvs_default_params", "phimvs_create", "phimvs_destroy", "phimvs_l
            "phimvs_patchmatch_batch", "phimvs_set_tuning", "phimvs_get_tuning", "phimvs_autotune",
            "phimvs_diag_enable", "phimvs_diag_read", "phimvs_check_reciprocal",
            "phimvs_default_filter_params", "phimvs_filter",
+           "phimvs_phi_hypotheses", "phimvs_phi_costs", "phimvs_default_phi_params", "phimvs_phi_select",
+           "phimvs_phi_decode_host", "phimvs_phi_normals",
            # learned initial-plane proposal (include/phimvs_net.h)
            "phimvs_net_create", "phimvs_net_destroy", "phimvs_net_last_error", "phimvs_net_set_stream",
            "phimvs_net_param_count", "phimvs_net_set_params", "phimvs_net_get_params", "phimvs_net_forward",
@@ -83,6 +85,22 @@ class FilterParams:
     max_angle_deg: float = 30.0
     max_reproj_px: float = 1.0
     min_consistent: int = 2
+
+
+class _PhiParams(C.Structure):
+    _fields_ = [("k1", C.c_double), ("k2", C.c_double), ("k3", C.c_double), ("iterations", C.c_int32)]
+
+
+@dataclass
+class PhiParams:
+    """Potentials and decoder sweeps of plane hypothesis inference (include/phimvs.h)."""
+    k1: float = 1.0
+    k2: float = 0.1
+    k3: float = 2.0
+    iterations: int = 8
+
+    def _c(self):
+        return _PhiParams(self.k1, self.k2, self.k3, self.iterations)
 
 
 @dataclass
@@ -151,6 +169,14 @@ def lib():
         L.phimvs_default_filter_params.restype = None
         L.phimvs_filter.argtypes = [vp, ip, C.POINTER(_DepthMap), ip, C.POINTER(C.c_int32), ip,
                                     C.POINTER(_FilterParams), fp, fp, vp]
+        L.phimvs_phi_hypotheses.argtypes = [vp, ip, ip, fp, fp]
+        L.phimvs_phi_costs.argtypes = [vp, fp, fp]
+        L.phimvs_default_phi_params.argtypes = [C.POINTER(_PhiParams)]
+        L.phimvs_default_phi_params.restype = None
+        L.phimvs_phi_select.argtypes = [vp, ip, ip, fp, fp, fp, C.POINTER(_PhiParams), fp]
+        L.phimvs_phi_decode_host.argtypes = [ip, ip, fp, fp, fp, C.c_double, C.c_double, C.c_double, C.c_double, ip,
+                                             vp, vp]
+        L.phimvs_phi_normals.argtypes = [vp, ip, fp, fp]
         L.phimvs_net_create.argtypes = [C.POINTER(vp), ip, vp]
         L.phimvs_net_destroy.argtypes = [vp]
         L.phimvs_net_destroy.restype = None
@@ -172,7 +198,7 @@ def lib():
         for name in EXPORTS:
             f = getattr(L, name)
             if name not in ("phimvs_default_params", "phimvs_destroy", "phimvs_last_error", "phimvs_net_destroy",
-                            "phimvs_net_last_error", "phimvs_default_filter_params"):
+                            "phimvs_net_last_error", "phimvs_default_filter_params", "phimvs_default_phi_params"):
                 f.restype = C.c_int
         L.phimvs_net_param_count.restype = C.c_int64
         _lib = L
@@ -318,6 +344,48 @@ class Context:
         self._check(lib().phimvs_filter(self.h, len(maps), arr, ref_map, nb, len(nbrs), C.byref(cp), od.data_ptr(),
                                         on.data_ptr(), oc.data_ptr()))
         return od, on, oc
+
+    # ------------------------------------------------------------------ plane hypothesis inference
+    def phi_hypotheses(self, depth):
+        """Depth hypotheses (4, H, W) of the pixels of ``depth`` (H, W) without depth (0 = none)."""
+        torch = self.torch
+        self._sync_stream()
+        d = depth.contiguous()
+        H, W = d.shape
+        hyp = torch.empty((4, H, W), dtype=torch.float32, device=self.device)
+        self._check(lib().phimvs_phi_hypotheses(self.h, W, H, d.data_ptr(), hyp.data_ptr()))
+        return hyp
+
+    def phi_costs(self, hyp):
+        """Matching cost (4, H, W) of the hypotheses under the prepared problem."""
+        torch = self.torch
+        self._sync_stream()
+        h = hyp.contiguous()
+        cost = torch.empty_like(h)
+        self._check(lib().phimvs_phi_costs(self.h, h.data_ptr(), cost.data_ptr()))
+        return cost
+
+    def phi_select(self, depth, hyp, cost, params: Optional["PhiParams"] = None):
+        """One hypothesis per pixel without depth (graph model decoded on the host) -> depth (H, W)."""
+        torch = self.torch
+        self._sync_stream()
+        d = depth.contiguous()
+        H, W = d.shape
+        out = torch.empty_like(d)
+        p = (params or PhiParams())._c()
+        self._check(lib().phimvs_phi_select(self.h, W, H, d.data_ptr(), hyp.contiguous().data_ptr(),
+                                            cost.contiguous().data_ptr(), C.byref(p), out.data_ptr()))
+        return out
+
+    def phi_normals(self, view: int, depth):
+        """Normals of Eq. 10 (H, W, 3) from a depth map of ``view``."""
+        torch = self.torch
+        self._sync_stream()
+        d = depth.contiguous()
+        H, W = d.shape
+        n = torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        self._check(lib().phimvs_phi_normals(self.h, view, d.data_ptr(), n.data_ptr()))
+        return n
 
     # ------------------------------------------------------------------ learned proposal
     def net_inputs(self, net: "Net", ref: int, srcs: Sequence[int]):
@@ -591,3 +659,23 @@ class Net:
                                              cost.contiguous().data_ptr(), float(max_cost), tgt.data_ptr(),
                                              mask.data_ptr()))
         return tgt, mask
+
+
+def phi_decode_host(depth, hyp, cost, params: Optional[PhiParams] = None, cost_max: float = COST_MAX):
+    """The host-side graph-model decoder of plane hypothesis inference on numpy arrays:
+    depth (H, W), hyp / cost (4, H, W) -> (labels (H, W) int32, depth (H, W) float32)."""
+    p = params or PhiParams()
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    h = np.ascontiguousarray(hyp, dtype=np.float32)
+    c = np.ascontiguousarray(cost, dtype=np.float32)
+    H, W = d.shape
+    if h.shape != (4, H, W) or c.shape != (4, H, W):
+        raise ValueError("hyp and cost must be (4, H, W)")
+    lab = np.zeros((H, W), np.int32)
+    out = np.zeros((H, W), np.float32)
+    fp = C.POINTER(C.c_float)
+    rc = lib().phimvs_phi_decode_host(W, H, d.ctypes.data_as(fp), h.ctypes.data_as(fp), c.ctypes.data_as(fp), p.k1,
+                                      p.k2, p.k3, cost_max, p.iterations, lab.ctypes.data, out.ctypes.data)
+    if rc != PHIMVS_OK:
+        raise PhimvsError(rc, "invalid decoder arguments")
+    return lab, out

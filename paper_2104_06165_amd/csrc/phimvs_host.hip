@@ -955,6 +955,97 @@ int phimvs_filter(phimvs_ctx* c, int n_maps, const phimvs_depth_map* maps, int r
   return PHIMVS_OK;
 }
 
+// ---------------------------------------------------------------------------- plane hypothesis inference
+
+int phimvs_phi_hypotheses(phimvs_ctx* c, int width, int height, const float* depth, float* hyp) {
+  if (!c) return PHIMVS_E_ARG;
+  if (width < 1 || height < 1 || !depth || !hyp) return fail(c, PHIMVS_E_ARG, "invalid size or null array");
+  HIPCHECK(c, hipSetDevice(c->device));
+  HIPCHECK(c, launch_phi_hypotheses(depth, width, height, hyp, c->stream));
+  return PHIMVS_OK;
+}
+
+int phimvs_phi_costs(phimvs_ctx* c, const float* hyp, float* cost) {
+  int rc = need_prepared(c);
+  if (rc) return rc;
+  if (!hyp || !cost) return fail(c, PHIMVS_E_ARG, "null array");
+  HIPCHECK(c, hipSetDevice(c->device));
+  const Job& J = c->single.jobs[0];
+  const size_t n = (size_t)J.A.W * J.A.H;
+  if ((rc = ensure(c, c->io_d, 4 * n))) return rc;
+  for (int k = 0; k < 4; ++k) {
+    HIPCHECK(c, launch_phi_planes(hyp + k * n, n, c->io_d.p, c->stream));
+    if ((rc = phimvs_eval_cost(c, c->io_d.p, cost + k * n, nullptr, nullptr, 1))) return rc;
+  }
+  HIPCHECK(c, launch_phi_mask_cost(hyp, 4 * n, PHIMVS_COST_MAX, cost, c->stream));
+  return PHIMVS_OK;
+}
+
+void phimvs_default_phi_params(phimvs_phi_params* p) {
+  if (!p) return;
+  p->k1 = 1.0;
+  p->k2 = 0.1;
+  p->k3 = 2.0;
+  p->iterations = 8;
+}
+
+int phimvs_phi_select(phimvs_ctx* c, int width, int height, const float* depth, const float* hyp, const float* cost,
+                      const phimvs_phi_params* pp, float* depth_out) {
+  if (!c) return PHIMVS_E_ARG;
+  if (width < 1 || height < 1 || !depth || !hyp || !cost || !depth_out)
+    return fail(c, PHIMVS_E_ARG, "invalid size or null array");
+  phimvs_phi_params p;
+  phimvs_default_phi_params(&p);
+  if (pp) p = *pp;
+  HIPCHECK(c, hipSetDevice(c->device));
+  const int W = width, H = height;
+  const size_t n = (size_t)W * H;
+  std::vector<float> d(n), hy(4 * n), co(4 * n);
+  HIPCHECK(c, hipMemcpyAsync(d.data(), depth, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(hy.data(), hyp, 4 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(co.data(), cost, 4 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  // half size: node (X, Y) takes pixel (2X, 2Y)
+  const int W2 = (W + 1) / 2, H2 = (H + 1) / 2;
+  const size_t n2 = (size_t)W2 * H2;
+  std::vector<float> d2(n2), h2(4 * n2), c2(4 * n2), dec(n2);
+  std::vector<int32_t> lab(n2);
+  for (int Y = 0; Y < H2; ++Y)
+    for (int X = 0; X < W2; ++X) {
+      const size_t q = (size_t)Y * W2 + X, src = (size_t)(2 * Y) * W + 2 * X;
+      d2[q] = d[src];
+      for (int k = 0; k < 4; ++k) {
+        h2[k * n2 + q] = hy[k * n + src];
+        c2[k * n2 + q] = co[k * n + src];
+      }
+    }
+  if (phimvs_phi_decode_host(W2, H2, d2.data(), h2.data(), c2.data(), p.k1, p.k2, p.k3, PHIMVS_COST_MAX,
+                             p.iterations, lab.data(), dec.data()) != PHIMVS_OK)
+    return fail(c, PHIMVS_E_ARG, "invalid PHI parameters (k1 > 0, k2 > 0, k3 > 1, iterations >= 0)");
+  // back to full size: pixel (x, y) takes node (x / 2, y / 2)
+  std::vector<float> ref(n);
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) ref[(size_t)y * W + x] = dec[(size_t)(y / 2) * W2 + x / 2];
+  int rc;
+  if ((rc = ensure(c, c->io_a, n))) return rc;
+  HIPCHECK(c, hipMemcpyAsync(c->io_a.p, ref.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(c, launch_phi_select(depth, hyp, c->io_a.p, W, H, depth_out, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));  // the host reference map goes out of scope
+  return PHIMVS_OK;
+}
+
+int phimvs_phi_normals(phimvs_ctx* c, int view, const float* depth, float* normal_out) {
+  if (!c) return PHIMVS_E_ARG;
+  if (view < 0 || view >= (int)c->views.size()) return fail(c, PHIMVS_E_ARG, "view index out of range");
+  if (!depth || !normal_out) return fail(c, PHIMVS_E_ARG, "null array");
+  HIPCHECK(c, hipSetDevice(c->device));
+  const ViewData& V = c->views[view];
+  PhiCam cam{};
+  if (!inv33(V.K, cam.Kinv)) return fail(c, PHIMVS_E_ARG, "singular K");
+  HIPCHECK(c, launch_phi_normals(depth, V.W, V.H, cam, normal_out, c->stream));
+  return PHIMVS_OK;
+}
+
 // ---------------------------------------------------------------------------- batches
 
 int phimvs_patchmatch_batch(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, int iters, int use_graph) {

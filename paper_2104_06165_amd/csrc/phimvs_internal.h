@@ -106,6 +106,17 @@ struct FilterArgs {
 };
 hipError_t launch_filter(const FilterArgs& a, hipStream_t st);
 
+// plane hypothesis inference
+struct PhiCam {
+  double Kinv[9];
+};
+hipError_t launch_phi_hypotheses(const float* depth, int W, int H, float* hyp, hipStream_t st);
+hipError_t launch_phi_planes(const float* hyp, size_t n, float* planes, hipStream_t st);
+hipError_t launch_phi_mask_cost(const float* hyp, size_t n, float cmax, float* cost, hipStream_t st);
+hipError_t launch_phi_select(const float* depth, const float* hyp, const float* ref, int W, int H, float* out,
+                             hipStream_t st);
+hipError_t launch_phi_normals(const float* depth, int W, int H, const PhiCam& cam, float* normal, hipStream_t st);
+
 // a view of a context's scene, for the proposal network's host code
 struct ViewInfo {
   int W, H;

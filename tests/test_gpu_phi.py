@@ -1,0 +1,138 @@
+"""GPU parity of plane hypothesis inference (Sec. III-E) through the C ABI against the
+oracle: hypotheses (FP64 line fits, bitwise), their costs (the cost kernel on
+fronto-parallel planes, against the PatchMatch oracle), the selection (decoded on the
+host; a half-size chain, where the decoder is exact, against the oracle's exact MAP),
+and the normals of Eq. 10 (bitwise); then the whole chain on a filtered depth map."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2104_06165_amd as pm  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return sg.workload_scene("tiny", device="cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx(tiny):
+    c = pm.Context(0)
+    c.set_scene(tiny)
+    yield c
+    c.close()
+
+
+def holey_depth(tiny, seed=3, drop_textureless=True):
+    """Ground-truth depth of the tiny scene with random blobs (and the texture-less planes) removed."""
+    r = np.random.default_rng(seed)
+    d = tiny.gt_depth.astype(np.float32).copy()
+    if drop_textureless:
+        d[~tiny.textured[tiny.gt_plane]] = 0.0
+    for _ in range(12):
+        y, x = r.integers(0, d.shape[0]), r.integers(0, d.shape[1])
+        d[max(0, y - 4):y + 5, max(0, x - 6):x + 7] = 0.0
+    return d
+
+
+def test_hypotheses_parity(ctx, tiny):
+    d = holey_depth(tiny)
+    g = ctx.phi_hypotheses(torch.from_numpy(d).cuda()).cpu().numpy().transpose(1, 2, 0)
+    o = oracle.phi_hypotheses(d)
+    say(f"hypotheses: {(o > 0).mean():.3f} of slots filled, bitwise equal {(g == o).mean():.6f}")
+    assert np.array_equal(g, o)
+
+
+def test_costs_parity(ctx, tiny):
+    d = holey_depth(tiny)
+    srcs = list(range(1, len(tiny.images)))
+    params = pm.Params(top_k=len(srcs), sigma_spatial_px=5.0)
+    ctx.prepare(0, srcs, 11, 1, params)
+    hyp = ctx.phi_hypotheses(torch.from_numpy(d).cuda())
+    cost = ctx.phi_costs(hyp).cpu().numpy()
+    pb = oracle.Problem.from_scene(tiny, 11, 1, top_k=len(srcs), bilateral=True, sigma_s=5.0, sigma_c=12.0)
+    m = pb.valid_mask()
+    h = hyp.cpu().numpy()
+    for k in range(4):
+        planes = np.zeros(d.shape + (4,))
+        planes[..., 2] = -1.0
+        planes[..., 3] = np.where(h[k] > 0, h[k], 1.0)
+        oc, _, _ = oracle.eval_cost(pb, planes)
+        oc = np.where(h[k] > 0, oc, pm.COST_MAX)
+        sel = m & (h[k] > 0)
+        ok = np.abs(cost[k][sel] - oc[sel]) <= 1e-4
+        say(f"costs k={k}: {sel.sum()} hypotheses, within 1e-4 {ok.mean():.6f}, "
+            f"bitwise {(cost[k][sel] == oc[sel].astype(np.float32)).mean():.6f}")
+        assert ok.mean() >= 0.999
+        assert np.all(cost[k][h[k] <= 0] == pm.COST_MAX)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_selection_parity_on_a_chain(ctx, seed):
+    """A 2 x 14 map: its half-size graph is a 1 x 7 chain, where the decoder is exact."""
+    r = np.random.default_rng(seed)
+    d = np.where(r.uniform(size=(2, 14)) < 0.35, r.uniform(2, 5, (2, 14)), 0.0).astype(np.float32)
+    hyp = oracle.phi_hypotheses(d)
+    hyp[(hyp > 0) & (r.uniform(size=hyp.shape) < 0.2)] = 0.0
+    cost = r.uniform(0, 2, hyp.shape).astype(np.float32)
+    g = ctx.phi_select(torch.from_numpy(d).cuda(), torch.from_numpy(hyp.transpose(2, 0, 1).copy()).cuda(),
+                       torch.from_numpy(cost.transpose(2, 0, 1).copy()).cuda(), pm.PhiParams(iterations=12))
+    o = oracle.phi_select(d, hyp, cost)
+    assert np.array_equal(g.cpu().numpy(), o)
+
+
+def test_normals_parity(ctx, tiny):
+    d = tiny.gt_depth.astype(np.float32).copy()
+    d[30:40, 50:70] = 0.0
+    g = ctx.phi_normals(0, torch.from_numpy(d).cuda()).cpu().numpy()
+    o = oracle.phi_normals(d, tiny.K[0])
+    assert np.array_equal(g, o)
+    # away from plane boundaries they are the ground-truth normals
+    inner = (o != 0).any(-1)
+    err = np.degrees(np.arccos(np.clip((o * tiny.gt_normal).sum(-1), -1, 1)))
+    say(f"normals: median angle to ground truth {np.median(err[inner]):.3f} deg")
+    assert np.median(err[inner]) < 1.0
+
+
+def test_phi_fills_holes_of_a_filtered_map(ctx, tiny):
+    """Holes inside planes (the case the method is for: pixels of a plane the search left
+    empty) get filled, and the filled depths are near the ground truth."""
+    d = holey_depth(tiny, seed=5, drop_textureless=False)
+    srcs = list(range(1, len(tiny.images)))
+    ctx.prepare(0, srcs, 11, 1, pm.Params(top_k=len(srcs), sigma_spatial_px=5.0))
+    D = torch.from_numpy(d).cuda()
+    hyp = ctx.phi_hypotheses(D)
+    cost = ctx.phi_costs(hyp)
+    out = ctx.phi_select(D, hyp, cost).cpu().numpy()
+    holes = d <= 0
+    filled = holes & (out > 0)
+    rel = np.abs(out - tiny.gt_depth) / tiny.gt_depth
+    say(f"PHI: {holes.mean():.3f} of pixels empty, {filled.sum() / holes.sum():.3f} of them filled, "
+        f"{(rel[filled] < 0.05).mean():.3f} of the filled within 5% of ground truth")
+    assert filled.sum() / holes.sum() > 0.9
+    assert (rel[filled] < 0.05).mean() > 0.9
+    assert np.array_equal(out[~holes], d[~holes])
+
+
+def test_phi_argument_errors(ctx, tiny):
+    with pytest.raises(pm.PhimvsError):
+        ctx.phi_normals(99, torch.zeros((4, 4), device="cuda"))
+    d = torch.zeros((4, 4), device="cuda")
+    h = torch.zeros((4, 4, 4), device="cuda")
+    with pytest.raises(pm.PhimvsError):
+        ctx.phi_select(d, h, h, pm.PhiParams(k3=0.5))

@@ -1,0 +1,89 @@
+"""The library's host-side graph-model decoder of plane hypothesis inference (Sec. III-E;
+the paper runs it on the CPU, so does the library) against the oracle's exact MAP on
+tiny grids: exact on chains (a tree, where sequential tree-reweighted message passing
+is exact), and on small loopy grids equal to the optimum or within a small margin of it.
+No GPU needed: the decoder takes host arrays."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2104_06165_amd as pm
+
+
+def log_potential(depth, hyp, cost, labels, k1, k2, k3, cmax=2.0):
+    """Sum of log potentials of a labelling (-1: the fixed depth)."""
+    H, W = depth.shape
+
+    def value(y, x):
+        l = labels[y, x]
+        if depth[y, x] > 0:
+            return float(depth[y, x])
+        return float(hyp[y, x, l]) if l >= 0 else 0.0
+
+    e = 0.0
+    for y in range(H):
+        for x in range(W):
+            l = labels[y, x]
+            if depth[y, x] <= 0 and l >= 0:
+                e += np.log((cmax - float(cost[y, x, l])) / k1 + k2)
+            v = value(y, x)
+            for yy, xx in ((y, x + 1), (y + 1, x)):
+                if yy < H and xx < W:
+                    u = value(yy, xx)
+                    if v > 0 and u > 0:
+                        rel = (v - u) / u if v > u else (u - v) / v
+                        e += np.log((k3 - min(1.0, rel)) ** 2)
+    return e
+
+
+def random_problem(r, H, W, fixed_frac=0.2, missing_frac=0.15):
+    depth = np.where(r.uniform(size=(H, W)) < fixed_frac, r.uniform(2, 5, (H, W)), 0.0).astype(np.float32)
+    hyp = r.uniform(2, 5, (H, W, 4)).astype(np.float32)
+    hyp[r.uniform(size=(H, W, 4)) < missing_frac] = 0.0
+    hyp[depth > 0] = 0.0
+    cost = r.uniform(0, 2, (H, W, 4)).astype(np.float32)
+    return depth, hyp, cost
+
+
+@pytest.mark.parametrize("W", [2, 4, 7])
+def test_decoder_is_exact_on_chains(W):
+    r = np.random.default_rng(W)
+    k1, k2, k3 = 1.0, 0.1, 2.0
+    for _ in range(15):
+        depth, hyp, cost = random_problem(r, 1, W)
+        lab_o, e_o = oracle.phi_map_bruteforce(depth, hyp, cost, k1, k2, k3)
+        lab, dep = pm.phi_decode_host(depth, hyp.transpose(2, 0, 1), cost.transpose(2, 0, 1),
+                                      pm.PhiParams(k1, k2, k3, 10))
+        e = log_potential(depth, hyp, cost, lab, k1, k2, k3)
+        assert np.isclose(e, e_o, rtol=1e-9, atol=1e-12), (e, e_o)
+        # depths follow the labels
+        exp = np.where(depth > 0, depth, np.take_along_axis(hyp, np.maximum(lab, 0)[..., None], 2)[..., 0])
+        exp = np.where((depth <= 0) & (lab < 0), 0.0, exp)
+        assert np.allclose(dep, exp)
+
+
+def test_decoder_on_small_loopy_grids():
+    r = np.random.default_rng(7)
+    k1, k2, k3 = 1.0, 0.1, 2.0
+    gaps = []
+    for _ in range(25):
+        depth, hyp, cost = random_problem(r, 3, 3)
+        _, e_o = oracle.phi_map_bruteforce(depth, hyp, cost, k1, k2, k3)
+        lab, _ = pm.phi_decode_host(depth, hyp.transpose(2, 0, 1), cost.transpose(2, 0, 1), pm.PhiParams(k1, k2, k3, 20))
+        e = log_potential(depth, hyp, cost, lab, k1, k2, k3)
+        assert e <= e_o + 1e-9  # never above the exact optimum (sanity of both)
+        gaps.append((e_o - e) / abs(e_o))
+    gaps = np.array(gaps)
+    assert (gaps < 1e-9).mean() >= 0.8  # the optimum itself in most cases
+    assert gaps.max() < 0.05
+
+
+def test_decoder_arguments():
+    d = np.zeros((2, 2), np.float32)
+    h = np.zeros((4, 2, 2), np.float32)
+    with pytest.raises(pm.PhimvsError):
+        pm.phi_decode_host(d, h, h, pm.PhiParams(k1=0.0))
+    with pytest.raises(ValueError):
+        pm.phi_decode_host(d, h[:3], h)
+    lab, dep = pm.phi_decode_host(d, h, h)  # no states anywhere
+    assert np.all(lab == -1) and np.all(dep == 0)
