@@ -144,6 +144,7 @@ def bench_batched(args):
         tap_views += nominal_tap_views(valid, len(j["srcs"]), (2 * R + 1) ** 2, iters)
     achieved = tap_views * FLOPS_PER_TAP_VIEW / (ms_batch * 1e-3) / 1e12
     filt = bench_filter(ctx, mv, jobs, outs)
+    phi = bench_phi(ctx, mv, jobs, outs)
     line = {
         "metric": "ms per batch of 24 mixed-size depth maps (8 it)", "value": ms_batch, "unit": "ms",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch,
@@ -159,6 +160,7 @@ def bench_batched(args):
                      "note": "whole-sequence time; nominal tap-views (all 11 candidates per iteration)"},
         "autotune": [r.__dict__ for r in allr],
         "consistency_filter": filt,
+        "plane_hypothesis_inference": phi,
     }
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -197,6 +199,78 @@ def bench_filter(ctx, mv, jobs, outs, reps=5):
             "roofline": {"bound": "hbm", "achieved": algo_bytes / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
                          "frac": algo_bytes / (ms * 1e-3) / 1e9 / 8000.0, "traffic": None,
                          "note": "whole-batch time over 24 launches (host launch gaps included)"}}
+
+
+def bench_phi(ctx, mv, jobs, outs, size=None):
+    """Plane hypothesis inference (Sec. III-E) on the references (of one size class if
+    given): each depth map is filtered by geometric consistency against the other
+    references among its sources, its empty pixels get hypotheses, costs, a selection (graph
+    model decoded on the host) and normals, and the filled maps are filtered again against
+    each other.  Reported: completeness (pixels with depth) and accuracy against the
+    rendered depth at each stage, the GPU time of hypotheses + costs + normals and the host
+    time of the selection."""
+    import torch
+
+    import paper_2104_06165_amd as pm
+
+    maps = [(j["ref"], o["depth"], o["normal"]) for j, o in zip(jobs, outs)]
+    index = {j["ref"]: i for i, j in enumerate(jobs)}
+    sel = [i for i, j in enumerate(jobs) if size is None or mv.images[j["ref"]].shape[::-1] == tuple(size)]
+    fparams = pm.FilterParams()
+    filtered = {}
+    for i, j in enumerate(jobs):
+        nb = [index[v] for v in j["srcs"] if v in index]
+        d, n, _ = ctx.filter(maps, i, nb, fparams)
+        filtered[i] = (d, n)
+    torch.cuda.synchronize()
+    gpu_ms = host_ms = 0.0
+    filled = {}
+    for i in sel:
+        j = jobs[i]
+        d, n = filtered[i]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.prepare(j["ref"], j["srcs"], j["window"], j["dilation"], j["params"])
+        hyp = ctx.phi_hypotheses(d)
+        cost = ctx.phi_costs(hyp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dp = ctx.phi_select(d, hyp, cost)
+        t2 = time.perf_counter()
+        npn = ctx.phi_normals(j["ref"], dp)
+        new = (d <= 0) & (dp > 0)
+        nf = torch.where(new[..., None], npn, n).contiguous()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        gpu_ms += (t1 - t0 + t3 - t2) * 1e3
+        host_ms += (t2 - t1) * 1e3
+        filled[i] = (dp, nf)
+    # second filter pass over the filled maps (the others keep their filtered maps)
+    maps2 = [(j["ref"],) + (filled[i] if i in filled else filtered[i]) for i, j in enumerate(jobs)]
+    final = {}
+    for i in sel:
+        nb = [index[v] for v in jobs[i]["srcs"] if v in index]
+        final[i] = ctx.filter(maps2, i, nb, fparams)[0]
+    torch.cuda.synchronize()
+
+    def stats(get):
+        n_px = hit = good1 = good5 = 0
+        for i in sel:
+            gt = mv.gt_depths[jobs[i]["ref"]]
+            d = get(i).cpu().numpy()
+            m = d > 0
+            rel = np.abs(d[m] - gt[m]) / gt[m]
+            n_px += d.size
+            hit += int(m.sum())
+            good1 += int((rel < 0.01).sum())
+            good5 += int((rel < 0.05).sum())
+        return {"completeness": hit / n_px, "within_1pct_of_filled": good1 / max(hit, 1),
+                "within_5pct_of_filled": good5 / max(hit, 1)}
+
+    return {"references": len(sel), "pixels": int(sum(mv.images[jobs[i]["ref"]].size for i in sel)),
+            "raw": stats(lambda i: outs[i]["depth"]), "filtered": stats(lambda i: filtered[i][0]),
+            "phi_filled": stats(lambda i: filled[i][0]), "phi_filtered_again": stats(lambda i: final[i]),
+            "gpu_ms": gpu_ms, "host_selection_ms": host_ms}
 
 
 def learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, random_ms, reps=3):

@@ -496,6 +496,7 @@ class MultiViewScene:
     sources: List[List[int]]
     windows: List[tuple]  # (window, dilation) per reference
     seed: int = 0
+    gt_depths: dict = field(default_factory=dict)  # reference camera -> rendered depth (H, W)
 
     @property
     def K(self):
@@ -548,7 +549,7 @@ def make_multiview_scene(seed: int = 4, grid=(5, 8), az_deg=20.0, el_deg=8.0, n_
             dirs.append((math.radians(az), math.radians(el)))
     Q = _random_rotation(rng)
     q = rng.uniform(-5, 5, 3)
-    images, cams, dranges = [], [], []
+    images, cams, dranges, gts = [], [], [], {}
     for ci, (az, el) in enumerate(dirs):
         w, h = sizes.get(ci, other_size)
         K = _intrinsics(w, h)
@@ -559,6 +560,8 @@ def make_multiview_scene(seed: int = 4, grid=(5, 8), az_deg=20.0, el_deg=8.0, n_
         images.append(img)
         good = np.isfinite(dep) & (dep > 0)
         dranges.append((0.9 * float(dep[good].min()), 1.1 * float(dep[good].max())))
+        if ci in sizes:
+            gts[ci] = dep.astype(np.float32)
         cams.append(Camera(K, Rm @ Q.T, -Rm @ (Q.T @ q + Cm), w, h))
     # sources: the nearest cameras by viewing direction, 6-12 of them
     centers = np.array([[math.sin(az) * math.cos(el), math.sin(el), math.cos(az) * math.cos(el)] for az, el in dirs])
@@ -569,7 +572,7 @@ def make_multiview_scene(seed: int = 4, grid=(5, 8), az_deg=20.0, el_deg=8.0, n_
         ang[cam] = np.inf
         sources.append(np.argsort(ang, kind="stable")[:nsrc].tolist())
         wins.append(windows[cam])
-    return MultiViewScene(images, cams, np.array(dranges), ref_ids, sources, wins, seed)
+    return MultiViewScene(images, cams, np.array(dranges), ref_ids, sources, wins, seed, gts)
 
 
 def workload_scene(name: str, device=None, seed: Optional[int] = None) -> Scene:
