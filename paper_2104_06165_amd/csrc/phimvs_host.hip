@@ -52,6 +52,7 @@ struct Batch {
   Job* d_jobs = nullptr;
   size_t d_cap = 0;
   int total_tiles = 0, total_cblk = 0, max_r = 0, max_taps = 0, tile_rows = 4;
+  int xcd_len[8] = {};
   std::string layout_key;        // problems + tile shape the state was built for
   // captured launch sequence
   hipGraph_t graph = nullptr;
@@ -345,6 +346,20 @@ void layout(Batch& b, int tile_rows) {
   }
   b.total_tiles = t;
   b.total_cblk = k;
+  // XCD k takes the k-th of 8 bands of every job, so every XCD gets the same share of each
+  // job's work (jobs differ in source count and window) and a compact band of each image
+  for (int x = 0; x < 8; ++x) b.xcd_len[x] = 0;
+  for (Job& J : b.jobs) {
+    const int T = J.tiles_x * J.tiles_y;
+    for (int x = 0; x < 8; ++x) {
+      J.xband[x] = (int)((int64_t)T * x / 8);
+      J.xoff[x] = b.xcd_len[x];
+    }
+    for (int x = 0; x < 8; ++x) {
+      const int end = x + 1 < 8 ? J.xband[x + 1] : T;
+      b.xcd_len[x] += end - J.xband[x];
+    }
+  }
 }
 
 int upload_jobs(phimvs_ctx* c, Batch& b) {
@@ -367,11 +382,12 @@ Launch base_launch(const Batch& b) {
   L.tile_rows = b.tile_rows;
   L.total_tiles = b.total_tiles;
   L.total_cblk = b.total_cblk;
+  for (int x = 0; x < 8; ++x) L.xcd_len[x] = b.xcd_len[x];
   return L;
 }
 
 int eval_grid(const phimvs_ctx* c, const Batch& b, bool persistent) {
-  if (!persistent) return ((b.total_tiles + 7) / 8) * 8;
+  if (!persistent) return 8 * *std::max_element(b.xcd_len, b.xcd_len + 8);
   const int wgs = std::max(1, c->tuning.wgs_per_cu) * c->n_cu;
   return ((std::min(wgs, b.total_tiles) + 7) / 8) * 8;
 }

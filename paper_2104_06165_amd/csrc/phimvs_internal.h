@@ -54,6 +54,8 @@ struct Job {
   float* planes_out;
   int tile0;               // first evaluate tile of this job
   int tiles_x, tiles_y;
+  int xband[8];            // XCD k evaluates local tiles [xband[k], xband[k + 1]) (xband[8] = all tiles)
+  int xoff[8];             // where that band starts in XCD k's list (bands of earlier jobs first)
   int cblk0;               // first candidate / unpack block of this job
   int cblk_x;              // blocks per row
 };
@@ -64,6 +66,7 @@ struct Launch {
   int colour, iteration, ncand, mode;  // mode 0: initialise, 1: update, 2: evaluate
   int tile_rows;                       // rows of an evaluate tile (4, 2 or 1); 256 / tile_rows columns
   int total_tiles, total_cblk;
+  int xcd_len[8];                      // evaluate tiles of each XCD's list
   int persistent;                      // evaluate: tiles pulled from per-XCD queues
   unsigned int* queue;                 // 8 counters, zero at launch (persistent only)
   unsigned long long* count;           // optional: + (pixel, hypothesis) pairs scored

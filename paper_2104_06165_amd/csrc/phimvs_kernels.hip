@@ -447,9 +447,11 @@ __device__ float plane_cost(const Args& A, const RefPix& rp, const float* __rest
 
 // ---------------------------------------------------------------------------- job lookup
 // The job owning global index g of a work space whose jobs start at first(j) (ascending).
-__device__ __forceinline__ int job_of_tile(const Job* __restrict__ jobs, int n_jobs, int g) {
+// The job owning position i of XCD x's tile list (its bands in job order; a job whose band
+// is empty shares its start with the next job and is passed over).
+__device__ __forceinline__ int job_of_xcd_tile(const Job* __restrict__ jobs, int n_jobs, int x, int i) {
   int j = 0;
-  while (j + 1 < n_jobs && g >= jobs[j + 1].tile0) ++j;
+  while (j + 1 < n_jobs && i >= jobs[j + 1].xoff[x]) ++j;
   return j;
 }
 
@@ -717,32 +719,32 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   gl(A.cost[colour])[cidx] = bc;
 }
 
-// Non-persistent: one workgroup per tile, tiles given to the 8 XCDs in contiguous ranges
-// (workgroup b runs on XCD b % 8), so each XCD's L2 serves a compact band of the image.
-// Persistent: a fixed grid; each workgroup pulls tiles from its XCD's queue over the same
-// contiguous range, so uneven jobs balance dynamically within an XCD.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void eval_kernel(const Job* __restrict__ jobs, Launch L) {
+// Each XCD has its own list of tiles: the k-th of 8 contiguous bands of every job, so each
+// XCD's L2 serves a compact band of each image and every XCD gets the same share of every
+// job.  Non-persistent: workgroup b runs on XCD b % 8 and takes position b / 8 of that
+// XCD's list.  Persistent: a fixed grid; each workgroup pulls positions from its XCD's
+// queue, so uneven tiles balance dynamically within an XCD.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void eval_kernel(
+    const Job* __restrict__ jobs, Launch L) {
   extern __shared__ float lds[];
   __shared__ int next_tile;
   const int xcd = blockIdx.x & 7;
-  const int per = (L.total_tiles + 7) / 8;
-  const int begin = xcd * per;
-  const int end = min(L.total_tiles, begin + per);
+  const int len = L.xcd_len[xcd];
   if (!L.persistent) {
-    const int tile = begin + (int)(blockIdx.x >> 3);
-    if (tile >= end) return;
-    const int jb = job_of_tile(jobs, L.n_jobs, tile);
-    eval_tile(jobs[jb], L, tile, lds);
+    const int i = (int)(blockIdx.x >> 3);
+    if (i >= len) return;
+    const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
+    eval_tile(J, L, J.tile0 + J.xband[xcd] + (i - J.xoff[xcd]), lds);
     return;
   }
   for (;;) {
-    if (threadIdx.x == 0) next_tile = begin + (int)atomicAdd(&L.queue[xcd], 1u);
+    if (threadIdx.x == 0) next_tile = (int)atomicAdd(&L.queue[xcd], 1u);
     __syncthreads();
-    const int tile = next_tile;
+    const int i = next_tile;
     __syncthreads();
-    if (tile >= end) return;
-    const int jb = job_of_tile(jobs, L.n_jobs, tile);
-    eval_tile(jobs[jb], L, tile, lds);
+    if (i >= len) return;
+    const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
+    eval_tile(J, L, J.tile0 + J.xband[xcd] + (i - J.xoff[xcd]), lds);
     __syncthreads();  // the next tile re-stages LDS
   }
 }
