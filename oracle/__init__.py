@@ -54,6 +54,7 @@ class _Problem(C.Structure):
         ("eps_v", C.c_double),
         ("eps_c", C.c_double),
         ("seed", C.c_uint64),
+        ("tap_radius", C.c_int32),
     ]
 
 
@@ -106,7 +107,8 @@ class Problem:
 
     def __init__(self, images: Sequence[np.ndarray], K, R, t, depth_range, window: int, dilation: int,
                  top_k: int = 0, bilateral: bool = True, sigma_s: Optional[float] = None,
-                 sigma_c: float = 12.0, eps_v: float = 1e-4, eps_c: float = 1e-4, seed: int = 0x5EED):
+                 sigma_c: float = 12.0, eps_v: float = 1e-4, eps_c: float = 1e-4, seed: int = 0x5EED,
+                 tap_radius: int = 0):
         self.images = [np.ascontiguousarray(im, dtype=np.float32) for im in images]
         n = len(self.images)
         self.K = np.ascontiguousarray(np.asarray(K, dtype=np.float64).reshape(n, 9))
@@ -117,12 +119,12 @@ class Problem:
         self._imgptrs = (C.POINTER(C.c_float) * n)(*[_ptr(im, C.c_float) for im in self.images])
         if sigma_s is None:
             sigma_s = (window - 1) / 2.0
-        self.window, self.dilation, self.top_k = window, dilation, top_k
+        self.window, self.dilation, self.top_k, self.tap_radius = window, dilation, top_k, tap_radius
         self.s = _Problem(n, _ptr(self.w, C.c_int32), _ptr(self.h, C.c_int32), self._imgptrs,
                           _ptr(self.K, C.c_double), _ptr(self.R, C.c_double), _ptr(self.t, C.c_double),
                           float(depth_range[0]), float(depth_range[1]), window, dilation, top_k,
                           1 if bilateral else 0, float(sigma_s), float(sigma_c), float(eps_v), float(eps_c),
-                          int(seed) & 0xFFFFFFFFFFFFFFFF)
+                          int(seed) & 0xFFFFFFFFFFFFFFFF, int(tap_radius))
 
     @property
     def W(self):
@@ -141,6 +143,8 @@ class Problem:
         return cls(scene.images, scene.K, scene.R, scene.t, scene.depth_range, window, dilation, top_k, **kw)
 
     def radius(self):
+        if self.tap_radius > 0:
+            return (self.window - 1) // 2
         return self.dilation * ((self.window - 1) // (2 * self.dilation))
 
     def valid_mask(self):

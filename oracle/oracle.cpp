@@ -145,6 +145,7 @@ typedef struct {
   int32_t window, dilation, top_k, bilateral;
   double sigma_s, sigma_c, eps_v, eps_c;
   uint64_t seed;
+  int32_t tap_radius;  // > 0: the window-resize scheme, r_now = tap_radius taps per side
 } oracle_problem;
 
 }  // extern "C"
@@ -183,6 +184,13 @@ template <typename T>
 struct Solver {
   const oracle_problem* pb;
   int W, H, n_src, R_now, s;
+  // window-resize scheme (Sec. III-C, Fig. 4, Table III): r_now taps per side spread over
+  // the original radius r_orig, spacing s = r_orig / r_now (not necessarily an integer);
+  // tap k sits at offset off[k] = s k (rounded to T), reference values are interpolated
+  bool frac = false;
+  int r_orig = 0;
+  double sf_d = 0.0;
+  std::vector<T> off;  // 2 R_now + 1 offsets, k = -R_now .. R_now
   double Kinv_d[9];     // reference K^-1 in FP64
   T Kinv[9];            // ... rounded to T
   std::vector<T> M;     // n_src * 9: K_j R_rel K_0^-1
@@ -197,6 +205,15 @@ struct Solver {
     n_src = p->n_views - 1;
     s = p->dilation;
     R_now = (p->window - 1) / (2 * p->dilation);
+    frac = p->tap_radius > 0;
+    if (frac) {
+      r_orig = (p->window - 1) / 2;
+      R_now = p->tap_radius;
+      s = 1;
+      sf_d = (double)r_orig / (double)R_now;
+    }
+    off.resize(2 * R_now + 1);
+    for (int k = -R_now; k <= R_now; ++k) off[k + R_now] = frac ? (T)sf_d * (T)k : (T)(s * k);
     if (!mat3_inverse(p->K, Kinv_d)) return false;
     for (int i = 0; i < 9; ++i) Kinv[i] = (T)Kinv_d[i];
     M.assign(9 * n_src, T(0));
@@ -225,8 +242,15 @@ struct Solver {
   }
 
   bool pixel_valid(int x, int y) const {
-    int r = s * R_now;
+    int r = frac ? r_orig : s * R_now;
     return x - r >= 0 && x + r <= W - 1 && y - r >= 0 && y + r <= H - 1;
+  }
+
+  // reference value of tap (k1, k2) (indices -R_now .. R_now) of pixel (x, y): a texel,
+  // or in the window-resize scheme the bilinear value at (x + off[k1], y + off[k2])
+  T ref_tap(int x, int y, int k1, int k2) const {
+    if (!frac) return ref(x + s * k1, y + s * k2);
+    return sample(0, (T)x + off[k1 + R_now], (T)y + off[k2 + R_now]);
   }
 
   T ref(int x, int y) const { return (T)pb->images[0][(size_t)y * W + x]; }
@@ -250,12 +274,13 @@ struct Solver {
   // bilateral weight factors
   T w_colour(T da) const {
     if (!pb->bilateral) return T(1);
-    double d = (double)da;
+    // an interpolated reference difference is taken at the nearest integer grey level
+    double d = frac ? (double)std::nearbyint(std::fabs(da)) : (double)da;
     return (T)std::exp(-(d * d) / (2.0 * pb->sigma_c * pb->sigma_c));
   }
   T w_space(int k1, int k2) const {
     if (!pb->bilateral) return T(1);
-    double r2 = (double)(s * s) * (double)(k1 * k1 + k2 * k2);
+    double r2 = (frac ? sf_d * sf_d : (double)(s * s)) * (double)(k1 * k1 + k2 * k2);
     return (T)std::exp(-r2 / (2.0 * pb->sigma_s * pb->sigma_s));
   }
 
@@ -324,7 +349,7 @@ struct Solver {
     T S_w = 0, S_a = 0, S_aa = 0;
     for (int k2 = -R, t = 0; k2 <= R; ++k2)
       for (int k1 = -R; k1 <= R; ++k1, ++t) {
-        T a = ref(x + s * k1, y + s * k2) - a_c;
+        T a = ref_tap(x, y, k1, k2) - a_c;
         T w = w_colour(a) * w_space(k1, k2);
         T wa = w * a;
         S_w = S_w + w;
@@ -347,7 +372,7 @@ struct Solver {
       const int cx[4] = {-R, R, -R, R}, cy[4] = {-R, -R, R, R};
       for (int c = 0; c < 4; ++c) {
         T up, vp;
-        T w = warp(Hm, (T)(x + s * cx[c]), (T)(y + s * cy[c]), &up, &vp);
+        T w = warp(Hm, (T)x + off[cx[c] + R], (T)y + off[cy[c] + R], &up, &vp);
         if (!(w > T(0)) || !(up >= T(0) && up <= Wm1 && vp >= T(0) && vp <= Hm1)) inside = false;
       }
       if (!inside) continue;
@@ -357,7 +382,7 @@ struct Solver {
       T S_b = 0, S_bb = 0, S_ab = 0;
       for (int k2 = -R, t = 0; k2 <= R; ++k2)
         for (int k1 = -R; k1 <= R; ++k1, ++t) {
-          warp(Hm, (T)(x + s * k1), (T)(y + s * k2), &up, &vp);
+          warp(Hm, (T)x + off[k1 + R], (T)y + off[k2 + R], &up, &vp);
           T b = sample(view, up, vp) - b_c;
           T tb = wk[t] * b;
           S_b = S_b + tb;
