@@ -273,6 +273,56 @@ def bench_phi(ctx, mv, jobs, outs, size=None):
             "gpu_ms": gpu_ms, "host_selection_ms": host_ms}
 
 
+def bench_resize(args):
+    """The paper's window-resize study (Table III) on the 1600x1066 scene (9 sources, top-4,
+    8 iterations): r_now taps per side over the original radius r_orig, for r_orig = 5..10,
+    against the dense window (r_now = r_orig).  Reported per configuration: ms per depth map,
+    depth accuracy against the ground truth and the evaluate kernel's rate."""
+    import torch
+
+    import paper_2104_06165_amd as pm
+    import scenegen as sg
+
+    scene = sg.workload_scene("mid", device="cuda")
+    ctx = pm.Context(0)
+    ctx.set_scene(scene)
+    srcs = list(range(1, len(scene.images)))
+    H, W = scene.images[0].shape
+    textured = scene.textured[scene.gt_plane]
+    rows = []
+    for r_orig in range(5, 11):
+        for r_now in sorted({5, r_orig}):
+            window = 2 * r_orig + 1
+            params = pm.Params(top_k=4, sigma_spatial_px=float(r_orig), seed=sg.PM_SEED,
+                               tap_radius=r_now if r_now != r_orig else 0)
+            run = lambda: ctx.patchmatch(0, srcs, window, 1, 8, params)  # noqa: E731
+            for _ in range(args.warmup):
+                run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                d, n, c = run()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            dd = d.cpu().numpy()
+            valid = np.zeros((H, W), bool)
+            valid[r_orig:H - r_orig, r_orig:W - r_orig] = True
+            rel = np.abs(dd - scene.gt_depth) / scene.gt_depth
+            rows.append({"r_now": r_now, "r_orig": r_orig, "taps": (2 * r_now + 1) ** 2, "ms": ms,
+                         "depth_within_1pct": float((rel[valid] < 0.01).mean()),
+                         "depth_within_1pct_textured": float((rel[valid & textured] < 0.01).mean())})
+            log(f"[bench] {r_now}/{r_orig}: {ms:.1f} ms, within 1% {rows[-1]['depth_within_1pct']:.4f}")
+    line = {"metric": "ms per 1600x1066 depth map by matching-window configuration (r_now/r_orig)",
+            "value": rows[0]["ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": rows[0]["ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": f"synthetic (seeded piecewise-planar scene, seed {sg.SCENE_SEEDS['mid']})",
+            "config": {"workload": "resize: 1 reference + 9 sources at 1600x1066, top-4, 8 iterations, windows "
+                                   "r_orig = 5..10 with r_now = 5 (window-resize scheme) or r_now = r_orig"},
+            "table": rows}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, random_ms, reps=3):
     """Learned-proposal initialisation against random initialisation at equal final cost:
     the mean cost (valid pixels) after k = 0..iters iterations of both, the fewest
@@ -343,7 +393,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="highres", choices=["highres", "mid", "mid_dense", "tiny", "batched"])
+    ap.add_argument("--workload", default="highres",
+                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize"])
     ap.add_argument("--cpu-iters", type=int, default=1, help="iterations of the oracle's bounded sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy"),
@@ -377,6 +428,8 @@ def main():
     wl = args.workload
     if wl == "batched":
         return bench_batched(args)
+    if wl == "resize":
+        return bench_resize(args)
     scene_name = "mid" if wl.startswith("mid") else wl
     solver = sg.SOLVER[wl]
     cfg = sg.CONFIGS[scene_name]

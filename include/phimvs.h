@@ -78,6 +78,12 @@ typedef struct {
   double eps_var;           /* a patch with weighted variance below this is invalid (default 1e-4)     */
   double eps_cost;          /* per-source cost floor in the inverse weights of Eq. 5 (default 1e-4)    */
   uint64_t seed;            /* Philox4x32-10 key for the random draws (default 0x5EED)                 */
+  int32_t tap_radius;       /* 0: taps x + s k, k = -r..r (integer dilation s).  > 0: the window-resize
+                               scheme (Sec. III-C, Table III): r_now = tap_radius taps per side spread
+                               over the window's radius r_orig = (window - 1) / 2 at spacing
+                               r_orig / r_now (not necessarily an integer), reference values
+                               interpolated bilinearly, the colour weight taken at the nearest integer
+                               grey difference; needs dilation 1 and r_now <= r_orig (default 0)       */
 } phimvs_params;
 
 void phimvs_default_params(phimvs_params* p);

@@ -206,7 +206,8 @@ std::string problem_key(const Problem& P) {
   std::string k = std::to_string(P.ref) + "," + std::to_string(P.window) + "," + std::to_string(P.dilation) + "," +
                   std::to_string(P.p.top_k) + "," + std::to_string(P.p.bilateral) + "," + std::to_string(P.p.seed) +
                   "," + std::to_string(P.p.sigma_color) + "," + std::to_string(P.p.sigma_spatial_px) + "," +
-                  std::to_string(P.p.eps_var) + "," + std::to_string(P.p.eps_cost);
+                  std::to_string(P.p.eps_var) + "," + std::to_string(P.p.eps_cost) + "," +
+                  std::to_string(P.p.tap_radius);
   for (int s : P.srcs) k += ";" + std::to_string(s);
   return k;
 }
@@ -231,6 +232,13 @@ int validate_problem(phimvs_ctx* c, const Problem& P) {
   if (R > 15) return fail(c, PHIMVS_E_UNSUPPORTED, "at most 31 taps per window side");
   if (P.dilation * R > 30) return fail(c, PHIMVS_E_UNSUPPORTED, "window radius above 30 px");
   const phimvs_params& p = P.p;
+  if (p.tap_radius < 0) return fail(c, PHIMVS_E_ARG, "tap_radius must be >= 0");
+  if (p.tap_radius > 0) {
+    if (P.dilation != 1) return fail(c, PHIMVS_E_ARG, "the window-resize scheme (tap_radius > 0) needs dilation 1");
+    if (p.tap_radius > (P.window - 1) / 2) return fail(c, PHIMVS_E_ARG, "tap_radius above the window radius");
+    if (p.tap_radius > 15) return fail(c, PHIMVS_E_UNSUPPORTED, "at most 31 taps per window side");
+    if ((P.window - 1) / 2 > 29) return fail(c, PHIMVS_E_UNSUPPORTED, "window radius above 29 px");
+  }
   const int n = (int)P.srcs.size();
   if (p.top_k < 0 || p.top_k > n) return fail(c, PHIMVS_E_ARG, "top_k must be in [0, n_srcs]");
   if (!std::isfinite(p.sigma_spatial_px) || !(std::isfinite(p.sigma_color) && p.sigma_color > 0))
@@ -246,12 +254,22 @@ int setup_job(phimvs_ctx* c, const Problem& P, Job& J, JobState& S) {
   const phimvs_params& p = P.p;
   Args& A = J.A;
   A = Args{};
-  const int R = (P.window - 1) / (2 * P.dilation);
+  const bool frac = p.tap_radius > 0;
+  const int r_orig = (P.window - 1) / 2;
+  const int R = frac ? p.tap_radius : (P.window - 1) / (2 * P.dilation);
+  // spacing of the window-resize scheme, rounded to float once; offsets s k in FP32
+  const double sf_d = frac ? (double)r_orig / (double)R : (double)P.dilation;
+  const float sf = (float)sf_d;
   A.W = V0.W;
   A.H = V0.H;
   A.Wc = (V0.W + 1) / 2;
   A.R = R;
-  A.s = P.dilation;
+  A.s = frac ? 1 : P.dilation;
+  A.frac = frac ? 1 : 0;
+  for (int k = 0; k <= 2 * R; ++k) A.off[k] = frac ? sf * (float)(k - R) : (float)(P.dilation * (k - R));
+  A.rv = frac ? r_orig : P.dilation * R;
+  // interpolated taps read one texel beyond their offset
+  A.halo = frac ? (int)std::ceil((double)A.off[2 * R]) + 1 : P.dilation * R;
   A.n_src = (int)P.srcs.size();
   A.top_k = p.top_k;
   A.bilateral = p.bilateral ? 1 : 0;
@@ -301,7 +319,7 @@ int setup_job(phimvs_ctx* c, const Problem& P, Job& J, JobState& S) {
   }
   for (int k2 = -R, t = 0; k2 <= R; ++k2)
     for (int k1 = -R; k1 <= R; ++k1, ++t) {
-      const double r2 = (double)(P.dilation * P.dilation) * (double)(k1 * k1 + k2 * k2);
+      const double r2 = sf_d * sf_d * (double)(k1 * k1 + k2 * k2);
       ws[t] = p.bilateral ? (float)std::exp(-r2 / (2.0 * ss * ss)) : 1.0f;
     }
   int rc;
@@ -341,7 +359,7 @@ void layout(Batch& b, int tile_rows) {
     J.cblk0 = k;
     J.cblk_x = (J.A.Wc + 127) / 128;
     k += J.cblk_x * J.A.H;
-    b.max_r = std::max(b.max_r, J.A.s * J.A.R);
+    b.max_r = std::max(b.max_r, J.A.halo);
     b.max_taps = std::max(b.max_taps, J.A.n_taps);
   }
   b.total_tiles = t;
@@ -573,6 +591,7 @@ void phimvs_default_params(phimvs_params* p) {
   p->eps_var = 1e-4;
   p->eps_cost = 1e-4;
   p->seed = 0x5EED;
+  p->tap_radius = 0;
 }
 
 int phimvs_create(phimvs_ctx** out, int device_ordinal, void* hip_stream) {

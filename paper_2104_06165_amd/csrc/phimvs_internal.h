@@ -12,6 +12,7 @@ namespace phimvs_internal {
 
 constexpr int kBlock = 256;        // threads per evaluate workgroup
 constexpr int kMaxTopK = PHIMVS_MAX_SOURCES;
+constexpr int kMaxTaps1D = 31;     // taps per window side
 
 // one source view as the kernels see it
 struct SrcDev {
@@ -28,6 +29,10 @@ struct Args {
   int R, s;                // tap radius (taps per side 2R+1) and dilation
   int n_src, top_k, bilateral;
   int n_taps;              // (2R+1)^2
+  int frac;                // window-resize scheme: interpolated reference taps at fractional offsets
+  int rv;                  // validity radius: a pixel is valid when its window (x +- rv) is inside
+  int halo;                // reference-tile halo in pixels
+  float off[kMaxTaps1D];   // tap offsets k = 0 .. 2R: s (k - R), in FP32
   float Kinv[9];
   double Kinv_d[9];
   float d_lo, d_hi, eps_v, eps_c;

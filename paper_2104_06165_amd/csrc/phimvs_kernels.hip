@@ -115,8 +115,33 @@ struct RefPix {
   float rx, ry, rz;       // K^-1 (x, y, 1)
   float a_c, S_w, mu_a, var_a;
   bool ok;                // pixel valid and reference patch variance >= eps_v
-  int tbase;              // LDS index of the window's first tap
+  int tbase;              // LDS index of the window's first tap (integer spacing)
+  int tox, toy;           // image position of the reference tile's first texel
 };
+
+// Reference value of tap (k1, k2) (0 .. 2R) from the LDS tile: a texel at integer
+// spacing; with the window-resize scheme the bilinear value at (x + off[k1], y + off[k2]),
+// lerp(a, b, t) = fma(t, b - a, a) as for the sources.  The tile replicates the image
+// border, so a position a rounding error outside the image reads the border value.
+template <bool FRAC>
+__device__ __forceinline__ float ref_tap(const Args& A, const RefPix& rp, const float* __restrict__ tile, int TW,
+                                         int k1, int k2) {
+  if (!FRAC) return tile[rp.tbase + (k2 * TW + k1) * A.s];
+  const float X = rp.X0 + A.off[k1], Y = rp.Y0 + A.off[k2];
+  const float fx = __builtin_amdgcn_fractf(X), fy = __builtin_amdgcn_fractf(Y);
+  const int ix = (int)floorf(X), iy = (int)floorf(Y);
+  const float* q = tile + (iy - rp.toy) * TW + (ix - rp.tox);
+  const float t00 = q[0], t01 = q[1], t10 = q[TW], t11 = q[TW + 1];
+  const float top = __builtin_fmaf(fx, t01 - t00, t00);
+  const float bot = __builtin_fmaf(fx, t11 - t10, t10);
+  return __builtin_fmaf(fy, bot - top, top);
+}
+
+// colour-weight table index of a reference difference (an integer unless interpolated)
+template <bool FRAC>
+__device__ __forceinline__ int colour_index(float a) {
+  return FRAC ? (int)__builtin_rintf(fabsf(a)) : (int)fabsf(a);
+}
 
 // ---------------------------------------------------------------------------- plane helpers
 // viewing ray K^-1 (x, y, 1) in float
@@ -146,7 +171,7 @@ __device__ __forceinline__ void facing_normal(const Args& A, int x, int y, doubl
 }
 
 __device__ __forceinline__ bool pixel_valid(const Args& A, int x, int y) {
-  const int r = A.s * A.R;
+  const int r = A.rv;
   return x - r >= 0 && x + r <= A.W - 1 && y - r >= 0 && y + r <= A.H - 1;
 }
 
@@ -168,7 +193,7 @@ struct Hyp {
 // texels are interpolated and accumulated, so each gather's latency overlaps a tap of
 // arithmetic.  Every tap's arithmetic and the order of accumulation are unchanged.  The
 // weight tables hold 1.0 when the weights are off, so w = 1 exactly then.
-template <int G, bool EXACT, bool CLAMP>
+template <int G, bool EXACT, bool CLAMP, bool FRAC>
 __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp, const float* __restrict__ tile,
                                          int TW, const float* __restrict__ wcol, const float* __restrict__ wsp,
                                          const float (&Hm)[G][9], const float (&bc)[G], float (&Sb)[G],
@@ -193,7 +218,8 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
   // bases of the row being issued: (H[1] Y + H[2], H[4] Y + H[5], H[7] Y + H[8])
   float rbu[G], rbv[G], rbw[G];
   auto row_bases = [&](int k2) {
-    const float Y = (float)(rp.y + s * (k2 - R));
+    // integer spacing: s (k - R) exactly (integers below 2^24), the table's value, without a load
+    const float Y = rp.Y0 + (FRAC ? A.off[k2] : (float)(s * (k2 - R)));
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       rbu[g] = __builtin_fmaf(Hm[g][1], Y, Hm[g][2]);
@@ -203,7 +229,7 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
   };
   // warp column k1 of the row whose bases are loaded and issue its texel loads
   auto issue = [&](int k1, uint32_t (&qo)[G], float (&fxo)[G], float (&fyo)[G]) {
-    const float X = rp.X0 + (float)(s * (k1 - R));  // exact: integers below 2^24
+    const float X = rp.X0 + (FRAC ? A.off[k1] : (float)(s * (k1 - R)));
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const float u = __builtin_fmaf(Hm[g][0], X, rbu[g]);
@@ -219,11 +245,11 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
       qo[g] = gl(quad[g])[__umul24(y0, Wq[g]) + x0];
     }
   };
-  // interpolate and accumulate tap (row trow, column k1, index t)
-  auto process = [&](const float* trow, int k1, int t, const uint32_t (&qi)[G], const float (&fxi)[G],
+  // interpolate and accumulate tap (row k2 at trow, column k1, index t)
+  auto process = [&](const float* trow, int k1, int k2, int t, const uint32_t (&qi)[G], const float (&fxi)[G],
                      const float (&fyi)[G]) {
-    const float a = trow[k1 * s] - rp.a_c;
-    const float w = wcol[(int)fabsf(a)] * wsp[t];
+    const float a = (FRAC ? ref_tap<true>(A, rp, tile, TW, k1, k2) : trow[k1 * s]) - rp.a_c;
+    const float w = wcol[colour_index<FRAC>(a)] * wsp[t];
     const float wa = w * a;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -247,15 +273,15 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
     const int t0 = k2 * n;
     for (int c = 0; c + 1 < n; c += 2) {
       issue(c + 1, qB, fxB, fyB);
-      process(trow, c, t0 + c, qA, fxA, fyA);
+      process(trow, c, k2, t0 + c, qA, fxA, fyA);
       issue(c + 2, qA, fxA, fyA);
-      process(trow, c + 1, t0 + c + 1, qB, fxB, fyB);
+      process(trow, c + 1, k2, t0 + c + 1, qB, fxB, fyB);
     }
     if (k2 + 1 < n) {
       row_bases(k2 + 1);
       issue(0, qB, fxB, fyB);
     }
-    process(trow, n - 1, t0 + n - 1, qA, fxA, fyA);
+    process(trow, n - 1, k2, t0 + n - 1, qA, fxA, fyA);
   };
 
   uint32_t qa[G], qb[G];
@@ -279,8 +305,7 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
                                            const float* __restrict__ tile, int TW, const float* __restrict__ wcol,
                                            const float* __restrict__ wsp, float (&c)[G], bool (&ok)[G]) {
   float Hm[G][9], bc[G];
-  const int r = A.s * A.R;
-  const float Xmax = rp.X0 + (float)r, Ymax = rp.Y0 + (float)r;
+  const float Xmax = rp.X0 + A.off[2 * A.R], Ymax = rp.Y0 + A.off[2 * A.R];
   bool need_exact = false, need_clamp = false, any_ok = false;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -295,8 +320,8 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
     float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float X = (float)(rp.x + ((k & 1) ? r : -r));
-      const float Y = (float)(rp.y + ((k & 2) ? r : -r));
+      const float X = rp.X0 + A.off[(k & 1) ? 2 * A.R : 0];
+      const float Y = rp.Y0 + A.off[(k & 2) ? 2 * A.R : 0];
       const float u = __builtin_fmaf(Hm[g][0], X, __builtin_fmaf(Hm[g][1], Y, Hm[g][2]));
       const float v = __builtin_fmaf(Hm[g][3], X, __builtin_fmaf(Hm[g][4], Y, Hm[g][5]));
       const float w = __builtin_fmaf(Hm[g][6], X, __builtin_fmaf(Hm[g][7], Y, Hm[g][8]));
@@ -352,12 +377,19 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
   }
   if (__ballot(any_ok) == 0) return;
   float Sb[G], Sbb[G], Sab[G];
-  if (__ballot(need_exact) != 0)
-    tap_pass<G, true, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
-  else if (__ballot(need_clamp) != 0)
-    tap_pass<G, false, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
-  else
-    tap_pass<G, false, false>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+  if (A.frac) {
+    // the window-resize scheme: one variant, clamped (the bounds above assume integer spacing)
+    if (__ballot(need_exact) != 0)
+      tap_pass<G, true, true, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+    else
+      tap_pass<G, false, true, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+  } else if (__ballot(need_exact) != 0) {
+    tap_pass<G, true, true, false>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+  } else if (__ballot(need_clamp) != 0) {
+    tap_pass<G, false, true, false>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+  } else {
+    tap_pass<G, false, false, false>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+  }
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     if (ok[g]) {
@@ -603,7 +635,7 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   const int local = tile - J.tile0;
   const int tile_y = local / J.tiles_x;
   const int tile_x = local - tile_y * J.tiles_x;
-  const int r = A.s * A.R;
+  const int r = A.halo;
   const int TW = 2 * TC + 2 * r, TH = TR + 2 * r;
   float* wcol = lds;            // 256
   float* wsp = lds + 256;       // n_taps
@@ -636,7 +668,9 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   rp.X0 = (float)x;
   rp.Y0 = (float)y;
   rp.ok = false;
-  rp.tbase = row * TW + 2 * col + par;  // tile position of the window's first tap (-R, -R)
+  rp.tbase = (row + r - A.s * A.R) * TW + 2 * col + par + r - A.s * A.R;  // first tap (-R, -R)
+  rp.tox = x_org;
+  rp.toy = y_org;
   ray_f(A, x, y, rp.rx, rp.ry, rp.rz);
   rp.a_c = 0.0f;
   rp.S_w = 1.0f;
@@ -649,9 +683,8 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
     for (int k2 = 0; k2 <= 2 * A.R; ++k2) {
       const float* trow = tile_lds + rp.tbase + k2 * A.s * TW;
       for (int k1 = 0; k1 <= 2 * A.R; ++k1, ++t) {
-        const float a = trow[k1 * A.s] - rp.a_c;
-        float w = 1.0f;
-        if (A.bilateral) w = wcol[(int)fabsf(a)] * wsp[t];
+        const float a = (A.frac ? ref_tap<true>(A, rp, tile_lds, TW, k1, k2) : trow[k1 * A.s]) - rp.a_c;
+        const float w = wcol[A.frac ? colour_index<true>(a) : colour_index<false>(a)] * wsp[t];
         const float wa = w * a;
         S_w = S_w + w;
         S_a = S_a + wa;

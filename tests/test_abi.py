@@ -37,6 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_params_and_null_context_errors():
     p = pm.default_params()
     assert p.top_k == 0 and p.bilateral and p.sigma_color == 12.0 and p.eps_var == 1e-4 and p.seed == 0x5EED
+    assert p.tap_radius == 0
     L = pm.lib()
     # calls on a null context fail with PHIMVS_E_ARG instead of crashing
     assert L.phimvs_prepare(None, 0, None, 0, 7, 1, None) == -1
