@@ -91,8 +91,10 @@ def lib():
                                                 C.c_double, ip]
         L.oracle_phi_map_bruteforce.restype = C.c_double
         L.oracle_phi_normals.argtypes = [fp, C.c_int, C.c_int, dp, fp]
+        L.oracle_fuse.argtypes = [C.c_int, ip, ip, dp, dp, dp, C.POINTER(fp), C.c_double, fp, ip,
+                                  C.POINTER(C.c_int64)]
         for f in ("oracle_patchmatch", "oracle_init", "oracle_halfsweep", "oracle_eval_cost", "oracle_homography",
-                  "oracle_consistency", "oracle_phi_normals"):
+                  "oracle_consistency", "oracle_phi_normals", "oracle_fuse"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -265,6 +267,31 @@ def consistency(depths, normals, K, R, t, ref: int, nbrs, tau_d: float = 0.02, t
     if rc != 0:
         raise ValueError("oracle_consistency failed (bad view, neighbour or camera)")
     return od, on, oc
+
+
+def fuse(depths, K, R, t, max_rel_dist: float = 0.01):
+    """Depth-map fusion (Sec. III-F) of the maps in the order given.  depths: list of
+    (H_i, W_i) float32 maps (<= 0: no depth); K, R: (n, 3, 3), t: (n, 3) of those maps'
+    cameras.  -> (points (P, 3) float32, support (P,) int32, owner (P,) int64) over the
+    concatenated pixels (P = sum of H_i W_i; map i at the offset of the earlier maps)."""
+    n = len(depths)
+    W = np.array([d.shape[1] for d in depths], np.int32)
+    H = np.array([d.shape[0] for d in depths], np.int32)
+    keep = [np.ascontiguousarray(d, dtype=np.float32) for d in depths]
+    dptr = (C.POINTER(C.c_float) * n)(*[_ptr(d, C.c_float) for d in keep])
+    Kd = np.ascontiguousarray(np.asarray(K, np.float64).reshape(n, 9))
+    Rd = np.ascontiguousarray(np.asarray(R, np.float64).reshape(n, 9))
+    td = np.ascontiguousarray(np.asarray(t, np.float64).reshape(n, 3))
+    P = int((W.astype(np.int64) * H).sum())
+    pts = np.zeros((P, 3), np.float32)
+    sup = np.zeros(P, np.int32)
+    own = np.zeros(P, np.int64)
+    rc = lib().oracle_fuse(n, _ptr(W, C.c_int32), _ptr(H, C.c_int32), _ptr(Kd, C.c_double), _ptr(Rd, C.c_double),
+                           _ptr(td, C.c_double), dptr, float(max_rel_dist), _ptr(pts, C.c_float),
+                           _ptr(sup, C.c_int32), _ptr(own, C.c_int64))
+    if rc != 0:
+        raise ValueError("oracle_fuse failed (bad map or camera)")
+    return pts, sup, own
 
 
 def phi_hypotheses(depth):

@@ -868,6 +868,82 @@ int oracle_consistency(int n_views, const int32_t* width, const int32_t* height,
   return 0;
 }
 
+// Depth-map fusion (Sec. III-F).  The maps are handled in the order given.  For map i,
+// every pixel that still has depth, in row-major order, is back-projected to X_i; for
+// every later map j (earlier maps are already deleted) X_i is projected into camera j and
+// rounded to the nearest pixel q = (floor(u + 1/2), floor(v + 1/2)); when q lies in the
+// image, still has depth and its back-projection X'_j is within max_rel_dist d_i of X_i
+// (Euclidean distance; d_i the depth of X_i in camera i), q is deleted from map j and X'_j
+// joins the point.  The point is the mean of X_i and its joined X'_j (summed in j order),
+// then map i is deleted.  Outputs over the concatenated maps (map i at the offset of the
+// pixel counts of maps 0..i-1): points (3 floats, world frame) and support (pixels merged)
+// at the pixel a point started from, zero elsewhere; owner = the concatenated index of
+// the point a pixel ended in, -1 for pixels without depth.  FP64 throughout.
+static void fuse_back_project(const CamD& c, int x, int y, double d, double* Xw) {
+  const double pix[3] = {(double)x, (double)y, 1.0};
+  double ray[3], X[3];
+  mat3_vec(c.Kinv, pix, ray);
+  for (int k = 0; k < 3; ++k) X[k] = d * ray[k];
+  cam_to_world(c, X, Xw);
+}
+
+int oracle_fuse(int n_maps, const int32_t* width, const int32_t* height, const double* K, const double* R,
+                const double* t, const float* const* depth, double max_rel_dist, float* points, int32_t* support,
+                int64_t* owner) {
+  std::vector<CamD> cams(n_maps);
+  std::vector<size_t> off(n_maps + 1, 0);
+  for (int v = 0; v < n_maps; ++v) {
+    if (!cam_setup(K + 9 * v, R + 9 * v, t + 3 * v, cams[v]) || !depth[v] || width[v] <= 0 || height[v] <= 0)
+      return -1;
+    off[v + 1] = off[v] + (size_t)width[v] * height[v];
+  }
+  std::vector<uint8_t> alive(off[n_maps]);
+  for (int v = 0; v < n_maps; ++v)
+    for (size_t p = 0; p < off[v + 1] - off[v]; ++p) {
+      alive[off[v] + p] = depth[v][p] > 0.0f;
+      owner[off[v] + p] = -1;
+      support[off[v] + p] = 0;
+      for (int c = 0; c < 3; ++c) points[3 * (off[v] + p) + c] = 0.0f;
+    }
+  for (int i = 0; i < n_maps; ++i) {
+    const int Wi = width[i], Hi = height[i];
+    for (int y = 0; y < Hi; ++y)
+      for (int x = 0; x < Wi; ++x) {
+        const size_t gi = off[i] + (size_t)y * Wi + x;
+        if (!alive[gi]) continue;
+        const double d = depth[i][(size_t)y * Wi + x];
+        double Xi[3];
+        fuse_back_project(cams[i], x, y, d, Xi);
+        double sum[3] = {Xi[0], Xi[1], Xi[2]};
+        int count = 1;
+        owner[gi] = (int64_t)gi;
+        for (int j = i + 1; j < n_maps; ++j) {
+          double Xj[3], p[3];
+          world_to_cam(cams[j], Xi, Xj);
+          mat3_vec(cams[j].K, Xj, p);
+          if (!(p[2] > 0.0)) continue;
+          const double xr = std::floor(p[0] / p[2] + 0.5), yr = std::floor(p[1] / p[2] + 0.5);
+          if (!(xr >= 0.0 && xr <= (double)(width[j] - 1) && yr >= 0.0 && yr <= (double)(height[j] - 1))) continue;
+          const int qx = (int)xr, qy = (int)yr;
+          const size_t q = (size_t)qy * width[j] + qx;
+          if (!alive[off[j] + q]) continue;
+          double Yw[3];
+          fuse_back_project(cams[j], qx, qy, (double)depth[j][q], Yw);
+          const double e0 = Yw[0] - Xi[0], e1 = Yw[1] - Xi[1], e2 = Yw[2] - Xi[2];
+          if (!(std::sqrt(e0 * e0 + e1 * e1 + e2 * e2) < max_rel_dist * d)) continue;
+          alive[off[j] + q] = 0;
+          owner[off[j] + q] = (int64_t)gi;
+          for (int k = 0; k < 3; ++k) sum[k] = sum[k] + Yw[k];
+          ++count;
+        }
+        alive[gi] = 0;
+        support[gi] = count;
+        for (int k = 0; k < 3; ++k) points[3 * gi + k] = (float)(sum[k] / (double)count);
+      }
+  }
+  return 0;
+}
+
 // Plane-hypothesis depths (Sec. III-E) of every pixel without depth: hyp (H*W*4), 0 = none.
 void oracle_phi_hypotheses(const float* depth, int W, int H, float* hyp) {
   for (int y = 0; y < H; ++y)
