@@ -401,6 +401,7 @@ Launch base_launch(const Batch& b) {
   L.total_tiles = b.total_tiles;
   L.total_cblk = b.total_cblk;
   for (int x = 0; x < 8; ++x) L.xcd_len[x] = b.xcd_len[x];
+  for (const Job& J : b.jobs) L.frac = L.frac || J.A.frac;
   return L;
 }
 

@@ -73,6 +73,7 @@ struct Launch {
   int total_tiles, total_cblk;
   int xcd_len[8];                      // evaluate tiles of each XCD's list
   int persistent;                      // evaluate: tiles pulled from per-XCD queues
+  int frac;                            // evaluate: some job uses the window-resize scheme
   unsigned int* queue;                 // 8 counters, zero at launch (persistent only)
   unsigned long long* count;           // optional: + (pixel, hypothesis) pairs scored
 };

@@ -300,7 +300,7 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
 // Views J0 .. J0+G-1: build H_j = M_j + e_j m^T, apply the border rule at the window
 // corners, take the centre sample, run the tap pass and finish each view's ZNCC.
 // c[g] / ok[g] receive 1 - Z and the validity.
-template <int G>
+template <int G, bool FR>
 __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& rp, const Hyp& h,
                                            const float* __restrict__ tile, int TW, const float* __restrict__ wcol,
                                            const float* __restrict__ wsp, float (&c)[G], bool (&ok)[G]) {
@@ -377,12 +377,15 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
   }
   if (__ballot(any_ok) == 0) return;
   float Sb[G], Sbb[G], Sab[G];
-  if (A.frac) {
-    // the window-resize scheme: one variant, clamped (the bounds above assume integer spacing)
+  if (FR && A.frac) {
+    // the window-resize scheme: computed tap positions X0 + off[k] are monotone in k, so they
+    // stay between the corners' and the bounds above hold for them as for integer spacing
     if (__ballot(need_exact) != 0)
       tap_pass<G, true, true, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
-    else
+    else if (__ballot(need_clamp) != 0)
       tap_pass<G, false, true, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+    else
+      tap_pass<G, false, false, true>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
   } else if (__ballot(need_exact) != 0) {
     tap_pass<G, true, true, false>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
   } else if (__ballot(need_clamp) != 0) {
@@ -420,8 +423,9 @@ __device__ __forceinline__ void topk_insert(float (&top)[kMaxTopK], float c) {
 
 // Cost (Eq. 5 over the best-K valid sources) of plane (n, d) at pixel rp.  Sources are
 // scored two at a time; per_view / valid (global, optional) receive 1 - Z and the flag of
-// each source.
-__device__ float plane_cost(const Args& A, const RefPix& rp, const float* __restrict__ tile, int TW,
+// each source.  FR: the job may use the window-resize scheme (A.frac decides).
+template <bool FR>
+__device__ __forceinline__ float plane_cost(const Args& A, const RefPix& rp, const float* __restrict__ tile, int TW,
                             const float* __restrict__ wcol, const float* __restrict__ wsp, float nx, float ny,
                             float nz, float d, float* per_view, uint8_t* valid) {
   float top[kMaxTopK];
@@ -447,11 +451,11 @@ __device__ float plane_cost(const Args& A, const RefPix& rp, const float* __rest
     const int gn = NV - j0 < 2 ? 1 : 2;
     if (any) {
       if (gn == 2) {
-        view_group<2>(A, j0, rp, h, tile, TW, wcol, wsp, c, ok);
+        view_group<2, FR>(A, j0, rp, h, tile, TW, wcol, wsp, c, ok);
       } else {
         float c1[1];
         bool ok1[1];
-        view_group<1>(A, j0, rp, h, tile, TW, wcol, wsp, c1, ok1);
+        view_group<1, FR>(A, j0, rp, h, tile, TW, wcol, wsp, c1, ok1);
         c[0] = c1[0];
         ok[0] = ok1[0];
       }
@@ -628,8 +632,10 @@ __global__ __launch_bounds__(128) void cand_refine_kernel(const Job* __restrict_
 // proposal, replaces it when not more expensive).  mode 1: update (candidates 0..ncand-1 in
 // order replace the current plane on a strictly lower cost; the first of equal costs wins).
 // mode 2: cost of row-major input planes, optionally per source.
+template <bool FR>
 __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile, float* lds) {
   const Args& A = J.A;
+  const bool frac = FR && A.frac;
   const int TR = L.tile_rows;
   const int TC = kBlock / TR;  // compacted columns per tile
   const int local = tile - J.tile0;
@@ -683,8 +689,8 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
     for (int k2 = 0; k2 <= 2 * A.R; ++k2) {
       const float* trow = tile_lds + rp.tbase + k2 * A.s * TW;
       for (int k1 = 0; k1 <= 2 * A.R; ++k1, ++t) {
-        const float a = (A.frac ? ref_tap<true>(A, rp, tile_lds, TW, k1, k2) : trow[k1 * A.s]) - rp.a_c;
-        const float w = wcol[A.frac ? colour_index<true>(a) : colour_index<false>(a)] * wsp[t];
+        const float a = (frac ? ref_tap<true>(A, rp, tile_lds, TW, k1, k2) : trow[k1 * A.s]) - rp.a_c;
+        const float w = wcol[frac ? colour_index<true>(a) : colour_index<false>(a)] * wsp[t];
         const float wa = w * a;
         S_w = S_w + w;
         S_a = S_a + wa;
@@ -707,7 +713,7 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
       uint8_t* vm = J.valid_out ? J.valid_out + p * A.n_src : nullptr;
       if (valid) {
         const float4 pl = ld4(reinterpret_cast<const float4*>(J.planes_in), p);
-        c = plane_cost(A, rp, tile_lds, TW, wcol, wsp, pl.x, pl.y, pl.z, pl.w, pv, vm);
+        c = plane_cost<FR>(A, rp, tile_lds, TW, wcol, wsp, pl.x, pl.y, pl.z, pl.w, pv, vm);
       } else {
         for (int j = 0; j < A.n_src; ++j) {
           if (pv) gl(pv)[j] = kCmax;
@@ -735,7 +741,7 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
     if (bal == 0) continue;
     if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(bal));
     if (has) {
-      const float c = plane_cost(A, rp, tile_lds, TW, wcol, wsp, h.x, h.y, h.z, h.w, nullptr, nullptr);
+      const float c = plane_cost<FR>(A, rp, tile_lds, TW, wcol, wsp, h.x, h.y, h.z, h.w, nullptr, nullptr);
       const bool take = L.mode == 0 ? (k == 0 || c <= bc) : (c < bc);
       if (take) {
         bc = c;
@@ -756,7 +762,10 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
 // XCD's L2 serves a compact band of each image and every XCD gets the same share of every
 // job.  Non-persistent: workgroup b runs on XCD b % 8 and takes position b / 8 of that
 // XCD's list.  Persistent: a fixed grid; each workgroup pulls positions from its XCD's
-// queue, so uneven tiles balance dynamically within an XCD.
+// queue, so uneven tiles balance dynamically within an XCD.  FR: instantiated with the
+// window-resize scheme's code (launches holding such a job), whose register needs then do
+// not weigh on the integer-spacing instance.
+template <bool FR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void eval_kernel(
     const Job* __restrict__ jobs, Launch L) {
   extern __shared__ float lds[];
@@ -767,7 +776,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     const int i = (int)(blockIdx.x >> 3);
     if (i >= len) return;
     const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
-    eval_tile(J, L, J.tile0 + J.xband[xcd] + (i - J.xoff[xcd]), lds);
+    eval_tile<FR>(J, L, J.tile0 + J.xband[xcd] + (i - J.xoff[xcd]), lds);
     return;
   }
   for (;;) {
@@ -777,7 +786,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     __syncthreads();
     if (i >= len) return;
     const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
-    eval_tile(J, L, J.tile0 + J.xband[xcd] + (i - J.xoff[xcd]), lds);
+    eval_tile<FR>(J, L, J.tile0 + J.xband[xcd] + (i - J.xoff[xcd]), lds);
     __syncthreads();  // the next tile re-stages LDS
   }
 }
@@ -868,15 +877,18 @@ size_t eval_lds_bytes(int tile_rows, int max_radius_px, int max_taps) {
 
 hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds, hipStream_t st) {
   // tiles above 64 KiB of LDS (one-row tiles with wide windows) need the opt-in limit
-  static bool raised = false;
-  if (lds > 65536 && !raised) {
-    const hipError_t e = hipFuncSetAttribute((const void*)pmk::eval_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+  static bool raised[2] = {false, false};
+  const void* fn = L.frac ? (const void*)pmk::eval_kernel<true> : (const void*)pmk::eval_kernel<false>;
+  if (lds > 65536 && !raised[L.frac ? 1 : 0]) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
     if (e != hipSuccess) return e;
-    raised = true;
+    raised[L.frac ? 1 : 0] = true;
   }
   if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pmk::eval_kernel, dim3(grid), dim3(kBlock), lds, st, d_jobs, L);
+  if (L.frac)
+    hipLaunchKernelGGL(pmk::eval_kernel<true>, dim3(grid), dim3(kBlock), lds, st, d_jobs, L);
+  else
+    hipLaunchKernelGGL(pmk::eval_kernel<false>, dim3(grid), dim3(kBlock), lds, st, d_jobs, L);
   return hipGetLastError();
 }
 
