@@ -873,7 +873,7 @@ int oracle_consistency(int n_views, const int32_t* width, const int32_t* height,
 // every later map j (earlier maps are already deleted) X_i is projected into camera j and
 // rounded to the nearest pixel q = (floor(u + 1/2), floor(v + 1/2)); when q lies in the
 // image, still has depth and its back-projection X'_j is within max_rel_dist d_i of X_i
-// (Euclidean distance; d_i the depth of X_i in camera i), q is deleted from map j and X'_j
+// (Euclidean distance, compared squared; d_i the depth of X_i in camera i), q is deleted from map j and X'_j
 // joins the point.  The point is the mean of X_i and its joined X'_j (summed in j order),
 // then map i is deleted.  Outputs over the concatenated maps (map i at the offset of the
 // pixel counts of maps 0..i-1): points (3 floats, world frame) and support (pixels merged)
@@ -930,7 +930,8 @@ int oracle_fuse(int n_maps, const int32_t* width, const int32_t* height, const d
           double Yw[3];
           fuse_back_project(cams[j], qx, qy, (double)depth[j][q], Yw);
           const double e0 = Yw[0] - Xi[0], e1 = Yw[1] - Xi[1], e2 = Yw[2] - Xi[2];
-          if (!(std::sqrt(e0 * e0 + e1 * e1 + e2 * e2) < max_rel_dist * d)) continue;
+          const double lim = max_rel_dist * d;
+          if (!(e0 * e0 + e1 * e1 + e2 * e2 < lim * lim)) continue;  // distance below lim, squared
           alive[off[j] + q] = 0;
           owner[off[j] + q] = (int64_t)gi;
           for (int k = 0; k < 3; ++k) sum[k] = sum[k] + Yw[k];
