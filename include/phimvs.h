@@ -222,6 +222,36 @@ int phimvs_filter(phimvs_ctx* ctx, int n_maps, const phimvs_depth_map* maps, int
                   int n_nbrs, const phimvs_filter_params* p, float* depth_out, float* normal_out,
                   uint8_t* count_out);
 
+/* ---- depth-map fusion (Sec. III-F) ---- */
+
+/* Merge threshold: a pixel of a later map joins a point when its back-projection lies
+ * within max_rel_dist d of the point's first pixel's back-projection X (Euclidean
+ * distance; d the depth of X in its own camera).  Default 0.01. */
+typedef struct {
+  double max_rel_dist;
+} phimvs_fuse_params;
+
+void phimvs_default_fuse_params(phimvs_fuse_params* p);
+
+/* Depth-map fusion into a point cloud, Sec. III-F.  The maps are processed in the order
+ * given (maps[k].normal is not used and may be NULL).  For map i, each pixel that still
+ * has depth (> 0) is back-projected to X; in every later map j, X is projected and
+ * rounded to the nearest pixel q (floor(u + 1/2), floor(v + 1/2)); if q is in the image,
+ * still has depth and its back-projection is within the threshold of X, q is deleted from
+ * map j and joins the point; among the pixels of map i that qualify for the same q, the
+ * first in row-major order takes it.  The point is the mean of X and the back-projections
+ * it took (summed in map order); then map i is deleted, and the next map is processed.
+ * Outputs (device arrays over the concatenated pixels of the maps, map k starting after
+ * the H*W pixels of maps 0..k-1; caller-owned):
+ *   points  (3 floats per pixel): the world-frame point at the pixel it started from, else 0;
+ *   support (int32 per pixel): the number of pixels merged into that point, else 0;
+ *   owner   (int64 per pixel): the concatenated index of the point the pixel ended in,
+ *           -1 for pixels without depth.
+ * All arithmetic is FP64.  Work is queued on the context's stream; the library keeps
+ * scratch of 5 bytes per concatenated pixel.  p = NULL uses the default threshold. */
+int phimvs_fuse(phimvs_ctx* ctx, int n_maps, const phimvs_depth_map* maps, const phimvs_fuse_params* p,
+                float* points, int32_t* support, int64_t* owner);
+
 /* ---- plane hypothesis inference (Sec. III-E) ----
  * Depth hypotheses for the pixels a filtered depth map leaves empty, their matching
  * costs, the selection of one hypothesis per pixel through a pairwise graph model (the

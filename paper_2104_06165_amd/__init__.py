@@ -30,7 +30,7 @@ EXPORTS = ("phimvs_default_params", "phimvs_create", "phimvs_destroy", "phimvs_l
            "phimvs_step", "phimvs_get_state", "phimvs_set_state", "phimvs_output", "phimvs_eval_cost",
            "phimvs_patchmatch_batch", "phimvs_set_tuning", "phimvs_get_tuning", "phimvs_autotune",
            "phimvs_diag_enable", "phimvs_diag_read", "phimvs_check_reciprocal",
-           "phimvs_default_filter_params", "phimvs_filter",
+           "phimvs_default_filter_params", "phimvs_filter", "phimvs_default_fuse_params", "phimvs_fuse",
            "phimvs_phi_hypotheses", "phimvs_phi_costs", "phimvs_default_phi_params", "phimvs_phi_select",
            "phimvs_phi_decode_host", "phimvs_phi_normals",
            # learned initial-plane proposal (include/phimvs_net.h)
@@ -85,6 +85,10 @@ class FilterParams:
     max_angle_deg: float = 30.0
     max_reproj_px: float = 1.0
     min_consistent: int = 2
+
+
+class _FuseParams(C.Structure):
+    _fields_ = [("max_rel_dist", C.c_double)]
 
 
 class _PhiParams(C.Structure):
@@ -170,6 +174,9 @@ def lib():
         L.phimvs_default_filter_params.restype = None
         L.phimvs_filter.argtypes = [vp, ip, C.POINTER(_DepthMap), ip, C.POINTER(C.c_int32), ip,
                                     C.POINTER(_FilterParams), fp, fp, vp]
+        L.phimvs_default_fuse_params.argtypes = [C.POINTER(_FuseParams)]
+        L.phimvs_default_fuse_params.restype = None
+        L.phimvs_fuse.argtypes = [vp, ip, C.POINTER(_DepthMap), C.POINTER(_FuseParams), fp, fp, fp]
         L.phimvs_phi_hypotheses.argtypes = [vp, ip, ip, fp, fp]
         L.phimvs_phi_costs.argtypes = [vp, fp, fp]
         L.phimvs_default_phi_params.argtypes = [C.POINTER(_PhiParams)]
@@ -199,7 +206,8 @@ def lib():
         for name in EXPORTS:
             f = getattr(L, name)
             if name not in ("phimvs_default_params", "phimvs_destroy", "phimvs_last_error", "phimvs_net_destroy",
-                            "phimvs_net_last_error", "phimvs_default_filter_params", "phimvs_default_phi_params"):
+                            "phimvs_net_last_error", "phimvs_default_filter_params", "phimvs_default_phi_params",
+                  "phimvs_default_fuse_params"):
                 f.restype = C.c_int
         L.phimvs_net_param_count.restype = C.c_int64
         _lib = L
@@ -346,6 +354,32 @@ class Context:
         self._check(lib().phimvs_filter(self.h, len(maps), arr, ref_map, nb, len(nbrs), C.byref(cp), od.data_ptr(),
                                         on.data_ptr(), oc.data_ptr()))
         return od, on, oc
+
+    # ------------------------------------------------------------------ depth-map fusion
+    def fuse(self, maps, max_rel_dist: float = 0.01):
+        """Depth-map fusion of the maps in the order given.  maps: list of (view, depth (H, W))
+        device tensors.  -> (points (P, 3) float32, support (P,) int32, owner (P,) int64) over
+        the concatenated pixels (map k after the pixels of maps 0..k-1)."""
+        torch = self.torch
+        self._sync_stream()
+        arr = (_DepthMap * max(len(maps), 1))()
+        P = 0
+        for i, (v, d) in enumerate(maps):
+            if d.dtype != torch.float32 or not d.is_contiguous():
+                raise ValueError("depth maps must be contiguous float32 tensors")
+            arr[i] = _DepthMap(int(v), d.data_ptr(), None)
+            if 0 <= int(v) < len(self.views):
+                H, W = self.views[int(v)]
+                if d.shape != (H, W):
+                    raise ValueError(f"map {i}: depth shape {tuple(d.shape)} is not the view's {(H, W)}")
+                P += H * W
+        pts = torch.empty((max(P, 1), 3), dtype=torch.float32, device=self.device)
+        sup = torch.empty((max(P, 1),), dtype=torch.int32, device=self.device)
+        own = torch.empty((max(P, 1),), dtype=torch.int64, device=self.device)
+        cp = _FuseParams(float(max_rel_dist))
+        self._check(lib().phimvs_fuse(self.h, len(maps), arr, C.byref(cp), pts.data_ptr(), sup.data_ptr(),
+                                      own.data_ptr()))
+        return pts[:P], sup[:P], own[:P]
 
     # ------------------------------------------------------------------ plane hypothesis inference
     def phi_hypotheses(self, depth):

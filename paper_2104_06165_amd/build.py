@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphimvs.so")
 SOURCES = ["phimvs_kernels.hip", "phimvs_host.hip", "phimvs_net.hip", "phimvs_net_host.hip", "phimvs_filter.hip",
-           "phimvs_phi.hip", "phimvs_mrf.hip"]
+           "phimvs_phi.hip", "phimvs_mrf.hip", "phimvs_fuse.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PHIMVS_ARCH", "gfx950")

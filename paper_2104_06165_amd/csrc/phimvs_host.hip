@@ -77,6 +77,10 @@ struct phimvs_ctx {
   DevBuf<float> io_a, io_b, io_c, io_d;  // staging for host inputs / outputs
   DevBuf<FilterNbr> filter_nbrs;          // neighbour table of the consistency filter
   std::vector<FilterNbr> filter_host;
+  DevBuf<FuseMap> fuse_maps;              // fusion: map table, live flags and claims
+  std::vector<FuseMap> fuse_host;
+  DevBuf<uint8_t> fuse_alive;
+  DevBuf<int32_t> fuse_claim;
   DevBuf<uint8_t> io_u8;
   // diagnostics
   int diag = 0;
@@ -633,6 +637,9 @@ void phimvs_destroy(phimvs_ctx* c) {
   release(c->io_c);
   release(c->io_d);
   release(c->filter_nbrs);
+  release(c->fuse_maps);
+  release(c->fuse_alive);
+  release(c->fuse_claim);
   release(c->io_u8);
   if (c->diag_count) (void)hipFree(c->diag_count);
   for (auto& e : c->diag_events) {
@@ -988,6 +995,55 @@ int phimvs_filter(phimvs_ctx* c, int n_maps, const phimvs_depth_map* maps, int r
   a.n_nbrs = n_nbrs;
   a.nbrs = c->filter_nbrs.p;
   HIPCHECK(c, launch_filter(a, c->stream));
+  return PHIMVS_OK;
+}
+
+// ---------------------------------------------------------------------------- depth-map fusion
+
+void phimvs_default_fuse_params(phimvs_fuse_params* p) {
+  if (!p) return;
+  p->max_rel_dist = 0.01;
+}
+
+int phimvs_fuse(phimvs_ctx* c, int n_maps, const phimvs_depth_map* maps, const phimvs_fuse_params* pp, float* points,
+                int32_t* support, int64_t* owner) {
+  if (!c) return PHIMVS_E_ARG;
+  if (n_maps < 1 || !maps) return fail(c, PHIMVS_E_ARG, "invalid map list");
+  if (!points || !support || !owner) return fail(c, PHIMVS_E_ARG, "null output");
+  phimvs_fuse_params p;
+  phimvs_default_fuse_params(&p);
+  if (pp) p = *pp;
+  if (!(p.max_rel_dist >= 0.0) || !std::isfinite(p.max_rel_dist))
+    return fail(c, PHIMVS_E_ARG, "max_rel_dist must be finite and >= 0");
+  HIPCHECK(c, hipSetDevice(c->device));
+  // the previous call's table may still be in use by its launches
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->fuse_host.assign(n_maps, FuseMap{});
+  int64_t total = 0;
+  for (int k = 0; k < n_maps; ++k) {
+    const phimvs_depth_map& M = maps[k];
+    if (M.view < 0 || M.view >= (int)c->views.size() || !M.depth)
+      return fail(c, PHIMVS_E_ARG, "map " + std::to_string(k) + ": invalid view or null depth");
+    const ViewData& V = c->views[M.view];
+    if ((int64_t)V.W * V.H >= INT32_MAX) return fail(c, PHIMVS_E_UNSUPPORTED, "map above 2^31 pixels");
+    FuseMap& f = c->fuse_host[k];
+    for (int i = 0; i < 9; ++i) f.K[i] = V.K[i], f.R[i] = V.R[i];
+    for (int i = 0; i < 3; ++i) f.t[i] = V.t[i];
+    if (!inv33(V.K, f.Kinv)) return fail(c, PHIMVS_E_ARG, "singular K");
+    f.W = V.W;
+    f.H = V.H;
+    f.off = total;
+    f.depth = M.depth;
+    total += (int64_t)V.W * V.H;
+  }
+  int rc;
+  if ((rc = ensure(c, c->fuse_maps, (size_t)n_maps))) return rc;
+  if ((rc = ensure(c, c->fuse_alive, (size_t)total))) return rc;
+  if ((rc = ensure(c, c->fuse_claim, (size_t)total))) return rc;
+  HIPCHECK(c, hipMemcpyAsync(c->fuse_maps.p, c->fuse_host.data(), n_maps * sizeof(FuseMap), hipMemcpyHostToDevice,
+                             c->stream));
+  HIPCHECK(c, launch_fuse(c->fuse_host.data(), c->fuse_maps.p, n_maps, p.max_rel_dist, c->fuse_alive.p,
+                          c->fuse_claim.p, points, support, owner, c->stream));
   return PHIMVS_OK;
 }
 

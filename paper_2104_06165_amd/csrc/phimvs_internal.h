@@ -115,6 +115,18 @@ struct FilterArgs {
 };
 hipError_t launch_filter(const FilterArgs& a, hipStream_t st);
 
+// depth-map fusion: one map's camera and depth, at offset `off` of the concatenated pixels
+struct FuseMap {
+  double K[9], Kinv[9], R[9], t[3];
+  int W, H;
+  int64_t off;
+  const float* depth;
+};
+// the whole fusion of n_maps maps (h_maps on the host, d_maps its device copy); alive and
+// claim: scratch over the concatenated pixels
+hipError_t launch_fuse(const FuseMap* h_maps, const FuseMap* d_maps, int n_maps, double tau, uint8_t* alive,
+                       int32_t* claim, float* points, int32_t* support, int64_t* owner, hipStream_t st);
+
 // plane hypothesis inference
 struct PhiCam {
   double Kinv[9];

@@ -1,0 +1,160 @@
+"""GPU parity of depth-map fusion (Sec. III-F) through the C ABI against the oracle's
+sequential walk: points, support and owners bitwise equal on random multi-view maps of
+mixed sizes, on a half-resolution copy (where several pixels compete for one), on the
+PatchMatch depth maps of every view of the tiny scene, and in the degenerate cases (one
+map, no depth at all, threshold zero)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2104_06165_amd as pm  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cam(f, W, H, centre=(0.0, 0.0, 0.0), yaw=0.0):
+    K = np.array([[f, 0.0, (W - 1) / 2.0], [0.0, f, (H - 1) / 2.0], [0.0, 0.0, 1.0]])
+    c, s = np.cos(yaw), np.sin(yaw)
+    R = np.array([[c, 0.0, -s], [0.0, 1.0, 0.0], [s, 0.0, c]])
+    t = -R @ np.asarray(centre, np.float64)
+    return K, R, t
+
+
+def arc_maps(seed, sizes, f_scale=0.8, noise=0.003, holes=0.15):
+    """Cameras on an arc looking at the world plane z = 4; depth maps with noise and holes."""
+    r = np.random.default_rng(seed)
+    cams, depths = [], []
+    n = len(sizes)
+    for v, (W, H) in enumerate(sizes):
+        a = 0.05 * (v - (n - 1) / 2)
+        K, R, t = cam(f_scale * W, W, H, (4.0 * np.sin(a), 0.03 * v, 4.0 - 4.0 * np.cos(a)), a)
+        y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+        ray = np.stack([(x - K[0, 2]) / K[0, 0], (y - K[1, 2]) / K[1, 1], np.ones_like(x)], -1) @ R
+        C = -R.T @ t
+        d = ((4.0 - C[2]) / ray[..., 2] * (1 + noise * r.standard_normal((H, W)))).astype(np.float32)
+        d[r.uniform(size=(H, W)) < holes] = 0.0
+        cams.append((K, R, t))
+        depths.append(d)
+    return cams, depths
+
+
+def gpu_fuse(cams, depths, tau):
+    ctx = pm.Context(0)
+    try:
+        # a scene needs two views; a lone map gets a copy of its camera as a spare view
+        views = cams if len(cams) > 1 else cams * 2
+        ims = [np.zeros(d.shape, np.uint8) for d in (depths if len(cams) > 1 else depths * 2)]
+        K = np.stack([c[0] for c in views])
+        R = np.stack([c[1] for c in views])
+        t = np.stack([c[2] for c in views])
+        ctx.set_views(ims, K, R, t, np.tile([1.0, 10.0], (len(views), 1)))
+        dev = [torch.from_numpy(d).cuda() for d in depths]
+        pts, sup, own = ctx.fuse([(v, dev[v]) for v in range(len(dev))], tau)
+        torch.cuda.synchronize()
+        return pts.cpu().numpy(), sup.cpu().numpy(), own.cpu().numpy()
+    finally:
+        ctx.close()
+
+
+def check(cams, depths, tau, label):
+    g = gpu_fuse(cams, depths, tau)
+    o = oracle.fuse(depths, np.stack([c[0] for c in cams]), np.stack([c[1] for c in cams]),
+                    np.stack([c[2] for c in cams]), tau)
+    has = np.concatenate([d.ravel() > 0 for d in depths])
+    say(f"{label}: {has.sum()} pixels with depth -> {(o[1] > 0).sum()} points, "
+        f"{(o[1] > 1).sum()} merged; points bitwise {np.array_equal(g[0], o[0])}, support {np.array_equal(g[1], o[1])}, "
+        f"owner {np.array_equal(g[2], o[2])}")
+    assert np.array_equal(g[1], o[1])
+    assert np.array_equal(g[2], o[2])
+    assert np.array_equal(g[0], o[0])
+    assert g[1].sum() == has.sum()
+    return o
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fuse_parity_random_views(seed):
+    sizes = [(96, 72), (64, 48), (96, 72), (80, 60), (96, 72), (48, 36)]
+    cams, depths = arc_maps(seed, sizes)
+    o = check(cams, depths, 0.01, f"arc seed {seed}")
+    assert (o[1] > 1).sum() > 0.1 * (o[1] > 0).sum()
+
+
+def test_fuse_parity_half_resolution_competition():
+    W, H, f, Z = 80, 48, 100.0, 4.0
+    cams = [cam(f, W, H), cam(f / 2, W // 2, H // 2)]
+    depths = [np.full((H, W), Z, np.float32), np.full((H // 2, W // 2), Z, np.float32)]
+    o = check(cams, depths, 0.01, "half resolution")
+    exp = np.ones((H, W), np.int32)
+    exp[0::2, 0::2] = 2
+    assert np.array_equal(o[1][:W * H].reshape(H, W), exp)
+
+
+def test_fuse_parity_degenerate_cases():
+    cams, depths = arc_maps(5, [(40, 30), (40, 30), (40, 30)])
+    check(cams[:1], depths[:1], 0.01, "one map")
+    check(cams, [np.zeros_like(d) for d in depths], 0.01, "no depth")
+    o = check(cams, depths, 0.0, "threshold zero")
+    assert np.all(o[1][o[1] > 0] == 1)
+
+
+def test_fuse_parity_patchmatch_maps():
+    """Every view of the tiny scene as reference (the others as sources), 3 iterations,
+    then the consistency filter, then fusion of the filtered maps."""
+    scene = sg.workload_scene("tiny", device="cuda")
+    ctx = pm.Context(0)
+    try:
+        ctx.set_scene(scene)
+        n = len(scene.images)
+        params = pm.Params(top_k=3, sigma_spatial_px=5.0)
+        raw = []
+        for v in range(n):
+            d, nm, _ = ctx.patchmatch(v, [j for j in range(n) if j != v], 11, 1, 3, params)
+            raw.append((v, d.clone(), nm.clone()))
+        filt = []
+        for v in range(n):
+            fd, _, _ = ctx.filter(raw, v, [j for j in range(n) if j != v])
+            filt.append((v, fd.clone()))
+        pts, sup, own = ctx.fuse(filt, 0.01)
+        torch.cuda.synchronize()
+        g = (pts.cpu().numpy(), sup.cpu().numpy(), own.cpu().numpy())
+    finally:
+        ctx.close()
+    depths = [d.cpu().numpy() for _, d in filt]
+    o = oracle.fuse(depths, scene.K, scene.R, scene.t, 0.01)
+    has = np.concatenate([d.ravel() > 0 for d in depths])
+    say(f"tiny scene: {has.sum()} filtered pixels -> {(o[1] > 0).sum()} points, mean support "
+        f"{o[1][o[1] > 0].mean():.2f}")
+    assert np.array_equal(g[1], o[1]) and np.array_equal(g[2], o[2]) and np.array_equal(g[0], o[0])
+    assert (o[1] > 1).mean() > 0 and o[1].sum() == has.sum()
+
+
+def test_fuse_argument_errors():
+    ctx = pm.Context(0)
+    try:
+        cams, depths = arc_maps(0, [(16, 12), (16, 12)])
+        ctx.set_views([np.zeros((12, 16), np.uint8)] * 2, np.stack([c[0] for c in cams]),
+                      np.stack([c[1] for c in cams]), np.stack([c[2] for c in cams]), np.tile([1.0, 10.0], (2, 1)))
+        d = torch.from_numpy(depths[0]).cuda()
+        with pytest.raises(pm.PhimvsError):
+            ctx.fuse([(0, d), (7, d)])
+        with pytest.raises(pm.PhimvsError):
+            ctx.fuse([(0, d)], -1.0)
+        with pytest.raises(pm.PhimvsError):
+            ctx.fuse([])
+        with pytest.raises(ValueError):
+            ctx.fuse([(0, torch.zeros((5, 5), device="cuda"))])
+    finally:
+        ctx.close()
