@@ -104,6 +104,45 @@ __device__ __forceinline__ float sample_quad(const uint32_t* __restrict__ quad, 
   return __builtin_fmaf(fy, bot - top, top);
 }
 
+// The tap loop's form of the same bilinear sample.  The quad's bytes become FP16
+// subnormals k 2^-24 (one byte permute per pair; exact, FP16 denormals are kept):
+// lo = (I00, I10), hi = (I01, I11), and one packed FP16 subtraction gives both exact
+// differences.  The mixed-precision FMA reads them as FP32 without a conversion, so every
+// lerp is the canonical one on values scaled by 2^-24: scaling by a power of two commutes
+// with each rounding (all intermediate values are 0 or far above the FP32 normal range's
+// lower end), and the caller undoes it exactly in its shift by the centre sample.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2v quad_lo(uint32_t q) {
+  return __builtin_bit_cast(h2v, __builtin_amdgcn_perm(0u, q, 0x0c020c00u));
+}
+__device__ __forceinline__ h2v quad_hi(uint32_t q) {
+  return __builtin_bit_cast(h2v, __builtin_amdgcn_perm(0u, q, 0x0c030c01u));
+}
+// 2^-24 times the bilinear sample of quad q at fractions (fx, fy)
+__device__ __forceinline__ float bilerp_scaled(uint32_t q, float fx, float fy) {
+  const h2v lo = quad_lo(q), hi = quad_hi(q);
+  const h2v df = hi - lo;  // (I01 - I00, I11 - I10) 2^-24, exact
+  const float top = __builtin_fmaf(fx, (float)df.x, (float)lo.x);
+  const float bot = __builtin_fmaf(fx, (float)df.y, (float)lo.y);
+  return __builtin_fmaf(fy, bot - top, top);
+}
+
+// Texel-quad gathers through a buffer resource with a 4-byte record stride: the hardware
+// scales the record index (no 64-bit address arithmetic per tap) and range-checks it
+// against the record count (an index past the end reads 0 instead of faulting).
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+__device__ int struct_buffer_load_i32(v4i32 rsrc, int vindex, int voffset, int soffset, int aux) __asm(
+    "llvm.amdgcn.struct.buffer.load.i32");
+__device__ __forceinline__ v4i32 quad_rsrc(const uint32_t* p, uint32_t n_records) {
+  const uint64_t a = (uint64_t)p;
+  v4i32 r;
+  r.x = (int)(uint32_t)a;                         // base address, low 32 bits
+  r.y = (int)((uint32_t)(a >> 32) | (4u << 16));  // base address, high bits; stride 4 bytes
+  r.z = (int)n_records;                           // records (range check)
+  r.w = 0x00020000;                               // 32-bit data format
+  return r;
+}
+
 // clamp into [0, hi]; equals fmin(fmax(v, 0), hi) for every non-NaN v (a NaN position only
 // arises in a view already ruled invalid, and any result keeps the sample address in range)
 __device__ __forceinline__ float clampf(float v, float hi) { return __builtin_amdgcn_fmed3f(v, 0.0f, hi); }
@@ -201,16 +240,16 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
   const int R = A.R, s = A.s;
   const int n = 2 * R + 1;
   const int T = n * n;
-  const uint32_t* quad[G];
   uint32_t Wq[G];
+  v4i32 rs[G];
   float Wm1[G], Hm1[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     Sb[g] = 0.0f;
     Sbb[g] = 0.0f;
     Sab[g] = 0.0f;
-    quad[g] = A.src[J0 + g].quad;
     Wq[g] = (uint32_t)A.src[J0 + g].W;
+    rs[g] = quad_rsrc(A.src[J0 + g].quad, (uint32_t)A.src[J0 + g].W * (uint32_t)A.src[J0 + g].H);
     Wm1[g] = A.src[J0 + g].Wm1;
     Hm1[g] = A.src[J0 + g].Hm1;
   }
@@ -242,7 +281,7 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
       fxo[g] = __builtin_amdgcn_fractf(up);
       fyo[g] = __builtin_amdgcn_fractf(vp);
       const uint32_t x0 = (uint32_t)up, y0 = (uint32_t)vp;
-      qo[g] = gl(quad[g])[__umul24(y0, Wq[g]) + x0];
+      qo[g] = (uint32_t)struct_buffer_load_i32(rs[g], (int)(__umul24(y0, Wq[g]) + x0), 0, 0, 0);
     }
   };
   // interpolate and accumulate tap (row k2 at trow, column k1, index t)
@@ -253,11 +292,8 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
     const float wa = w * a;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const float t00 = (float)(qi[g] & 0xFFu), t01 = (float)((qi[g] >> 8) & 0xFFu);
-      const float t10 = (float)((qi[g] >> 16) & 0xFFu), t11 = (float)(qi[g] >> 24);
-      const float top = __builtin_fmaf(fxi[g], t01 - t00, t00);
-      const float bot = __builtin_fmaf(fxi[g], t11 - t10, t10);
-      const float b = __builtin_fmaf(fyi[g], bot - top, top) - bc[g];
+      // b - b_c with the sample's 2^-24 scale undone inside one exact-product FMA
+      const float b = __builtin_fmaf(bilerp_scaled(qi[g], fxi[g], fyi[g]), 0x1p24f, -bc[g]);
       const float tb = w * b;
       Sb[g] = Sb[g] + tb;
       Sbb[g] = __builtin_fmaf(tb, b, Sbb[g]);
