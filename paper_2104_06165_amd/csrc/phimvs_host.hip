@@ -368,13 +368,14 @@ void layout(Batch& b, int tile_rows) {
   }
   b.total_tiles = t;
   b.total_cblk = k;
-  // XCD k takes the k-th of 8 bands of every job, so every XCD gets the same share of each
-  // job's work (jobs differ in source count and window) and a compact band of each image
+  // XCD k takes the k-th of 8 bands (runs of whole tile rows) of every job, so every XCD
+  // gets the same share of each job's work (jobs differ in source count and window) and a
+  // compact band of each image
   for (int x = 0; x < 8; ++x) b.xcd_len[x] = 0;
   for (Job& J : b.jobs) {
     const int T = J.tiles_x * J.tiles_y;
     for (int x = 0; x < 8; ++x) {
-      J.xband[x] = (int)((int64_t)T * x / 8);
+      J.xband[x] = (int)((int64_t)J.tiles_y * x / 8) * J.tiles_x;
       J.xoff[x] = b.xcd_len[x];
     }
     for (int x = 0; x < 8; ++x) {

@@ -59,7 +59,7 @@ struct Job {
   float* planes_out;
   int tile0;               // first evaluate tile of this job
   int tiles_x, tiles_y;
-  int xband[8];            // XCD k evaluates local tiles [xband[k], xband[k + 1]) (xband[8] = all tiles)
+  int xband[8];            // XCD k evaluates local tiles [xband[k], xband[k + 1]) (xband[8] = all tiles); whole tile rows
   int xoff[8];             // where that band starts in XCD k's list (bands of earlier jobs first)
   int cblk0;               // first candidate / unpack block of this job
   int cblk_x;              // blocks per row

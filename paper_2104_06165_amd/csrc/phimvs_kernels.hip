@@ -527,6 +527,28 @@ __device__ __forceinline__ int job_of_xcd_tile(const Job* __restrict__ jobs, int
   return j;
 }
 
+// Tile (tx, ty) at position p of job J's band on XCD x.  A band is a run of whole tile
+// rows; it is walked in columns of kTileBlockW tiles, row-major inside a column, so the
+// tiles an XCD has in flight together form a compact block whose source footprint stays in
+// that XCD's L2 (row-major order over the full image width would not fit).
+constexpr int kTileBlockW = 16;
+__device__ __forceinline__ void band_tile(const Job& J, int x, int p, int& tx, int& ty) {
+  const int ry0 = J.xband[x] / J.tiles_x;
+  const int ry1 = (x + 1 < 8 ? J.xband[x + 1] : J.tiles_x * J.tiles_y) / J.tiles_x;
+  const int nrows = ry1 - ry0;  // > 0: the band holds position p
+  const int nb = J.tiles_x / kTileBlockW, per = kTileBlockW * nrows;
+  const int bc = p / per;
+  if (bc < nb) {
+    const int q = p - bc * per;
+    ty = ry0 + q / kTileBlockW;
+    tx = bc * kTileBlockW + q % kTileBlockW;
+  } else {
+    const int rem = J.tiles_x - nb * kTileBlockW, q = p - nb * per;
+    ty = ry0 + q / rem;
+    tx = nb * kTileBlockW + q % rem;
+  }
+}
+
 __device__ __forceinline__ int job_of_cblk(const Job* __restrict__ jobs, int n_jobs, int g) {
   int j = 0;
   while (j + 1 < n_jobs && g >= jobs[j + 1].cblk0) ++j;
@@ -669,14 +691,11 @@ __global__ __launch_bounds__(128) void cand_refine_kernel(const Job* __restrict_
 // order replace the current plane on a strictly lower cost; the first of equal costs wins).
 // mode 2: cost of row-major input planes, optionally per source.
 template <bool FR>
-__device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile, float* lds) {
+__device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile_x, int tile_y, float* lds) {
   const Args& A = J.A;
   const bool frac = FR && A.frac;
   const int TR = L.tile_rows;
   const int TC = kBlock / TR;  // compacted columns per tile
-  const int local = tile - J.tile0;
-  const int tile_y = local / J.tiles_x;
-  const int tile_x = local - tile_y * J.tiles_x;
   const int r = A.halo;
   const int TW = 2 * TC + 2 * r, TH = TR + 2 * r;
   float* wcol = lds;            // 256
@@ -812,7 +831,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     const int i = (int)(blockIdx.x >> 3);
     if (i >= len) return;
     const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
-    eval_tile<FR>(J, L, J.tile0 + J.xband[xcd] + (i - J.xoff[xcd]), lds);
+    int tx, ty;
+    band_tile(J, xcd, i - J.xoff[xcd], tx, ty);
+    eval_tile<FR>(J, L, tx, ty, lds);
     return;
   }
   for (;;) {
@@ -822,7 +843,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     __syncthreads();
     if (i >= len) return;
     const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
-    eval_tile<FR>(J, L, J.tile0 + J.xband[xcd] + (i - J.xoff[xcd]), lds);
+    int tx, ty;
+    band_tile(J, xcd, i - J.xoff[xcd], tx, ty);
+    eval_tile<FR>(J, L, tx, ty, lds);
     __syncthreads();  // the next tile re-stages LDS
   }
 }
