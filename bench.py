@@ -442,8 +442,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs the depth-map estimation on one GPU; --gpus above 1 is not "
-              "supported (see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print("bench.py: the depth-map estimation runs on one GPU; --gpus above 1 is not supported "
+              "(the depth maps of a scene would shard by reference view, one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -5,7 +5,7 @@
  * the depth range, random normal) can be replaced per pixel by a plane predicted by a
  * small convolutional network; the paper notes that a good initialisation speeds up
  * convergence (Sec. III-B) but proposes no network, so the network below is this
- * library's own addition.  The plain method stays the judge: a pixel keeps the
+ * library's own addition.  The plain method's cost decides: a pixel keeps the
  * proposed plane only when its matching cost (Eq. 5) is not higher than that of its
  * random plane, and the random plane is kept otherwise.
  *
