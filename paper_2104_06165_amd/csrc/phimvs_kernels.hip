@@ -86,6 +86,14 @@ __device__ __forceinline__ float rcp_nr(float w) {
   return __builtin_fmaf(e, r0, r0);
 }
 
+// 1/w correctly rounded (the IEEE quotient) for every w: the fast form when every lane's
+// |w| lies in [2^-100, 2^100) (a wave-uniform test, so only one form runs), division else
+__device__ __forceinline__ float rcp_ieee(float w) {
+  const float a = fabsf(w);
+  if (__ballot(!(a >= 0x1p-100f && a < 0x1p100f)) == 0) return rcp_nr(w);
+  return 1.0f / w;
+}
+
 // bilinear sample from a texel-quad image at a position already clamped into the image:
 // the 32-bit quad at (x0, y0) holds the bytes I[y0][x0], I[y0][x1], I[y1][x0], I[y1][x1]
 // (x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1)); lerp(a, b, t) = fma(t, b - a, a) with
@@ -350,7 +358,7 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
     for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) Hm[g][rr * 3 + cc] = __builtin_fmaf(V.e[rr], h.m[cc], V.M[rr * 3 + cc]);
-    // border rule at the four window corners (IEEE division)
+    // border rule at the four window corners (correctly rounded reciprocals)
     bool inside = h.ok;
     float wmin = 3.0e38f, wmax = -3.0e38f;
     float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
@@ -361,7 +369,7 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
       const float u = __builtin_fmaf(Hm[g][0], X, __builtin_fmaf(Hm[g][1], Y, Hm[g][2]));
       const float v = __builtin_fmaf(Hm[g][3], X, __builtin_fmaf(Hm[g][4], Y, Hm[g][5]));
       const float w = __builtin_fmaf(Hm[g][6], X, __builtin_fmaf(Hm[g][7], Y, Hm[g][8]));
-      const float rw = 1.0f / w;
+      const float rw = rcp_ieee(w);
       const float up = u * rw, vp = v * rw;
       inside = inside && (w > 0.0f) && (up >= 0.0f && up <= V.Wm1 && vp >= 0.0f && vp <= V.Hm1);
       wmin = fminf(wmin, w);
@@ -384,10 +392,11 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
     if (inside && fast) {
       const float Su = fabsf(Hm[g][0]) * Xmax + fabsf(Hm[g][1]) * Ymax + fabsf(Hm[g][2]);
       const float Sv = fabsf(Hm[g][3]) * Xmax + fabsf(Hm[g][4]) * Ymax + fabsf(Hm[g][5]);
-      const float wlow = wmin - slack;
+      // 1 / w_low in [2^-100, 2^100] here; the factor 2 covers a product's rounding
+      const float rlow = rcp_nr(wmin - slack);
       const float Wf = V.Wm1 + 1.0f, Hf = V.Hm1 + 1.0f;
-      const float mu_u = 2.0f * ((Su + Wf * S) * 0x1p-23f / wlow + Wf * 0x1p-22f);
-      const float mu_v = 2.0f * ((Sv + Hf * S) * 0x1p-23f / wlow + Hf * 0x1p-22f);
+      const float mu_u = 2.0f * ((Su + Wf * S) * 0x1p-23f * rlow + Wf * 0x1p-22f);
+      const float mu_v = 2.0f * ((Sv + Hf * S) * 0x1p-23f * rlow + Hf * 0x1p-22f);
       const bool safe = umin >= 2.0f * mu_u && umax <= V.Wm1 - 2.0f * mu_u && vmin >= 2.0f * mu_v &&
                         vmax <= V.Hm1 - 2.0f * mu_v;
       need_clamp = need_clamp || !safe;
@@ -400,7 +409,7 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
       const float u = __builtin_fmaf(Hm[g][0], rp.X0, __builtin_fmaf(Hm[g][1], rp.Y0, Hm[g][2]));
       const float v = __builtin_fmaf(Hm[g][3], rp.X0, __builtin_fmaf(Hm[g][4], rp.Y0, Hm[g][5]));
       const float w = __builtin_fmaf(Hm[g][6], rp.X0, __builtin_fmaf(Hm[g][7], rp.Y0, Hm[g][8]));
-      const float rw = 1.0f / w;
+      const float rw = rcp_ieee(w);
       bc[g] = sample_quad(V.quad, V.W, clampf(u * rw, V.Wm1), clampf(v * rw, V.Hm1));
     }
     // a lane whose view is invalid walks the constant map to texel (0, 0): its sums are
