@@ -428,8 +428,8 @@ def learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, ra
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="highres",
                     choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize"])
     ap.add_argument("--cpu-iters", type=int, default=1, help="iterations of the oracle's bounded sample")
