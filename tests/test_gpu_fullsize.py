@@ -1,0 +1,137 @@
+"""The remaining workloads at their full sizes: the 1600x1066 scene (9 sources, top-4,
+8 iterations) with the 21x21 window at dilation 2 and dense, and the learned proposal's
+gated initialisation on the 3200x2130 scene (10 sources).  The oracle re-evaluates the
+GPU's output planes at sampled pixels (teacher-forced), one further half-sweep is
+compared pixel by pixel on a sample, and the gate's rule is checked where it decided."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2104_06165_amd as pm  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy")
+COST_TOL = 1e-4
+DEPTH_TOL = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def problem(scene, window, dilation, top_k):
+    return oracle.Problem.from_scene(scene, window, dilation, top_k=top_k, bilateral=True,
+                                     sigma_s=(window - 1) / 2.0, sigma_c=12.0, seed=sg.PM_SEED)
+
+
+def params(window, top_k):
+    return pm.Params(top_k=top_k, bilateral=True, sigma_spatial_px=(window - 1) / 2.0, seed=sg.PM_SEED)
+
+
+@pytest.fixture(scope="module")
+def mid():
+    return sg.workload_scene("mid", device="cuda")
+
+
+@pytest.mark.parametrize("dilation", [2, 1], ids=["21x21-s2", "21x21-dense"])
+def test_mid_full_frame_sampled(mid, dilation):
+    sol = sg.SOLVER["mid"]
+    win, K, iters = sol["window"], sol["top_k"], sol["iters"]
+    srcs = list(range(1, len(mid.images)))
+    ctx = pm.Context(0)
+    try:
+        ctx.set_scene(mid)
+        ctx.prepare(0, srcs, win, dilation, params(win, K))
+        ctx.init_planes()
+        for it in range(1, iters + 1):
+            for col in (0, 1):
+                ctx.step(it, col)
+        planes, cost = ctx.get_state()
+        torch.cuda.synchronize()
+        pb = problem(mid, win, dilation, K)
+        m = pb.valid_mask()
+        g_all = cost.cpu().numpy()
+        assert np.all(g_all[~m] == pm.COST_MAX) and np.all((g_all >= 0) & (g_all <= pm.COST_MAX))
+        rng = np.random.default_rng(3)
+        idx = np.flatnonzero(m.ravel())
+        sub = rng.choice(idx, size=600, replace=False).astype(np.int32)
+        P = planes.cpu().numpy().astype(np.float64)
+        oc, _, _ = oracle.eval_cost(pb, P, subset=sub)
+        g = g_all.ravel()[sub]
+        o = oc.ravel()[sub]
+        ok = np.abs(g - o) <= COST_TOL
+        say(f"1600x1066 s={dilation}: final cost at {len(sub)} pixels within 1e-4 {ok.mean():.5f}, "
+            f"bitwise {(g == o.astype(np.float32)).mean():.5f}")
+        assert ok.sum() >= len(sub) - 1
+        # one more half-sweep (black), GPU vs oracle pixel by pixel on a sample
+        ctx.step(iters + 1, 1)
+        gp2, gc2 = ctx.get_state()
+        torch.cuda.synchronize()
+        ys, xs = np.divmod(idx, pb.W)
+        black = idx[((xs + ys) & 1) == 1]
+        sub2 = rng.choice(black, size=200, replace=False).astype(np.int32)
+        P2, C2 = oracle.halfsweep(pb, P, g_all.astype(np.float64), iters + 1, 1, subset=sub2)
+        ok2 = (np.abs(gc2.cpu().numpy().ravel()[sub2] - C2.ravel()[sub2]) <= COST_TOL) & (
+            np.abs(gp2.cpu().numpy()[..., 3].ravel()[sub2] - P2[..., 3].ravel()[sub2])
+            <= DEPTH_TOL * np.abs(P2[..., 3].ravel()[sub2]))
+        say(f"1600x1066 s={dilation}: half-sweep at {len(sub2)} pixels within tolerance {ok2.mean():.5f}")
+        assert ok2.sum() >= len(sub2) - 1
+    finally:
+        ctx.close()
+
+
+def test_proposal_gate_full_size():
+    """3200x2130: the gated initialisation keeps, per pixel, the random plane or the
+    proposal, never a plane of higher cost than the random one; every output cost is the
+    oracle's cost of the output plane."""
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("no trained weights committed")
+    scene = sg.workload_scene("highres", device="cuda")
+    sol = sg.SOLVER["highres"]
+    win, dil, K = sol["window"], sol["dilation"], sol["top_k"]
+    srcs = list(range(1, len(scene.images)))
+    ctx = pm.Context(0)
+    net = pm.Net(0, np.load(WEIGHTS))
+    try:
+        ctx.set_scene(scene)
+        p = params(win, K)
+        rd, rn, rc = [t.clone() for t in ctx.patchmatch(0, srcs, win, dil, 0, p)]
+        prop = ctx.propose(net, 0, srcs)
+        gd, gn, gc = [t.clone() for t in ctx.patchmatch_proposal(0, srcs, win, dil, 0, prop, p)]
+        torch.cuda.synchronize()
+        rd, rn, rc, gd, gn, gc = [t.cpu().numpy() for t in (rd, rn, rc, gd, gn, gc)]
+        pb = problem(scene, win, dil, K)
+        m = pb.valid_mask()
+        same = (gd == rd) & np.all(gn == rn, -1)
+        kept = m & ~same
+        say(f"3200x2130 gate: proposal kept on {kept.sum() / m.sum():.3f} of valid pixels")
+        assert np.all(gc[m] <= rc[m])  # the gate never raises the cost
+        assert np.all(gc[m & same] == rc[m & same])
+        rng = np.random.default_rng(5)
+        sub = np.concatenate([rng.choice(np.flatnonzero(kept.ravel()), 300, replace=False),
+                              rng.choice(np.flatnonzero((m & same).ravel()), 100, replace=False)]).astype(np.int32)
+        planes = np.concatenate([gn, gd[..., None]], -1).astype(np.float64)
+        oc, _, _ = oracle.eval_cost(pb, planes, subset=sub)
+        rplanes = np.concatenate([rn, rd[..., None]], -1).astype(np.float64)
+        orc, _, _ = oracle.eval_cost(pb, rplanes, subset=sub)
+        g = gc.ravel()[sub]
+        ok = np.abs(g - oc.ravel()[sub]) <= COST_TOL
+        not_worse = g <= orc.ravel()[sub] + COST_TOL
+        say(f"3200x2130 gate: output cost = oracle cost of the output plane at {ok.mean():.5f} of {len(sub)} samples, "
+            f"never above the random plane's at {not_worse.mean():.5f}")
+        assert ok.sum() >= len(sub) - 1 and not_worse.all()
+    finally:
+        net.close()
+        ctx.close()
