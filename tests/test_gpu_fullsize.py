@@ -1,6 +1,7 @@
 """The remaining workloads at their full sizes: the 1600x1066 scene (9 sources, top-4,
-8 iterations) with the 21x21 window at dilation 2 and dense, and the learned proposal's
-gated initialisation on the 3200x2130 scene (10 sources).  The oracle re-evaluates the
+8 iterations) with the 21x21 window at dilation 2, dense, and with the window-resize
+scheme (5 taps per side over radius 8 and 10), and the learned proposal's gated
+initialisation on the 3200x2130 scene (10 sources).  The oracle re-evaluates the
 GPU's output planes at sampled pixels (teacher-forced), one further half-sweep is
 compared pixel by pixel on a sample, and the gate's rule is checked where it decided."""
 import os
@@ -134,4 +135,39 @@ def test_proposal_gate_full_size():
         assert ok.sum() >= len(sub) - 1 and not_worse.all()
     finally:
         net.close()
+        ctx.close()
+
+
+@pytest.mark.parametrize("r_orig", [8, 10])
+def test_resize_full_frame_sampled(mid, r_orig):
+    """The window-resize scheme (5 taps per side over radius r_orig, fractional spacing) on
+    the 1600x1066 workload, 8 iterations: final costs re-evaluated by the oracle at sampled
+    pixels."""
+    sol = sg.SOLVER["mid"]
+    K, iters, win = sol["top_k"], sol["iters"], 2 * r_orig + 1
+    srcs = list(range(1, len(mid.images)))
+    ctx = pm.Context(0)
+    try:
+        ctx.set_scene(mid)
+        p = pm.Params(top_k=K, bilateral=True, sigma_spatial_px=float(r_orig), seed=sg.PM_SEED, tap_radius=5)
+        ctx.prepare(0, srcs, win, 1, p)
+        ctx.init_planes()
+        for it in range(1, iters + 1):
+            for col in (0, 1):
+                ctx.step(it, col)
+        planes, cost = ctx.get_state()
+        torch.cuda.synchronize()
+        pb = oracle.Problem.from_scene(mid, win, 1, top_k=K, bilateral=True, sigma_s=float(r_orig), sigma_c=12.0,
+                                       seed=sg.PM_SEED, tap_radius=5)
+        m = pb.valid_mask()
+        rng = np.random.default_rng(11)
+        sub = rng.choice(np.flatnonzero(m.ravel()), size=400, replace=False).astype(np.int32)
+        oc, _, _ = oracle.eval_cost(pb, planes.cpu().numpy().astype(np.float64), subset=sub)
+        g = cost.cpu().numpy().ravel()[sub]
+        o = oc.ravel()[sub]
+        ok = np.abs(g - o) <= COST_TOL
+        say(f"1600x1066 resize 5/{r_orig}: final cost at {len(sub)} pixels within 1e-4 {ok.mean():.5f}, "
+            f"bitwise {(g == o.astype(np.float32)).mean():.5f}")
+        assert ok.sum() >= len(sub) - 1
+    finally:
         ctx.close()
