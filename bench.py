@@ -432,7 +432,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="highres",
                     choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize"])
-    ap.add_argument("--cpu-iters", type=int, default=1, help="iterations of the oracle's bounded sample")
+    ap.add_argument("--cpu-iters", type=int, default=2, help="iterations of the oracle's bounded sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy"),
                     help="parameters of the proposal network for the learned-versus-random comparison")
