@@ -160,7 +160,8 @@ struct RefPix {
   int x, y;
   float X0, Y0;
   float rx, ry, rz;       // K^-1 (x, y, 1)
-  float a_c, S_w, mu_a, var_a;
+  float a_c;              // 4x the centre's grey value (the tile's scale)
+  float S_w, mu_a, var_a;
   bool ok;                // pixel valid and reference patch variance >= eps_v
   int tbase;              // LDS index of the window's first tap (integer spacing)
   int tox, toy;           // image position of the reference tile's first texel
@@ -184,10 +185,18 @@ __device__ __forceinline__ float ref_tap(const Args& A, const RefPix& rp, const 
   return __builtin_fmaf(fy, bot - top, top);
 }
 
-// colour-weight table index of a reference difference (an integer unless interpolated)
+// Colour weight of a reference tap from its difference to the centre, given four times
+// over (the LDS tile holds 4x the grey values, exactly, and every reference difference
+// and sum below carries that factor until it is divided out).  A power-of-two factor
+// commutes with every rounding in the normal range; a product that falls below it (a
+// weight of a difference above 158 grey levels) can differ in bits that vanish in any
+// sum with a normal term.  At integer spacing 4 |a - a_c| is the byte offset of the
+// table entry, which sits at LDS address 0, so the lookup needs no index arithmetic;
+// interpolated taps take the nearest grey level as before.
 template <bool FRAC>
-__device__ __forceinline__ int colour_index(float a) {
-  return FRAC ? (int)__builtin_rintf(fabsf(a)) : (int)fabsf(a);
+__device__ __forceinline__ float colour_weight(const float* __restrict__ wcol, float a4) {
+  if (FRAC) return wcol[(int)__builtin_rintf(fabsf(a4) * 0.25f)];
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(wcol) + (uint32_t)fabsf(a4));
 }
 
 // ---------------------------------------------------------------------------- plane helpers
@@ -295,9 +304,9 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
   // interpolate and accumulate tap (row k2 at trow, column k1, index t)
   auto process = [&](const float* trow, int k1, int k2, int t, const uint32_t (&qi)[G], const float (&fxi)[G],
                      const float (&fyi)[G]) {
-    const float a = (FRAC ? ref_tap<true>(A, rp, tile, TW, k1, k2) : trow[k1 * s]) - rp.a_c;
-    const float w = wcol[colour_index<FRAC>(a)] * wsp[t];
-    const float wa = w * a;
+    const float a4 = (FRAC ? ref_tap<true>(A, rp, tile, TW, k1, k2) : trow[k1 * s]) - rp.a_c;  // 4 (a - a_c)
+    const float w = colour_weight<FRAC>(wcol, a4) * wsp[t];
+    const float wa = w * a4;  // 4 w (a - a_c): the cross sum below is 4 S_ab
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       // b - b_c with the sample's 2^-24 scale undone inside one exact-product FMA
@@ -443,7 +452,7 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
     if (ok[g]) {
       const float mu_b = Sb[g] / rp.S_w;
       const float var_b = Sbb[g] / rp.S_w - mu_b * mu_b;
-      const float cov = Sab[g] / rp.S_w - rp.mu_a * mu_b;
+      const float cov = (Sab[g] * 0.25f) / rp.S_w - rp.mu_a * mu_b;
       if (var_b >= A.eps_v) {
         float z = cov / __builtin_sqrtf(rp.var_a * var_b);
         z = fminf(fmaxf(z, -1.0f), 1.0f);
@@ -700,15 +709,15 @@ __global__ __launch_bounds__(128) void cand_refine_kernel(const Job* __restrict_
 // order replace the current plane on a strictly lower cost; the first of equal costs wins).
 // mode 2: cost of row-major input planes, optionally per source.
 template <bool FR>
-__device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile_x, int tile_y, float* lds) {
+__device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile_x, int tile_y, float* wcol,
+                                          float* lds) {
   const Args& A = J.A;
   const bool frac = FR && A.frac;
   const int TR = L.tile_rows;
   const int TC = kBlock / TR;  // compacted columns per tile
   const int r = A.halo;
   const int TW = 2 * TC + 2 * r, TH = TR + 2 * r;
-  float* wcol = lds;            // 256
-  float* wsp = lds + 256;       // n_taps
+  float* wsp = lds;             // n_taps
   float* tile_lds = wsp + A.n_taps;
   const int x_org = tile_x * 2 * TC - r;
   const int y_org = tile_y * TR - r;
@@ -719,7 +728,7 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
     const int gx = min(max(x_org + tx, 0), A.W - 1);
     const int gy = min(max(y_org + ty, 0), A.H - 1);
     const unsigned short hb = gl(reinterpret_cast<const unsigned short*>(A.ref))[(size_t)gy * A.W + gx];
-    tile_lds[i] = __half2float(__ushort_as_half(hb));
+    tile_lds[i] = 4.0f * __half2float(__ushort_as_half(hb));  // 4x the grey value, exact
   }
   __syncthreads();
 
@@ -748,22 +757,22 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   rp.var_a = 0.0f;
   if (valid) {
     rp.a_c = tile_lds[(row + r) * TW + 2 * col + par + r];
-    float S_w = 0.0f, S_a = 0.0f, S_aa = 0.0f;
+    float S_w = 0.0f, S_a4 = 0.0f, S_aa16 = 0.0f;  // S_a and S_aa, 4 and 16 times over
     int t = 0;
     for (int k2 = 0; k2 <= 2 * A.R; ++k2) {
       const float* trow = tile_lds + rp.tbase + k2 * A.s * TW;
       for (int k1 = 0; k1 <= 2 * A.R; ++k1, ++t) {
-        const float a = (frac ? ref_tap<true>(A, rp, tile_lds, TW, k1, k2) : trow[k1 * A.s]) - rp.a_c;
-        const float w = wcol[frac ? colour_index<true>(a) : colour_index<false>(a)] * wsp[t];
-        const float wa = w * a;
+        const float a4 = (frac ? ref_tap<true>(A, rp, tile_lds, TW, k1, k2) : trow[k1 * A.s]) - rp.a_c;
+        const float w = (frac ? colour_weight<true>(wcol, a4) : colour_weight<false>(wcol, a4)) * wsp[t];
+        const float wa4 = w * a4;
         S_w = S_w + w;
-        S_a = S_a + wa;
-        S_aa = __builtin_fmaf(wa, a, S_aa);
+        S_a4 = S_a4 + wa4;
+        S_aa16 = __builtin_fmaf(wa4, a4, S_aa16);
       }
     }
     rp.S_w = S_w;
-    rp.mu_a = S_a / S_w;
-    rp.var_a = S_aa / S_w - rp.mu_a * rp.mu_a;
+    rp.mu_a = (S_a4 * 0.25f) / S_w;
+    rp.var_a = (S_aa16 * 0.0625f) / S_w - rp.mu_a * rp.mu_a;
     rp.ok = rp.var_a >= A.eps_v;
   }
   const int lane = threadIdx.x & 63;
@@ -832,6 +841,9 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
 template <bool FR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void eval_kernel(
     const Job* __restrict__ jobs, Launch L) {
+  // the colour-weight table at the start of LDS: a reference difference (x4) is then its
+  // entry's address
+  __shared__ float wcol[256];
   extern __shared__ float lds[];
   __shared__ int next_tile;
   const int xcd = blockIdx.x & 7;
@@ -842,7 +854,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
     int tx, ty;
     band_tile(J, xcd, i - J.xoff[xcd], tx, ty);
-    eval_tile<FR>(J, L, tx, ty, lds);
+    eval_tile<FR>(J, L, tx, ty, wcol, lds);
     return;
   }
   for (;;) {
@@ -854,7 +866,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
     int tx, ty;
     band_tile(J, xcd, i - J.xoff[xcd], tx, ty);
-    eval_tile<FR>(J, L, tx, ty, lds);
+    eval_tile<FR>(J, L, tx, ty, wcol, lds);
     __syncthreads();  // the next tile re-stages LDS
   }
 }
@@ -940,7 +952,7 @@ namespace phimvs_internal {
 size_t eval_lds_bytes(int tile_rows, int max_radius_px, int max_taps) {
   const int TC = kBlock / tile_rows;
   const size_t tw = 2 * TC + 2 * max_radius_px, th = tile_rows + 2 * max_radius_px;
-  return sizeof(float) * (256 + (size_t)max_taps + tw * th);
+  return sizeof(float) * ((size_t)max_taps + tw * th);  // the colour-weight table is static
 }
 
 hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds, hipStream_t st) {
