@@ -111,9 +111,15 @@ def bench_batched(args):
     for i, (ref, srcs, (win, dil)) in enumerate(zip(mv.refs, mv.sources, mv.windows)):
         jobs.append(dict(ref=ref, srcs=srcs, window=win, dilation=dil,
                          params=pm.Params(top_k=min(5, len(srcs)), seed=sg.PM_SEED + i)))
-    best, allr = ctx.autotune(jobs, iters=1)
-    log("[bench] autotune: " + ", ".join(f"rows{r.tile_rows}/p{int(r.persistent)}/{r.wgs_per_cu}={r.ms:.1f}ms"
-                                         for r in allr))
+    if args.tuning:
+        rows, persistent, wgs = (int(v) for v in args.tuning.split(","))
+        ctx.set_tuning(pm.Tuning(rows, bool(persistent), wgs))
+        best, allr = ctx.get_tuning(), []
+        log(f"[bench] launch configuration fixed: rows{rows}/p{persistent}/{wgs}")
+    else:
+        best, allr = ctx.autotune(jobs, iters=1)
+        log("[bench] autotune: " + ", ".join(f"rows{r.tile_rows}/p{int(r.persistent)}/{r.wgs_per_cu}={r.ms:.1f}ms"
+                                             for r in allr))
     outs = [dict(depth=torch.empty(mv.images[j["ref"]].shape, dtype=torch.float32, device="cuda"),
                  normal=torch.empty(mv.images[j["ref"]].shape + (3,), dtype=torch.float32, device="cuda"),
                  cost=torch.empty(mv.images[j["ref"]].shape, dtype=torch.float32, device="cuda")) for j in jobs]
@@ -425,18 +431,74 @@ def learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, ra
     return out
 
 
+def bench_taps(args):
+    """Split of the evaluate kernel's time on the 3200x2130 workload (10 sources, top-5, 8
+    iterations) into a part per window tap and a fixed part per (pixel, hypothesis, view):
+    the same depth map at 3x3 to 19x19 taps (window and dilation varied), and a
+    least-squares line through the evaluate time against the tap count."""
+    import torch
+
+    import paper_2104_06165_amd as pm
+    import scenegen as sg
+
+    scene = sg.workload_scene("highres", device="cuda")
+    sol = sg.SOLVER["highres"]
+    srcs = list(range(1, len(scene.images)))
+    params = pm.Params(top_k=sol["top_k"], bilateral=True, sigma_spatial_px=(sol["window"] - 1) / 2.0,
+                       seed=sg.PM_SEED)
+    ctx = pm.Context(0)
+    ctx.set_scene(scene)
+    rows = []
+    for window, dilation in [(31, 15), (31, 5), (25, 3), (31, 3), (25, 2), (29, 2), (37, 2)]:
+        n = (window - 1) // dilation + 1
+        for _ in range(args.warmup):
+            ctx.patchmatch(0, srcs, window, dilation, sol["iters"], params)
+        torch.cuda.synchronize()
+        ctx.diag_enable(pm.DIAG_TIME | pm.DIAG_COUNT)
+        for _ in range(args.steps):
+            ctx.patchmatch(0, srcs, window, dilation, sol["iters"], params)
+        torch.cuda.synchronize()
+        hyp, launches, kms = ctx.diag_read()
+        ctx.diag_enable(0)
+        rows.append({"window": window, "dilation": dilation, "taps": n * n, "eval_ms": kms / args.steps,
+                     "hypotheses": hyp // args.steps})
+        log(f"[bench] {n}x{n} taps: evaluate {rows[-1]['eval_ms']:.1f} ms per depth map")
+    ctx.close()
+    t = np.array([r["taps"] for r in rows], np.float64)
+    ms = np.array([r["eval_ms"] for r in rows], np.float64)
+    slope, fixed = np.polyfit(t, ms, 1)
+    # wave64 VALU issue: 4 SIMDs per CU, one wave instruction per 4 cycles each
+    wave_instr_per_s = 256 * 4 * 2.4e9 / 4
+    wave_views = np.mean([r["hypotheses"] for r in rows]) * len(srcs) / 64
+    line = {"metric": "evaluate-kernel ms per 3200x2130 depth map against window taps",
+            "value": float(ms[t == 121][0]), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": float(ms[t == 121][0]), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": f"synthetic (seeded piecewise-planar scene, seed {sg.SCENE_SEEDS['highres']})",
+            "config": {"workload": "taps: 1 reference + 10 sources at 3200x2130, top-5, 8 iterations, "
+                                   "3x3 to 19x19 taps"},
+            "fit": {"ms_per_tap": float(slope), "fixed_ms": float(fixed),
+                    "fixed_share_at_121_taps": float(fixed / (fixed + 121 * slope)),
+                    "wave_instr_time_per_tap_view": float(slope * 1e-3 * wave_instr_per_s / wave_views),
+                    "wave_instr_time_fixed_per_view": float(fixed * 1e-3 * wave_instr_per_s / wave_views)},
+            "table": rows}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="highres",
-                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize"])
+                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize", "taps"])
     ap.add_argument("--cpu-iters", type=int, default=2, help="iterations of the oracle's bounded sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy"),
                     help="parameters of the proposal network for the learned-versus-random comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-versus-random comparison")
+    ap.add_argument("--tuning", default="", metavar="ROWS,PERSISTENT,WGS",
+                    help="batched workload: use this launch configuration instead of autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration) and exit")
     args = ap.parse_args()
@@ -467,6 +529,8 @@ def main():
         return bench_batched(args)
     if wl == "resize":
         return bench_resize(args)
+    if wl == "taps":
+        return bench_taps(args)
     scene_name = "mid" if wl.startswith("mid") else wl
     solver = sg.SOLVER[wl]
     cfg = sg.CONFIGS[scene_name]

@@ -263,7 +263,8 @@ int phimvs_fuse(phimvs_ctx* ctx, int n_maps, const phimvs_depth_map* maps, const
  * pixels with depth closest along that line (both sides, fewer if the image ends; none
  * below two points or when the fitted depth is not positive).  depth: device H*W;
  * hyp: device, planar 4*H*W (hypothesis k of pixel p at hyp[k * H * W + p]), 0 = none.
- * FP64 fit. */
+ * FP64 fit.  Work is queued on the context's stream; the library keeps scratch of one bit
+ * per pixel and direction ((4 W + 2 H) H / 8 bytes, rounded up to 64-bit words). */
 int phimvs_phi_hypotheses(phimvs_ctx* ctx, int width, int height, const float* depth, float* hyp);
 
 /* Matching cost (Eq. 5, the prepared problem's cost) of every hypothesis: the fronto-

@@ -81,6 +81,7 @@ struct phimvs_ctx {
   std::vector<FuseMap> fuse_host;
   DevBuf<uint8_t> fuse_alive;
   DevBuf<int32_t> fuse_claim;
+  DevBuf<uint64_t> phi_bits;              // per-direction occupancy bitmaps of the hypothesis fits
   DevBuf<uint8_t> io_u8;
   // diagnostics
   int diag = 0;
@@ -641,6 +642,7 @@ void phimvs_destroy(phimvs_ctx* c) {
   release(c->fuse_maps);
   release(c->fuse_alive);
   release(c->fuse_claim);
+  release(c->phi_bits);
   release(c->io_u8);
   if (c->diag_count) (void)hipFree(c->diag_count);
   for (auto& e : c->diag_events) {
@@ -1054,7 +1056,9 @@ int phimvs_phi_hypotheses(phimvs_ctx* c, int width, int height, const float* dep
   if (!c) return PHIMVS_E_ARG;
   if (width < 1 || height < 1 || !depth || !hyp) return fail(c, PHIMVS_E_ARG, "invalid size or null array");
   HIPCHECK(c, hipSetDevice(c->device));
-  HIPCHECK(c, launch_phi_hypotheses(depth, width, height, hyp, c->stream));
+  int rc = ensure(c, c->phi_bits, phi_bits_words(width, height));
+  if (rc) return rc;
+  HIPCHECK(c, launch_phi_hypotheses(depth, width, height, c->phi_bits.p, hyp, c->stream));
   return PHIMVS_OK;
 }
 

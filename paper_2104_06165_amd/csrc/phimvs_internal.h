@@ -131,7 +131,9 @@ hipError_t launch_fuse(const FuseMap* h_maps, const FuseMap* d_maps, int n_maps,
 struct PhiCam {
   double Kinv[9];
 };
-hipError_t launch_phi_hypotheses(const float* depth, int W, int H, float* hyp, hipStream_t st);
+// 64-bit words of the per-direction occupancy bitmaps of a W x H map (the fit's scratch)
+size_t phi_bits_words(int W, int H);
+hipError_t launch_phi_hypotheses(const float* depth, int W, int H, uint64_t* bits, float* hyp, hipStream_t st);
 hipError_t launch_phi_planes(const float* hyp, size_t n, float* planes, hipStream_t st);
 hipError_t launch_phi_mask_cost(const float* hyp, size_t n, float cmax, float* cost, hipStream_t st);
 hipError_t launch_phi_select(const float* depth, const float* hyp, const float* ref, int W, int H, float* out,

@@ -956,15 +956,24 @@ size_t eval_lds_bytes(int tile_rows, int max_radius_px, int max_taps) {
 }
 
 hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds, hipStream_t st) {
-  // tiles above 64 KiB of LDS (one-row tiles with wide windows) need the opt-in limit
-  static bool raised[2] = {false, false};
-  const void* fn = L.frac ? (const void*)pmk::eval_kernel<true> : (const void*)pmk::eval_kernel<false>;
-  if (lds > 65536 && !raised[L.frac ? 1 : 0]) {
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
-    if (e != hipSuccess) return e;
-    raised[L.frac ? 1 : 0] = true;
-  }
+  // tiles above 64 KiB of LDS (one-row tiles with wide windows) need the opt-in limit,
+  // set once per device and kernel instance
+  constexpr int kMaxDevices = 64;
+  static bool raised[kMaxDevices][2] = {};
   if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  if (lds > 65536) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    bool& done = raised[dev][L.frac ? 1 : 0];
+    if (!done) {
+      const void* fn = L.frac ? (const void*)pmk::eval_kernel<true> : (const void*)pmk::eval_kernel<false>;
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+      if (e != hipSuccess) return e;
+      done = true;
+    }
+  }
   if (L.frac)
     hipLaunchKernelGGL(pmk::eval_kernel<true>, dim3(grid), dim3(kBlock), lds, st, d_jobs, L);
   else

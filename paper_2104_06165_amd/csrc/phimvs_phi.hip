@@ -7,50 +7,154 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <climits>
+
 #include "phimvs_internal.h"
 
 namespace pmp {
 
 using namespace phimvs_internal;
 
-__constant__ int kDir[4][2] = {{1, 0}, {0, 1}, {1, 1}, {1, -1}};
+// Each direction's pixels with depth are held as a bitmap along that direction's lines, so
+// that a fit finds the next pixel with depth on either side with a word scan instead of a
+// pixel-by-pixel walk (holes can span hundreds of pixels).  Direction k, its lines and
+// the position of a pixel on its line:
+//   0 (1, 0):  line y,             position x, W positions
+//   1 (0, 1):  line x,             position y, H positions
+//   2 (1, 1):  line x - y + H - 1, position y, H positions (W + H - 1 lines)
+//   3 (1, -1): line x + y,         position y, H positions (W + H - 1 lines)
+// Word w of line l is at bm[w * lines + l] (so neighbouring lines are neighbouring words);
+// bit b is position 64 w + b; positions outside the image are 0.
+struct PhiBits {
+  uint64_t* bm[4];
+  int lines[4], words[4];
+};
 
-// least-squares line through the six closest pixels with depth along (dx, dy), value at s = 0
-__device__ double line_fit(const float* __restrict__ depth, int W, int H, int x, int y, int dx, int dy) {
+__host__ __device__ inline PhiBits phi_bits_layout(uint64_t* base, int W, int H) {
+  PhiBits B;
+  const int wx = (W + 63) / 64, wy = (H + 63) / 64;
+  B.lines[0] = H;
+  B.words[0] = wx;
+  B.lines[1] = W;
+  B.words[1] = wy;
+  B.lines[2] = B.lines[3] = W + H - 1;
+  B.words[2] = B.words[3] = wy;
+  size_t off = 0;
+  for (int k = 0; k < 4; ++k) {
+    B.bm[k] = base ? base + off : nullptr;
+    off += (size_t)B.lines[k] * B.words[k];
+  }
+  return B;
+}
+
+__device__ __forceinline__ bool has_depth(const float* __restrict__ depth, int W, int x, int y) {
+  return depth[(size_t)y * W + x] > 0.0f;  // the same test as (double)d > 0.0
+}
+
+// direction 0: one wave per 64 pixels of a row, the word is the wave's ballot
+__global__ __launch_bounds__(256) void phi_bits_rows_kernel(const float* __restrict__ depth, int W, int H,
+                                                            PhiBits B) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  const bool v = x < W && has_depth(depth, W, x, y);
+  const uint64_t word = __ballot(v);
+  const int x0 = x & ~63;
+  if ((threadIdx.x & 63) == 0 && x0 < W) B.bm[0][(size_t)(x0 >> 6) * B.lines[0] + y] = word;
+}
+
+// directions 1-3 (blockIdx.z): one thread per (line, word), 64 rows; neighbouring threads
+// take neighbouring lines, which read neighbouring pixels of a row
+__global__ __launch_bounds__(256) void phi_bits_cols_kernel(const float* __restrict__ depth, int W, int H,
+                                                            PhiBits B) {
+  const int k = 1 + blockIdx.z;
+  const int line = blockIdx.x * 256 + threadIdx.x, w = blockIdx.y;
+  if (line >= B.lines[k]) return;
+  uint64_t word = 0;
+  for (int b = 0; b < 64; ++b) {
+    const int y = w * 64 + b;
+    if (y >= H) break;
+    const int x = k == 1 ? line : (k == 2 ? line - (H - 1) + y : line - y);
+    if (x >= 0 && x < W && has_depth(depth, W, x, y)) word |= 1ull << b;
+  }
+  B.bm[k][(size_t)w * B.lines[k] + line] = word;
+}
+
+// nearest position with depth above q on line l (q may be -1), or -1
+__device__ __forceinline__ int bits_up(const uint64_t* __restrict__ bm, int lines, int words, int l, int q) {
+  const int p = q + 1;
+  int w = p >> 6;
+  if (w >= words) return -1;
+  uint64_t bits = bm[(size_t)w * lines + l] & (~0ull << (p & 63));
+  while (bits == 0) {
+    if (++w >= words) return -1;
+    bits = bm[(size_t)w * lines + l];
+  }
+  return w * 64 + __builtin_ctzll(bits);
+}
+
+// nearest position with depth below q on line l, or -1
+__device__ __forceinline__ int bits_down(const uint64_t* __restrict__ bm, int lines, int l, int q) {
+  const int p = q - 1;
+  if (p < 0) return -1;
+  int w = p >> 6;
+  uint64_t bits = bm[(size_t)w * lines + l] & (~0ull >> (63 - (p & 63)));
+  while (bits == 0) {
+    if (--w < 0) return -1;
+    bits = bm[(size_t)w * lines + l];
+  }
+  return w * 64 + 63 - __builtin_clzll(bits);
+}
+
+// Least-squares line through the six pixels with depth closest to (x, y) along direction
+// k, value at step 0.  Candidates are taken by increasing step s, the -s side before the
+// +s side at equal s, until six are taken or both sides leave the image; the sums take
+// them in that order.
+__device__ double line_fit(const float* __restrict__ depth, int W, int H, const PhiBits& B, int k, int x, int y) {
+  const uint64_t* bm = B.bm[k];
+  const int lines = B.lines[k], words = B.words[k];
+  const int l = k == 0 ? y : (k == 1 ? x : (k == 2 ? x - y + H - 1 : x + y));
+  const int pos = k == 0 ? x : y;
+  // along direction 3 a step of +1 lowers the position
+  const bool rev = k == 3;
+  int a = rev ? bits_up(bm, lines, words, l, pos) : bits_down(bm, lines, l, pos);  // side -1
+  int b = rev ? bits_down(bm, lines, l, pos) : bits_up(bm, lines, words, l, pos);  // side +1
   double S0 = 0.0, S1 = 0.0, S2 = 0.0, T0 = 0.0, T1 = 0.0;
   int n = 0;
-  for (int s = 1; n < 6; ++s) {
-    bool any_inside = false;
-    for (int side = -1; side <= 1 && n < 6; side += 2) {
-      const int xs = x + side * s * dx, ys = y + side * s * dy;
-      if (xs < 0 || xs >= W || ys < 0 || ys >= H) continue;
-      any_inside = true;
-      const double d = depth[(size_t)ys * W + xs];
-      if (!(d > 0.0)) continue;
-      const double si = (double)(side * s);
-      S0 = S0 + 1.0;
-      S1 = S1 + si;
-      S2 = S2 + si * si;
-      T0 = T0 + d;
-      T1 = T1 + si * d;
-      ++n;
+  while (n < 6 && (a >= 0 || b >= 0)) {
+    const int sa = a >= 0 ? abs(a - pos) : INT_MAX, sb = b >= 0 ? abs(b - pos) : INT_MAX;
+    int q, step;
+    if (sa <= sb) {
+      q = a;
+      step = -sa;
+      a = rev ? bits_up(bm, lines, words, l, a) : bits_down(bm, lines, l, a);
+    } else {
+      q = b;
+      step = sb;
+      b = rev ? bits_down(bm, lines, l, b) : bits_up(bm, lines, words, l, b);
     }
-    if (!any_inside) break;
+    const int xs = k == 0 ? q : (k == 1 ? x : (k == 2 ? x + (q - y) : x - (q - y)));
+    const int ys = k == 0 ? y : q;
+    const double d = depth[(size_t)ys * W + xs];
+    const double si = (double)step;
+    S0 = S0 + 1.0;
+    S1 = S1 + si;
+    S2 = S2 + si * si;
+    T0 = T0 + d;
+    T1 = T1 + si * d;
+    ++n;
   }
   if (n < 2) return 0.0;
   const double det = S0 * S2 - S1 * S1;
-  const double a = (S2 * T0 - S1 * T1) / det;
-  return a > 0.0 ? a : 0.0;
+  const double a0 = (S2 * T0 - S1 * T1) / det;
+  return a0 > 0.0 ? a0 : 0.0;
 }
 
-__global__ __launch_bounds__(256) void phi_hyp_kernel(const float* __restrict__ depth, int W, int H,
+__global__ __launch_bounds__(256) void phi_hyp_kernel(const float* __restrict__ depth, int W, int H, PhiBits B,
                                                       float* __restrict__ hyp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= W || y >= H) return;
   const size_t p = (size_t)y * W + x, plane = (size_t)W * H;
   const bool hole = !(depth[p] > 0.0f);
-  for (int k = 0; k < 4; ++k)
-    hyp[k * plane + p] = hole ? (float)line_fit(depth, W, H, x, y, kDir[k][0], kDir[k][1]) : 0.0f;
+  for (int k = 0; k < 4; ++k) hyp[k * plane + p] = hole ? (float)line_fit(depth, W, H, B, k, x, y) : 0.0f;
 }
 
 // hypothesis k -> fronto-parallel plane (n = (0, 0, -1), d = h); an empty one gets d = 1
@@ -138,8 +242,19 @@ __global__ void phi_normals_kernel(const float* __restrict__ depth, int W, int H
 
 namespace phimvs_internal {
 
-hipError_t launch_phi_hypotheses(const float* depth, int W, int H, float* hyp, hipStream_t st) {
-  hipLaunchKernelGGL(pmp::phi_hyp_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, depth, W, H, hyp);
+size_t phi_bits_words(int W, int H) {
+  const pmp::PhiBits B = pmp::phi_bits_layout(nullptr, W, H);
+  size_t n = 0;
+  for (int k = 0; k < 4; ++k) n += (size_t)B.lines[k] * B.words[k];
+  return n;
+}
+
+hipError_t launch_phi_hypotheses(const float* depth, int W, int H, uint64_t* bits, float* hyp, hipStream_t st) {
+  const pmp::PhiBits B = pmp::phi_bits_layout(bits, W, H);
+  hipLaunchKernelGGL(pmp::phi_bits_rows_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, depth, W, H, B);
+  hipLaunchKernelGGL(pmp::phi_bits_cols_kernel, dim3((W + H - 1 + 255) / 256, B.words[1], 3), dim3(256), 0, st,
+                     depth, W, H, B);
+  hipLaunchKernelGGL(pmp::phi_hyp_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, depth, W, H, B, hyp);
   return hipGetLastError();
 }
 

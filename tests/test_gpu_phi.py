@@ -58,6 +58,37 @@ def test_hypotheses_parity(ctx, tiny):
     assert np.array_equal(g, o)
 
 
+def hole_map(seed, H, W, kind):
+    """Depths in [1, 9] with holes: sparse (90% empty), blocks (rectangles and a band wider
+    than one 64-pixel word, negative and NaN entries), empty, or full."""
+    r = np.random.default_rng(seed)
+    d = r.uniform(1.0, 9.0, size=(H, W)).astype(np.float32)
+    if kind == "sparse":
+        d[r.uniform(size=(H, W)) < 0.9] = 0.0
+    elif kind == "blocks":
+        for _ in range(6):
+            y, x = r.integers(0, H), r.integers(0, W)
+            d[y:y + r.integers(1, 40), x:x + r.integers(1, 90)] = 0.0
+        y = r.integers(0, H)
+        d[y:y + 5, max(0, W // 2 - 150):W // 2 + 150] = 0.0
+        d[r.uniform(size=(H, W)) < 0.01] = -1.0
+        d[r.uniform(size=(H, W)) < 0.005] = np.nan
+    elif kind == "empty":
+        d[:] = 0.0
+    return d
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 150), (150, 1), (3, 65), (67, 130), (64, 64), (129, 400)])
+@pytest.mark.parametrize("kind", ["sparse", "blocks", "empty", "full"])
+def test_hypotheses_parity_shapes(ctx, H, W, kind):
+    """Image sizes around the 64-pixel words of the occupancy bitmaps, single rows and
+    columns, holes reaching the image border and spanning several words: bitwise."""
+    d = hole_map(H * 1000 + W, H, W, kind)
+    g = ctx.phi_hypotheses(torch.from_numpy(d).cuda()).cpu().numpy().transpose(1, 2, 0)
+    o = oracle.phi_hypotheses(d)
+    assert np.array_equal(g, o), f"{H}x{W} {kind}: {(g != o).sum()} of {g.size} differ"
+
+
 def test_costs_parity(ctx, tiny):
     d = holey_depth(tiny)
     srcs = list(range(1, len(tiny.images)))
