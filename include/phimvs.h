@@ -137,7 +137,9 @@ int phimvs_set_state(phimvs_ctx* ctx, const float* planes, const float* cost, in
 int phimvs_output(phimvs_ctx* ctx, float* depth, float* normal, float* cost, int on_device);
 /* Cost (Eq. 5) of the given planes at every pixel; per_view (H*W*n_srcs, or NULL)
  * receives each source's 1 - Z (PHIMVS_COST_MAX when that source is invalid) and
- * valid (H*W*n_srcs bytes, or NULL) its validity flag. */
+ * valid (H*W*n_srcs bytes, or NULL) its validity flag.  A plane whose depth is NaN
+ * fails the border rule in every source: cost PHIMVS_COST_MAX, every source invalid
+ * (written without evaluating the window). */
 int phimvs_eval_cost(phimvs_ctx* ctx, const float* planes, float* cost, float* per_view, uint8_t* valid,
                      int on_device);
 

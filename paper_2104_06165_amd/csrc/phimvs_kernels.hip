@@ -707,7 +707,8 @@ __global__ __launch_bounds__(128) void cand_refine_kernel(const Job* __restrict_
 // lane per pixel.  mode 0: initialisation (slot 0, the random plane, is taken; slot 1, a
 // proposal, replaces it when not more expensive).  mode 1: update (candidates 0..ncand-1 in
 // order replace the current plane on a strictly lower cost; the first of equal costs wins).
-// mode 2: cost of row-major input planes, optionally per source.
+// mode 2: cost of row-major input planes, optionally per source (a plane whose depth is NaN
+// scores C_max with every source invalid).
 template <bool FR>
 __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile_x, int tile_y, float* wcol,
                                           float* lds) {
@@ -780,12 +781,18 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   if (L.mode == 2) {
     if (in_img) {
       const size_t p = (size_t)y * A.W + x;
-      if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(__ballot(valid)));
       float c = kCmax;
       float* pv = J.per_view_out ? J.per_view_out + p * A.n_src : nullptr;
       uint8_t* vm = J.valid_out ? J.valid_out + p * A.n_src : nullptr;
-      if (valid) {
-        const float4 pl = ld4(reinterpret_cast<const float4*>(J.planes_in), p);
+      float4 pl = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (valid) pl = ld4(reinterpret_cast<const float4*>(J.planes_in), p);
+      // a plane whose depth is NaN fails the border rule in every source, so it scores
+      // C_max with every source invalid: written without evaluating it (waves whose
+      // planes are all such skip the tap passes)
+      const bool score = valid && !__builtin_isnan(pl.w);
+      const unsigned long long bal = __ballot(score);
+      if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(bal));
+      if (score) {
         c = plane_cost<FR>(A, rp, tile_lds, TW, wcol, wsp, pl.x, pl.y, pl.z, pl.w, pv, vm);
       } else {
         for (int j = 0; j < A.n_src; ++j) {

@@ -157,8 +157,8 @@ __global__ __launch_bounds__(256) void phi_hyp_kernel(const float* __restrict__ 
   for (int k = 0; k < 4; ++k) hyp[k * plane + p] = hole ? (float)line_fit(depth, W, H, B, k, x, y) : 0.0f;
 }
 
-// hypothesis k -> fronto-parallel plane (n = (0, 0, -1), d = h); an empty one gets d = 1
-// (finite arithmetic; its cost is replaced afterwards)
+// hypothesis k -> fronto-parallel plane (n = (0, 0, -1), d = h); an empty one gets d = NaN,
+// which the cost evaluation scores C_max without running the window
 __global__ void phi_planes_kernel(const float* __restrict__ hyp, size_t n, float* __restrict__ planes) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -166,7 +166,7 @@ __global__ void phi_planes_kernel(const float* __restrict__ hyp, size_t n, float
   planes[4 * i] = 0.0f;
   planes[4 * i + 1] = 0.0f;
   planes[4 * i + 2] = -1.0f;
-  planes[4 * i + 3] = h > 0.0f ? h : 1.0f;
+  planes[4 * i + 3] = h > 0.0f ? h : __int_as_float(0x7fc00000);
 }
 
 __global__ void phi_mask_cost_kernel(const float* __restrict__ hyp, size_t n, float cmax, float* __restrict__ cost) {

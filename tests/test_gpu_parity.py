@@ -106,8 +106,12 @@ def _test_planes(scene, pb, rng):
     rnd[..., :3] = n  # about half of them face away (cost C_max expected)
     lo, hi = scene.depth_range
     rnd[..., 3] = rng.uniform(lo, hi, size=(H, W))
+    # planes without a depth (NaN): whole rows (entire waves) and 30% of the other pixels
+    gtn = gt.astype(np.float32).astype(np.float64)
+    gtn[20:60, :, 3] = np.nan
+    gtn[..., 3][rng.uniform(size=(H, W)) < 0.3] = np.nan
     return {"init": init_p, "gt": gt.astype(np.float32).astype(np.float64),
-            "random": rnd.astype(np.float32).astype(np.float64)}
+            "random": rnd.astype(np.float32).astype(np.float64), "gt_nan_depths": gtn}
 
 
 def test_eval_cost_parity_tiny(ctx, tiny):
