@@ -20,6 +20,10 @@
  *     whose reference window leaves the image are invalid: depth 0, normal 0,
  *     cost PHIMVS_COST_MAX.
  *   - "planes" arrays are H*W*4 float32 (n.x, n.y, n.z, d) per pixel, row-major.
+ *   - Limits (beyond them calls fail with PHIMVS_E_UNSUPPORTED): images below 2^28
+ *     pixels; at most PHIMVS_MAX_SOURCES source views per reference; at most 31 taps
+ *     per window side and a window radius (dilation x taps per side from the centre)
+ *     of at most 30 px, 29 px with the window-resize scheme.
  *
  * Ownership and memory
  *   - The caller owns every buffer it passes.  phimvs_set_views copies the images

@@ -193,6 +193,8 @@ def test_patchmatch_parity_tiny(ctx, tiny):
     (97, 50, 1, 7, 3, 0, False),     # one source, dilation 3, plain Eq. 4 weights
     (200, 9, 2, 7, 1, 2, True),      # 1 valid row band
     (64, 40, 6, 5, 1, 3, True),      # six sources
+    (100, 72, 2, 61, 2, 0, True),    # the largest window: 31 taps per side over a 30-pixel radius
+    (96, 64, 12, 7, 1, 5, True),     # the most sources (12)
 ])
 def test_edge_case_parity(ctx, W, H, n_src, window, dilation, top_k, bilateral):
     scene = sg.make_scene(100 + W + H, sg.tiny_config(W, H, n_src=n_src, n_planes=3, n_textureless=1), device="cuda")
@@ -238,6 +240,28 @@ def test_argument_errors(ctx, tiny):
         ctx.patchmatch(0, [1, 2], 11, 1, 1, pm.Params(top_k=3))  # top_k > n_srcs
     with pytest.raises(pm.PhimvsError):
         ctx.prepare(0, [1], 11, 1, pm.Params(sigma_color=-1.0))
+
+
+def test_size_limits(ctx, tiny):
+    """Requests beyond the documented limits fail with PHIMVS_E_UNSUPPORTED (-5)."""
+    scene, cfg = tiny
+    ctx.set_scene(scene)
+    for window, dilation in [(63, 1), (67, 3)]:  # 32 taps per side; a 33-pixel radius
+        with pytest.raises(pm.PhimvsError) as e:
+            ctx.patchmatch(0, [1], window, dilation, 1)
+        assert e.value.code == -5
+    many = sg.make_scene(11, sg.tiny_config(40, 30, n_src=13, n_planes=1), device="cuda")
+    ctx.set_scene(many)
+    with pytest.raises(pm.PhimvsError) as e:  # 13 sources
+        ctx.patchmatch(0, list(range(1, 14)), 5, 1, 1)
+    assert e.value.code == -5
+    K = np.array([[100.0, 0.0, 8.0], [0.0, 100.0, 8.0], [0.0, 0.0, 1.0]])
+    big = np.zeros((1 << 14, 1 << 14), np.uint8)  # 2^28 pixels
+    with pytest.raises(pm.PhimvsError) as e:
+        ctx.set_views([big, np.zeros((16, 16), np.uint8)], np.stack([K, K]), np.stack([np.eye(3)] * 2),
+                      np.zeros((2, 3)), np.tile([1.0, 10.0], (2, 1)))
+    assert e.value.code == -5
+    ctx.set_scene(scene)
 
 
 # ----------------------------------------------------------------------------- high-resolution workload
