@@ -632,14 +632,20 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
   const GLOBAL float* __restrict__ ocost = gl(A.cost[oc]);
   float rx, ry, rz;
   ray_f(A, x, y, rx, ry, rz);
+#pragma unroll
   for (int g = 0; g < 8; ++g) {
     float4 cand = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
     if (valid) {
       const int dir = g & 3;
       const bool far = g >= 4;
       const int count = far ? 10 : 9;
-      int qx = -1, qy = -1;
-      float qc = 0.0f;
+      // every offset's cost is loaded first (at index 0 where the offset is unusable), so
+      // that the region's loads are in flight together; then the usable ones are compared
+      // in enumeration order
+      int xs[10], ys[10];
+      bool use[10];
+      float cs_[10];
+#pragma unroll
       for (int i = 0; i < count; ++i) {
         const int dx = far ? 0 : (int)kNearUp[i][0];
         const int dy = far ? -(2 * (i + 3) + 1) : (int)kNearUp[i][1];
@@ -648,11 +654,16 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
         else if (dir == 1) { ox = dx; oy = -dy; }
         else if (dir == 2) { ox = dy; oy = dx; }
         else { ox = -dy; oy = dx; }
-        const int xq = x + ox, yq = y + oy;
-        if (xq < 0 || xq >= A.W || yq < 0 || yq >= A.H || !pixel_valid(A, xq, yq)) continue;
-        const float c = ocost[(size_t)yq * A.Wc + (xq >> 1)];
-        if (qx < 0 || c < qc) { qx = xq; qy = yq; qc = c; }
+        xs[i] = x + ox;
+        ys[i] = y + oy;
+        use[i] = !(xs[i] < 0 || xs[i] >= A.W || ys[i] < 0 || ys[i] >= A.H || !pixel_valid(A, xs[i], ys[i]));
+        cs_[i] = ocost[use[i] ? (size_t)ys[i] * A.Wc + (xs[i] >> 1) : 0];
       }
+      int qx = -1, qy = -1;
+      float qc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < count; ++i)
+        if (use[i] && (qx < 0 || cs_[i] < qc)) { qx = xs[i]; qy = ys[i]; qc = cs_[i]; }
       if (qx >= 0) {
         const float4 q = ld4(oplane, (size_t)qy * A.Wc + (qx >> 1));
         float rqx, rqy, rqz;
