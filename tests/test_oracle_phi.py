@@ -46,6 +46,41 @@ def test_six_closest_samples_and_numpy_fit():
     assert np.all(hyp[0, :, 1:] == 0)
 
 
+@pytest.mark.parametrize("k", range(4))
+def test_tie_at_the_sixth_sample_takes_the_negative_side(k):
+    """Samples at steps -1, +1, -2, +2, -3, -4, +4 along direction k: the six closest
+    are those up to |s| = 3 and then -4 (the negative side first on the tie at 4), so
+    the fit equals numpy's on exactly those six; step +s is (x + s dx, y + s dy)."""
+    dx, dy = DIRS[k]
+    H = W = 21
+    x0 = y0 = 10
+    steps = [-1, 1, -2, 2, -3, -4, 4]
+    r = np.random.default_rng(k)
+    vals = r.uniform(2.0, 6.0, len(steps)).astype(np.float32)
+    d = np.zeros((H, W), np.float32)
+    for st, v in zip(steps, vals):
+        d[y0 + st * dy, x0 + st * dx] = v
+    hyp = oracle.phi_hypotheses(d)
+    take = steps[:6]
+    coef = np.polyfit(np.array(take, np.float64), vals[:6].astype(np.float64), 1)
+    assert np.isclose(hyp[y0, x0, k], np.polyval(coef, 0.0), rtol=1e-6)
+    # with +4 instead of -4 the value differs, so the tie order is what decides it
+    alt = np.polyfit(np.array(steps[:5] + [4], np.float64), np.r_[vals[:5], vals[6]].astype(np.float64), 1)
+    assert not np.isclose(np.polyval(alt, 0.0), np.polyval(coef, 0.0), rtol=1e-6)
+
+
+def test_negative_and_nan_depths_are_holes():
+    r = np.random.default_rng(4)
+    d = r.uniform(1.0, 9.0, (15, 17)).astype(np.float32)
+    d[r.uniform(size=d.shape) < 0.5] = 0.0
+    bad = d.copy()
+    neg = r.uniform(size=d.shape) < 0.1
+    nan = (r.uniform(size=d.shape) < 0.1) & ~neg
+    bad[neg & (d == 0)] = -2.0
+    bad[nan & (d == 0)] = np.nan
+    assert np.array_equal(oracle.phi_hypotheses(bad), oracle.phi_hypotheses(d))
+
+
 def test_too_few_samples_or_negative_fit_give_no_hypothesis():
     d = np.zeros((1, 20), np.float32)
     d[0, 3] = 4.0
