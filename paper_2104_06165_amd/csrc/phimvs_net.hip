@@ -9,7 +9,8 @@
 // on the matrix cores (v_mfma_f32_16x16x16bf16_1k).  Activations are NHWC with the
 // channel count padded to a multiple of 16.  A convolution is an implicit GEMM over
 // K = 9 taps x input channels: one wave computes 16 pixels of one image row x 16
-// output channels per matrix instruction.  Training runs on the same kernels: the data
+// output channels per matrix instruction; a workgroup of 16 waves stages the layer's
+// weights in LDS once, so only the input patches go through the texture path.  Training runs on the same kernels: the data
 // gradient is the forward convolution with flipped, transposed weights; the weight
 // gradient accumulates (input patch)^T x (output gradient) over 16-pixel slices per
 // image row, written as per-row partial sums and reduced in a fixed order.
@@ -41,10 +42,25 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint
 // w: bf16 [9][CO][CI]; CO multiple of 16.  Output: bf16 (y16, CO channels) and / or fp32
 // (y32, first co_keep channels).  If mask16 is given the result is multiplied by
 // (mask16 > 0) (ReLU backward of the producing layer) before storing.
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
+constexpr int kConvBlock = 1024;  // 16 waves, each 16 pixels of a row
+constexpr int kMaxCI = 32;        // widest layer input (channels, padded)
+constexpr int kConvPad = 4;       // bf16 padding of each LDS weight row (spreads the banks)
+__global__ __launch_bounds__(kConvBlock) void conv3x3_kernel(ConvArgs a) {
+  // the weights [9][CO][CI], staged once per workgroup; each (tap, output channel) row padded
+  __shared__ uint2 wl[9 * kMaxCO * (kMaxCI + kConvPad) / 4];
+  const int q = a.CI / 4, qp = (a.CI + kConvPad) / 4;
+  {
+    const uint2* __restrict__ wg = reinterpret_cast<const uint2*>(a.wt);
+    for (int i = threadIdx.x; i < 9 * a.CO * q; i += kConvBlock) {
+      const int row = i / q, k = i - row * q;
+      wl[row * qp + k] = wg[i];
+    }
+  }
+  __syncthreads();
+  const uint16_t* ws = reinterpret_cast<const uint16_t*>(wl);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int segs = (a.w + 15) / 16;
-  const int task = blockIdx.x * 4 + wave;  // (b, r, seg)
+  const int task = blockIdx.x * (kConvBlock / 64) + wave;  // (b, r, seg)
   if (task >= a.B * a.h * segs) return;
   const int seg = task % segs;
   const int br = task / segs;
@@ -68,7 +84,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
       for (int i = 0; i < kMaxCO / 16; ++i) {
         if (i < nco) {
           const int co = i * 16 + lr;
-          const v4s Bf = *reinterpret_cast<const v4s*>(a.wt + ((size_t)t * a.CO + co) * a.CI + ci);
+          const v4s Bf = *reinterpret_cast<const v4s*>(ws + (t * a.CO + co) * (qp * 4) + ci);
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bf, acc[i], 0, 0, 0);
         }
       }
@@ -365,7 +381,10 @@ namespace phimvs_net_internal {
 hipError_t launch_conv(const ConvArgs& a, hipStream_t st) {
   const int segs = (a.w + 15) / 16;
   const int tasks = a.B * a.h * segs;
-  hipLaunchKernelGGL(pmn::conv3x3_kernel, dim3((tasks + 3) / 4), dim3(256), 0, st, a);
+  if (a.CI % 16 || a.CO % 16 || a.CI < 16 || a.CO < 16 || a.CI > pmn::kMaxCI || a.CO > kMaxCO)
+    return hipErrorInvalidValue;
+  constexpr int wpb = pmn::kConvBlock / 64;
+  hipLaunchKernelGGL(pmn::conv3x3_kernel, dim3((tasks + wpb - 1) / wpb), dim3(pmn::kConvBlock), 0, st, a);
   return hipGetLastError();
 }
 
