@@ -4,9 +4,10 @@
 // neighbour's bilinear depth and its normal at the rounded position, and the neighbour's
 // point is carried back to test the re-projection error.  FP64 throughout, each step
 // written out in the order stated (no contraction), so the keep / drop decision of every
-// pixel is the one a sequential FP64 evaluation takes.  The work is a few hundred FP64
-// operations and about 30 bytes of gathers per pixel and neighbour: bound by the
-// memory system, not by arithmetic.
+// pixel is the one a sequential FP64 evaluation takes.  The work is about 250 FP64
+// instructions (the camera chain, four divisions, a square root) and about 30 bytes of
+// gathers per pixel and neighbour, so the FP64 pipe and the memory system are both
+// about half busy.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
