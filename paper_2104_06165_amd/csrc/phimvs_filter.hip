@@ -6,8 +6,8 @@
 // written out in the order stated (no contraction), so the keep / drop decision of every
 // pixel is the one a sequential FP64 evaluation takes.  The work is about 250 FP64
 // instructions (the camera chain, four divisions, a square root) and about 30 bytes of
-// gathers per pixel and neighbour, so the FP64 pipe and the memory system are both
-// about half busy.
+// gathers per pixel and neighbour: the FP64 instruction stream is the tighter limit
+// (the vector ALU about 80% busy), the memory system about half.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
