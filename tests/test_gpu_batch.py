@@ -75,6 +75,25 @@ def test_batch_equals_single_runs(ctx, mv, tuning, use_graph):
     say(f"batch of {len(jobs)} jobs == single runs ({tuning}, graph={use_graph})")
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_mixing_window_resize_and_integer_jobs(ctx, mv, use_graph):
+    """A launch that holds a window-resize job runs the fractional-spacing kernel instance
+    for every job in it: each job, resize or integer spacing, still equals its single run
+    bitwise."""
+    iters = 2
+    jobs = jobs_of(mv)
+    j0 = jobs[0]  # radius 6 sampled by 5 taps per side (spacing 6/5)
+    jobs[0] = dict(j0, window=13, dilation=1,
+                   params=pm.Params(top_k=j0["params"].top_k, seed=j0["params"].seed, tap_radius=5))
+    ctx.set_tuning(pm.Tuning(4, False, 0))
+    ref = single_runs(ctx, jobs, iters)
+    outs = ctx.patchmatch_batch(jobs, iters, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for k, ((d, n, c), (rd, rn, rc)) in enumerate(zip(outs, ref)):
+        assert torch.equal(d, rd) and torch.equal(n, rn) and torch.equal(c, rc), f"job {k}"
+    say(f"mixed batch ({len(jobs)} jobs, one window-resize) == single runs (graph={use_graph})")
+
+
 def test_graph_replays_with_eager_work_between(ctx, mv):
     iters = 2
     jobs = jobs_of(mv)
