@@ -1,9 +1,9 @@
 """The steps after estimation on the batched workload's full-size depth maps (24
 references from the 40-camera scene, 8 iterations): the consistency filter of two
-references against the oracle (whole maps, bitwise), plane hypotheses and Eq. 10 normals
-of a filtered map (whole map, bitwise), fusion of the eight 960x640 maps against the
-oracle's sequential walk (bitwise), and fusion of all 24 maps (73 M pixels) checked by
-the invariants any fusion must keep."""
+references against the oracle (whole maps, bitwise), plane hypotheses and Eq. 10
+normals of a filtered 960x640 and a filtered 3200x2130 map (whole maps, bitwise),
+fusion of the eight 960x640 maps against the oracle's sequential walk (bitwise), and
+fusion of all 24 maps (73 M pixels) checked by the invariants any fusion must keep."""
 import sys
 
 import numpy as np
@@ -65,14 +65,15 @@ def test_filter_full_size(run):
         assert np.array_equal(gc, oc) and np.array_equal(gd, od) and np.array_equal(gn, on)
 
 
-def test_phi_steps_full_size(run):
+@pytest.mark.parametrize("i", [2, 0], ids=["960x640", "3200x2130"])
+def test_phi_steps_full_size(run, i):
     mv, ctx, jobs, filtered = run
-    i = 2
     d = filtered[i][0]
     hyp = ctx.phi_hypotheses(d).cpu().numpy().transpose(1, 2, 0)
     dn = d.cpu().numpy()
     o = oracle.phi_hypotheses(dn)
-    say(f"hypotheses of job {i}: {(dn <= 0).mean():.3f} of pixels empty, bitwise {np.array_equal(hyp, o)}")
+    say(f"hypotheses of job {i} ({dn.shape[1]}x{dn.shape[0]}): {(dn <= 0).mean():.3f} of pixels empty, "
+        f"bitwise {np.array_equal(hyp, o)}")
     assert np.array_equal(hyp, o)
     nrm = ctx.phi_normals(jobs[i]["ref"], d).cpu().numpy()
     assert np.array_equal(nrm, oracle.phi_normals(dn, mv.K[jobs[i]["ref"]]))
