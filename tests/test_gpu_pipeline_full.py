@@ -2,8 +2,8 @@
 references from the 40-camera scene, 8 iterations): the consistency filter of two
 references against the oracle (whole maps, bitwise), plane hypotheses and Eq. 10
 normals of a filtered 960x640 and a filtered 3200x2130 map (whole maps, bitwise),
-fusion of the eight 960x640 maps against the oracle's sequential walk (bitwise), and
-fusion of all 24 maps (73 M pixels) checked by the invariants any fusion must keep."""
+fusion of the eight 960x640 maps and of all 24 maps (73 M pixels) against the oracle's
+sequential walk (bitwise), and the invariants any fusion must keep on all 24."""
 import sys
 
 import numpy as np
@@ -88,6 +88,19 @@ def test_fusion_small_maps_against_oracle(run):
     o = oracle.fuse([filtered[i][0].cpu().numpy() for i in sel], mv.K[views], mv.R[views], mv.t[views])
     say(f"fusion of {len(sel)} 960x640 maps: {(o[1] > 0).sum()} points, mean support {o[1][o[1] > 0].mean():.2f}; "
         f"bitwise points {np.array_equal(pts, o[0])}, support {np.array_equal(sup, o[1])}, owner {np.array_equal(own, o[2])}")
+    assert np.array_equal(sup, o[1]) and np.array_equal(own, o[2]) and np.array_equal(pts, o[0])
+
+
+def test_fusion_all_maps_against_oracle(run):
+    """All 24 filtered maps (three sizes, 73 M pixels) against the oracle's sequential walk."""
+    mv, ctx, jobs, filtered = run
+    maps = [(j["ref"], filtered[i][0]) for i, j in enumerate(jobs)]
+    pts, sup, own = [t.cpu().numpy() for t in ctx.fuse(maps)]
+    views = [j["ref"] for j in jobs]
+    o = oracle.fuse([filtered[i][0].cpu().numpy() for i in range(len(jobs))], mv.K[views], mv.R[views],
+                    mv.t[views])
+    say(f"fusion of all {len(jobs)} maps: {(o[1] > 0).sum()} points; bitwise points {np.array_equal(pts, o[0])}, "
+        f"support {np.array_equal(sup, o[1])}, owner {np.array_equal(own, o[2])}")
     assert np.array_equal(sup, o[1]) and np.array_equal(own, o[2]) and np.array_equal(pts, o[0])
 
 
