@@ -1,7 +1,8 @@
 """The steps after estimation on the batched workload's full-size depth maps (24
-references from the 40-camera scene, 8 iterations): the consistency filter of two
-references against the oracle (whole maps, bitwise), plane hypotheses and Eq. 10
-normals of a filtered 960x640 and a filtered 3200x2130 map (whole maps, bitwise),
+references from the 40-camera scene, 8 iterations): the consistency filter of three
+references, one of each size, against the oracle (whole maps, bitwise), plane
+hypotheses and Eq. 10 normals of a filtered 960x640 and a filtered 3200x2130 map
+(whole maps, bitwise),
 fusion of the eight 960x640 maps and of all 24 maps (73 M pixels) against the oracle's
 sequential walk (bitwise), and the invariants any fusion must keep on all 24."""
 import sys
@@ -55,7 +56,7 @@ def test_filter_full_size(run):
     mv, ctx, jobs, filtered = run
     depths = {j["ref"]: j["depth"].cpu().numpy() for j in jobs}
     normals = {j["ref"]: j["normal"].cpu().numpy() for j in jobs}
-    for i in (2, 1):  # a 960x640 and a 1600x1066 reference
+    for i in (2, 1, 0):  # a 960x640, a 1600x1066 and a 3200x2130 reference
         nb = filtered[i][3]
         od, on, oc = oracle.consistency(depths, normals, mv.K, mv.R, mv.t, jobs[i]["ref"],
                                         [jobs[k]["ref"] for k in nb])
