@@ -2,9 +2,9 @@
 references from the 40-camera scene, 8 iterations): the consistency filter of three
 references, one of each size, against the oracle (whole maps, bitwise), plane
 hypotheses and Eq. 10 normals of a filtered 960x640 and a filtered 3200x2130 map
-(whole maps, bitwise),
-fusion of the eight 960x640 maps and of all 24 maps (73 M pixels) against the oracle's
-sequential walk (bitwise), and the invariants any fusion must keep on all 24."""
+(whole maps, bitwise), fusion of the eight 960x640 maps and of all 24 maps (73 M
+pixels) against the oracle's sequential walk (bitwise), and the invariants any fusion
+must keep on all 24."""
 import sys
 
 import numpy as np
