@@ -428,6 +428,16 @@ def learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, ra
         out["speedup_at_equal_cost"] = out["random_ms_at_target"] / out["learned_ms"]
         out["learned_at_target"] = learned[k_learned]
         out["random_final"] = rand[iters]
+    # the ceiling of any initialisation under this metric: the scene's true planes as the
+    # proposal (the search converges below their cost, so they too need iterations)
+    true_p = np.concatenate([scene.gt_normal, scene.gt_depth[..., None]], -1).astype(np.float32)
+    gt_planes = torch.from_numpy(np.ascontiguousarray(true_p)).to(proposal.device)
+    k_gt = None
+    for k in range(iters + 1):
+        if stats(*ctx.patchmatch_proposal(0, srcs, win, dil, k, gt_planes, params)[::2])["mean_cost"] <= target:
+            k_gt = k
+            break
+    out["true_planes_iters_to_target"] = k_gt
     return out
 
 
