@@ -495,13 +495,58 @@ def bench_taps(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_train(args):
+    """One training step of the proposal network at the training shape: a minibatch of 8
+    samples at 267x400 (1/4 of 1600x1066), 5 input channels, masked loss, gradient of
+    every layer and an Adam step, on seeded synthetic inputs and targets."""
+    import torch
+
+    import paper_2104_06165_amd as pm
+
+    B, h, w = 8, 267, 400
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.rand((B, h, w, 5), generator=g, device="cuda")
+    nrm = torch.nn.functional.normalize(torch.randn((B, h, w, 3), generator=g, device="cuda"), dim=-1)
+    nrm[..., 2] = -nrm[..., 2].abs()
+    rng = torch.tensor([1.0, 20.0], device="cuda").repeat(B, 1).contiguous()
+    dep = 1.0 + 19.0 * torch.rand((B, h, w, 1), generator=g, device="cuda")
+    target = torch.cat([dep, nrm], -1).contiguous()
+    mask = (torch.rand((B, h, w), generator=g, device="cuda") < 0.7).float().contiguous()
+    net = pm.Net(0, np.load(args.weights) if os.path.exists(args.weights) else None)
+    step = lambda: (net.loss_grad(x, target, mask, rng, 1.0, want_loss=True), net.adam(1e-3))  # noqa: E731
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    net.close()
+    # flops per pixel: forward, weight gradient and data gradient (none for the input layer)
+    fwd = sum(2 * 9 * ci * co for ci, co in pm.Net.SHAPES)
+    per_px = 2 * fwd + (fwd - 2 * 9 * pm.Net.SHAPES[0][0] * pm.Net.SHAPES[0][1])
+    flops = per_px * B * h * w
+    line = {"metric": "ms per proposal-network training step (minibatch 8 at 267x400)", "value": ms, "unit": "ms",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+            "data": "synthetic (seeded random inputs and targets)",
+            "config": {"workload": "train: 5-layer 3x3 network (5-32-32-32-32-4), bf16 MFMA, minibatch 8 at "
+                                   "267x400, masked loss, all gradients, Adam"},
+            "samples_per_s": B / (ms * 1e-3),
+            "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": flops / (ms * 1e-3) / 1e12 / 2500.0, "traffic": None,
+                         "note": "whole step (loss read back to the host each step, as in training)"}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="highres",
-                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize", "taps"])
+                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize", "taps", "train"])
     ap.add_argument("--cpu-iters", type=int, default=2, help="iterations of the oracle's bounded sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy"),
@@ -541,6 +586,8 @@ def main():
         return bench_resize(args)
     if wl == "taps":
         return bench_taps(args)
+    if wl == "train":
+        return bench_train(args)
     scene_name = "mid" if wl.startswith("mid") else wl
     solver = sg.SOLVER[wl]
     cfg = sg.CONFIGS[scene_name]

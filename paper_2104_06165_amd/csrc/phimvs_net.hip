@@ -13,7 +13,8 @@
 // weights in LDS once, so only the input patches go through the texture path.  Training runs on the same kernels: the data
 // gradient is the forward convolution with flipped, transposed weights; the weight
 // gradient accumulates (input patch)^T x (output gradient) over 16-pixel slices per
-// image row, written as per-row partial sums and reduced in a fixed order.
+// image row, written as per-row partial sums and reduced in a fixed order (16
+// interleaved groups of rows, then the groups in turn).
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_bfloat16.h>
@@ -111,61 +112,133 @@ __global__ __launch_bounds__(kConvBlock) void conv3x3_kernel(ConvArgs a) {
 
 // Weight gradient partials: for image row (b, r): P[b r][t][ci][co] = sum_c x[b, r+dy, c+dx, ci] *
 // g[b, r, c, co]; bias partial Pb[b r][co] = sum_c g[b, r, c, co].  One workgroup per image row;
-// wave k of 4 handles the taps t = k, k + 4, k + 8 for every (ci, co) block.
+// wave k of 4 handles the taps t = k, k + 4, k + 8 for every (ci, co) block.  The row is
+// walked in chunks of 64 pixels staged in LDS by coalesced loads (the three input rows
+// and the output-gradient row); every accumulator takes its 16-pixel slices in row order.
+constexpr int kWgChunk = 64;   // pixels staged per step (4 slices of 16)
+constexpr int kWgStride = 36;  // bf16 per staged pixel: 32 channels + 4 of padding (spreads the banks)
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a) {
+  // rows r - 1 .. r + 1 of the input (pixels c_base - 1 .. c_base + 64) and row r of the
+  // output gradient (pixels c_base .. c_base + 63), zero outside the image
+  __shared__ uint2 xs2[3 * (kWgChunk + 2) * kWgStride / 4];
+  __shared__ uint2 gs2[kWgChunk * kWgStride / 4];
   const int br = blockIdx.x;
   if (br >= a.B * a.h) return;
   const int r = br % a.h, b = br / a.h;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int nci = a.CI / 16, nco = a.CO / 16;
-  for (int t = wave; t < 9; t += 4) {
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
-    const int rr = r + dy;
-    for (int cib = 0; cib < nci; ++cib)
-      for (int cob = 0; cob < nco; ++cob) {
-        v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
-        for (int c0 = 0; c0 < a.w; c0 += 16) {
-          // A (16 ci x 16 px): lane -> ci = 16 cib + lr, pixels c0 + 4 lk .. + 3
-          // B (16 px x 16 co): lane -> co = 16 cob + lr, pixels c0 + 4 lk .. + 3
-          v4s A, Bf;
+  const int qi = a.CI / 4, qo = a.CO / 4;
+  const uint16_t* xs = reinterpret_cast<const uint16_t*>(xs2);
+  const uint16_t* gs = reinterpret_cast<const uint16_t*>(gs2);
+  const uint2* __restrict__ xg = reinterpret_cast<const uint2*>(a.x);
+  const uint2* __restrict__ gg = reinterpret_cast<const uint2*>(a.g);
+  v4f acc[3][kMaxCO / 16][kMaxCO / 16];  // taps wave, wave + 4, wave + 8 x input block x output block
+#pragma unroll
+  for (int ti = 0; ti < 3; ++ti)
+#pragma unroll
+    for (int u = 0; u < kMaxCO / 16; ++u)
+#pragma unroll
+      for (int v = 0; v < kMaxCO / 16; ++v) acc[ti][u][v] = v4f{0.f, 0.f, 0.f, 0.f};
+  float bias = 0.f;
+  for (int c_base = 0; c_base < a.w; c_base += kWgChunk) {
+    __syncthreads();  // the previous chunk's reads are done
+    for (int i = threadIdx.x; i < 3 * (kWgChunk + 2) * qi; i += 256) {
+      const int row = i / ((kWgChunk + 2) * qi);
+      const int rem = i - row * (kWgChunk + 2) * qi;
+      const int px = rem / qi, k = rem - px * qi;
+      const int rr = r + row - 1, cx = c_base + px - 1;
+      uint2 v = make_uint2(0u, 0u);
+      if (rr >= 0 && rr < a.h && cx >= 0 && cx < a.w) v = xg[(((size_t)b * a.h + rr) * a.w + cx) * qi + k];
+      xs2[(row * (kWgChunk + 2) + px) * (kWgStride / 4) + k] = v;
+    }
+    for (int i = threadIdx.x; i < kWgChunk * qo; i += 256) {
+      const int px = i / qo, k = i - px * qo;
+      const int c = c_base + px;
+      uint2 v = make_uint2(0u, 0u);
+      if (c < a.w) v = gg[(((size_t)b * a.h + r) * a.w + c) * qo + k];
+      gs2[px * (kWgStride / 4) + k] = v;
+    }
+    __syncthreads();
+    for (int sl = 0; sl < kWgChunk / 16; ++sl) {
+      const int lp = sl * 16;  // first pixel of the slice, relative to c_base
+      if (c_base + lp >= a.w) break;
+#pragma unroll
+      for (int ti = 0; ti < 3; ++ti) {
+        const int t = wave + 4 * ti;
+        if (t >= 9) break;
+        const int ty = t / 3, dx = t % 3 - 1;
+#pragma unroll
+        for (int cib = 0; cib < kMaxCO / 16; ++cib) {
+          if (cib >= nci) break;
+          // A (16 ci x 16 px): lane -> ci = 16 cib + lr, pixels c + 4 lk .. + 3 (zero past the row end)
+          v4s A;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const int c = c0 + lk * 4 + j;
-            const int cx = c + dx;
-            const bool in_g = c < a.w;
-            const bool in_x = in_g && rr >= 0 && rr < a.h && cx >= 0 && cx < a.w;
-            uint16_t xa = 0, gb = 0;
-            if (in_x) xa = a.x[(((size_t)b * a.h + rr) * a.w + cx) * a.CI + cib * 16 + lr];
-            if (in_g) gb = a.g[(((size_t)b * a.h + r) * a.w + c) * a.CO + cob * 16 + lr];
-            A[j] = (short)xa;
-            Bf[j] = (short)gb;
+            const int p = lp + lk * 4 + j;
+            A[j] = (c_base + p < a.w) ? (short)xs[(ty * (kWgChunk + 2) + p + dx + 1) * kWgStride + cib * 16 + lr] : 0;
           }
-          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bf, acc, 0, 0, 0);
-        }
-        // acc[j]: ci = 16 cib + 4 lk + j, co = 16 cob + lr
-        float* P = a.partial + (size_t)br * 9 * a.CI * a.CO;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) P[((size_t)t * a.CI + cib * 16 + lk * 4 + j) * a.CO + cob * 16 + lr] = acc[j];
+          for (int cob = 0; cob < kMaxCO / 16; ++cob) {
+            if (cob >= nco) break;
+            // B (16 px x 16 co): lane -> co = 16 cob + lr, pixels c + 4 lk .. + 3
+            v4s Bf;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Bf[j] = (short)gs[(lp + lk * 4 + j) * kWgStride + cob * 16 + lr];
+            acc[ti][cib][cob] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bf, acc[ti][cib][cob], 0, 0, 0);
+          }
+        }
       }
-  }
-  // bias partial: first wave, one lane per output channel (in pixel order)
-  if (a.partial_bias && wave == 0) {
-    for (int co = lane; co < a.CO; co += 64) {
-      float s = 0.f;
-      for (int c = 0; c < a.w; ++c) s += bf2f(a.g[(((size_t)b * a.h + r) * a.w + c) * a.CO + co]);
-      a.partial_bias[(size_t)br * a.CO + co] = s;
+    }
+    // bias partial: first wave, one lane per output channel, in pixel order
+    if (a.partial_bias && wave == 0 && lane < a.CO) {
+      const int n = min(kWgChunk, a.w - c_base);
+      for (int p = 0; p < n; ++p) bias = bias + bf2f(gs[p * kWgStride + lane]);
     }
   }
+  float* P = a.partial + (size_t)br * 9 * a.CI * a.CO;
+#pragma unroll
+  for (int ti = 0; ti < 3; ++ti) {
+    const int t = wave + 4 * ti;
+    if (t >= 9) break;
+#pragma unroll
+    for (int cib = 0; cib < kMaxCO / 16; ++cib) {
+      if (cib >= nci) break;
+#pragma unroll
+      for (int cob = 0; cob < kMaxCO / 16; ++cob) {
+        if (cob >= nco) break;
+        // acc[j]: ci = 16 cib + 4 lk + j, co = 16 cob + lr
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          P[((size_t)t * a.CI + cib * 16 + lk * 4 + j) * a.CO + cob * 16 + lr] = acc[ti][cib][cob][j];
+      }
+    }
+  }
+  if (a.partial_bias && wave == 0 && lane < a.CO) a.partial_bias[(size_t)br * a.CO + lane] = bias;
 }
 
-// out[i] = sum_{k < n_rows} partial[k * stride + i], in row order
-__global__ void reduce_rows_kernel(const float* __restrict__ partial, int n_rows, int stride, int n, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// out[i] = sum_{k < n_rows} partial[k * stride + i] in a fixed order: a workgroup of 16
+// waves takes 64 outputs, wave g sums rows g, g + 16, g + 32, ... in turn, and the 16
+// sums are added in wave order, so the result does not depend on scheduling
+constexpr int kReduceGroups = 16;
+__global__ __launch_bounds__(kReduceGroups * 64) void reduce_rows_kernel(const float* __restrict__ partial,
+                                                                         int n_rows, int stride, int n,
+                                                                         float* __restrict__ out) {
+  __shared__ float part[kReduceGroups][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int k = 0; k < n_rows; ++k) s += partial[(size_t)k * stride + i];
-  out[i] = s;
+  if (i < n) {
+#pragma unroll 4
+    for (int k = g; k < n_rows; k += kReduceGroups) s += partial[(size_t)k * stride + i];
+  }
+  part[g][lane] = s;
+  __syncthreads();
+  if (g == 0 && i < n) {
+    float t = 0.f;
+    for (int q = 0; q < kReduceGroups; ++q) t += part[q][lane];
+    out[i] = t;
+  }
 }
 
 // fp32 NHWC (C0 channels) -> bf16 NHWC (CP channels, zero padded)
@@ -389,12 +462,14 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t st) {
+  if (a.CI % 16 || a.CO % 16 || a.CI < 16 || a.CO < 16 || a.CI > kMaxCO || a.CO > kMaxCO) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pmn::conv3x3_wgrad_kernel, dim3(a.B * a.h), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_rows(const float* partial, int n_rows, int stride, int n, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(pmn::reduce_rows_kernel, dim3((n + 255) / 256), dim3(256), 0, st, partial, n_rows, stride, n, out);
+  hipLaunchKernelGGL(pmn::reduce_rows_kernel, dim3((n + 63) / 64), dim3(pmn::kReduceGroups * 64), 0, st, partial,
+                     n_rows, stride, n, out);
   return hipGetLastError();
 }
 
