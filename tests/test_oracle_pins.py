@@ -366,6 +366,132 @@ def test_refinement_ranges(small_scene):
     assert np.all(dphi[same_side] <= np.pi / 12 + 1e-5)
 
 
+def _zero_baseline_problem(h, w, f, depth_range, window=5, seed=31):
+    """A reference and one source with the same camera and the same image: every plane
+    that faces the camera scores eps_c (Z = 1 in the one view), so under the strict-
+    improvement rule a pixel whose stored cost is C_max takes the first candidate it is
+    offered, whatever that candidate's plane.  This exposes the candidates themselves."""
+    img = _textured(h, w, seed)
+    K = _K(w, h, f=f)
+    return oracle.Problem([img, img], np.stack([K, K]), np.stack([np.eye(3)] * 2), np.stack([np.zeros(3)] * 2),
+                          depth_range, window, 1, top_k=0, bilateral=True)
+
+
+def _colour_mask(h, w, colour):
+    return (np.add.outer(np.arange(h), np.arange(w)) & 1) == colour
+
+
+def _inner(pb):
+    """Valid pixels whose window stays at least one pixel inside the image: with H = I up
+    to rounding, a window touching the edge exactly can be placed a rounding error outside."""
+    m = pb.valid_mask()
+    return m & np.roll(m, 1, 0) & np.roll(m, -1, 0) & np.roll(m, 1, 1) & np.roll(m, -1, 1)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_propagation_re_expresses_a_slanted_plane(fp64):
+    """Sec. III-C propagation hands a neighbour's plane to the pixel (reading s17: the plane
+    itself, so the depth is where the pixel's own ray meets it).  Every black pixel holds
+    the same strongly slanted plane; after one red propagation half-sweep every red pixel
+    must hold that plane too, its depth being the intersection of its ray with the plane,
+    found here by solving the parametric form X0 + a u1 + b u2 = lam r (not the oracle's
+    formula).  A copied neighbour depth would be off by > 0.5% per pixel of offset."""
+    h, w = 56, 72
+    pb = _zero_baseline_problem(h, w, f=0.9 * w, depth_range=(1.0, 20.0))
+    n = np.array([0.6, -0.6, -1.0])
+    n /= np.linalg.norm(n)
+    X0 = np.array([0.2, -0.1, 6.0])
+    u1 = np.cross(n, [0.0, 0.0, 1.0])
+    u1 /= np.linalg.norm(u1)
+    u2 = np.cross(n, u1)
+    Kinv = np.linalg.inv(pb.K[0].reshape(3, 3))
+    ys, xs = np.mgrid[0:h, 0:w]
+    rays = np.einsum("ij,jhw->hwi", Kinv, np.stack([xs, ys, np.ones_like(xs)]).astype(np.float64))
+    depth = np.empty((h, w))
+    for y in range(h):
+        for x in range(w):
+            lam, _, _ = np.linalg.solve(np.stack([rays[y, x], -u1, -u2], axis=1), X0)
+            depth[y, x] = lam * rays[y, x, 2]
+    assert depth.min() > 2.0 and depth.max() < 19.0
+    # the plane is steep: one pixel step along either axis changes the depth by > 0.5%
+    assert (np.abs(np.diff(depth, axis=1)) / depth[:, 1:]).min() > 0.005
+    assert (np.abs(np.diff(depth, axis=0)) / depth[1:, :]).min() > 0.005
+    P = np.zeros((h, w, 4))
+    C = np.full((h, w), 2.0)
+    black = _colour_mask(h, w, 1)
+    P[..., :3] = n
+    P[..., 3] = np.where(black, depth, 9.0)
+    P[~black, :3] = [0.0, 0.0, -1.0]
+    C[black] = 0.5
+    P2, C2 = oracle.halfsweep(pb, P, C, 1, 0, fp64=fp64, propagate=True, refine=False)
+    red = _inner(pb) & ~black
+    assert red.sum() > 1500
+    assert np.all(C2[red] < 2.0)  # every red pixel took a candidate
+    stored_n = n if fp64 else n.astype(np.float32).astype(np.float64)
+    assert np.array_equal(P2[red][:, :3], np.broadcast_to(stored_n, (red.sum(), 3)))
+    rel = np.abs(P2[..., 3][red] - depth[red]) / depth[red]
+    assert rel.max() <= (1e-12 if fp64 else 1e-5), rel.max()
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_refinement_depth_perturbation_covers_its_range(fp64):
+    """Sec. III-C random refinement: Delta_d is drawn from [-d_max/4, d_max/4] (reading s12:
+    d_max = d_hi).  Each red pixel holds depth 5.5 in the range [1, 10], so d_new always
+    stays in range and the first listed candidate (d_new, n_old) is the one taken; the
+    observed Delta_d must then be uniform on [-2.5, 2.5], reach within 5% of both ends, and
+    leave the normal untouched."""
+    h, w = 96, 80
+    pb = _zero_baseline_problem(h, w, f=0.9 * w, depth_range=(1.0, 10.0))
+    P = np.zeros((h, w, 4))
+    P[..., :3] = [0.1, -0.2, -0.97467943448]
+    P[..., 3] = 5.5
+    C = np.full((h, w), 2.0)
+    P2, C2 = oracle.halfsweep(pb, P, C, 1, 0, fp64=fp64, propagate=False, refine=True)
+    red = _inner(pb) & _colour_mask(h, w, 0)
+    assert red.sum() > 3000
+    assert np.all(C2[red] < 2.0)
+    n0 = P[..., :3][red] if fp64 else P[..., :3][red].astype(np.float32).astype(np.float64)
+    assert np.array_equal(P2[..., :3][red], n0)
+    dd = P2[..., 3][red] - 5.5
+    half = 10.0 / 4
+    assert np.all(np.abs(dd) <= half * (1 + 1e-6))
+    assert dd.min() <= -0.95 * half and dd.max() >= 0.95 * half
+    assert scipy.stats.kstest((dd + half) / (2 * half), "uniform").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_refinement_normal_perturbation_covers_its_ranges(fp64):
+    """Sec. III-C random refinement: the normal's angles are perturbed by Delta_theta in
+    [-pi/2, pi/2] and Delta_phi in [-pi/12, pi/12] (reading s13: on theta = atan2(n_y, n_x),
+    phi = acos(n_z)).  Every red pixel sits at d_hi with a range of width 0.01, so d_new
+    leaves the range on all but ~0.2% of pixels and the candidate (d_old, n_new) is taken;
+    with phi = 3 pi/4 and a narrow field of view (f = 3 W) no perturbed normal needs the
+    camera-facing flip, so the angles of the new normal, less the old ones, are the draws:
+    uniform on their ranges and reaching within 5% of every end."""
+    h, w = 96, 80
+    pb = _zero_baseline_problem(h, w, f=3.0 * w, depth_range=(9.99, 10.0))
+    th0, ph0 = 0.3, 3 * np.pi / 4
+    n0 = np.array([np.cos(th0) * np.sin(ph0), np.sin(th0) * np.sin(ph0), np.cos(ph0)])
+    P = np.zeros((h, w, 4))
+    P[..., :3] = n0
+    P[..., 3] = 10.0
+    C = np.full((h, w), 2.0)
+    P2, C2 = oracle.halfsweep(pb, P, C, 2, 0, fp64=fp64, propagate=False, refine=True)
+    red = _inner(pb) & _colour_mask(h, w, 0)
+    took_n = red & (P2[..., 3] == 10.0)
+    assert took_n.sum() > 0.99 * red.sum() > 3000
+    assert np.all(C2[red] < 2.0)
+    ns = n0 if fp64 else n0.astype(np.float32).astype(np.float64)
+    th_old, ph_old = np.arctan2(ns[1], ns[0]), np.arccos(ns[2])
+    n1 = P2[..., :3][took_n]
+    dth = np.angle(np.exp(1j * (np.arctan2(n1[:, 1], n1[:, 0]) - th_old)))
+    dph = np.arccos(np.clip(n1[:, 2], -1, 1)) - ph_old
+    for d, half in ((dth, np.pi / 2), (dph, np.pi / 12)):
+        assert np.all(np.abs(d) <= half + 1e-5)
+        assert d.min() <= -0.95 * half and d.max() >= 0.95 * half
+        assert scipy.stats.kstest((d + half) / (2 * half), "uniform").pvalue > 1e-3
+
+
 def test_resume_equals_uninterrupted_run(small_scene):
     pb = oracle.Problem.from_scene(small_scene, 7, 1, top_k=1)
     d, n, c = oracle.patchmatch(pb, 2)
