@@ -5,7 +5,14 @@ paper (Sec. III-B, Sec. III-C, Eq. 4, Eq. 5, Algorithm 1 "depth map estimation")
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg may
 import this package; the GPU library never does.
 
-Each function here only marshals arguments; all arithmetic is in ``oracle.cpp``.
+Each function here marshals arguments to ``oracle.cpp``, except ``phi_select``, which
+subsamples the hypothesis maps, calls the exact MAP enumeration of ``oracle.cpp`` and
+brings the decoded depth back to full size in plain Python loops.
+
+``oracle.cpp`` is built twice from the same source: ``liboracle.so`` single-threaded and
+``liboracle_omp.so`` with OpenMP over the pixels of one colour (bitwise the same results,
+since pixels of one colour are independent within a half-sweep).  The functions taking
+``threads`` use the OpenMP build when it is above 1.
 """
 from __future__ import annotations
 
@@ -19,19 +26,27 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 
 CMAX = 2.0
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle with g++ (single-threaded, no fast-math, no fp contraction)."""
+def _compile(path: str, openmp: bool, verbose: bool) -> str:
     cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-mfma",
-           "-fPIC", "-shared", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC]
+           "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas"] + (["-fopenmp"] if openmp else []) + \
+          ["-o", path + ".tmp", _SRC]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
-    return _LIB_PATH
+    os.replace(path + ".tmp", path)
+    return path
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with g++ (no fast-math, no fp contraction): the single-threaded
+    library and the OpenMP build of the same source."""
+    _compile(_OMP_PATH, True, verbose)
+    return _compile(_LIB_PATH, False, verbose)
 
 
 class _Problem(C.Structure):
@@ -58,20 +73,33 @@ class _Problem(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-            build()
-        L = C.CDLL(_LIB_PATH)
+def default_threads() -> int:
+    """The host threads this process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def lib(threads: int = 1):
+    """The single-threaded oracle, or (threads > 1) its OpenMP build set to that many threads."""
+    omp = threads > 1
+    path = _OMP_PATH if omp else _LIB_PATH
+    if path not in _libs:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _compile(path, omp, False)
+        L = C.CDLL(path)
         P = C.POINTER(_Problem)
         dp = C.POINTER(C.c_double)
         fp = C.POINTER(C.c_float)
         ip = C.POINTER(C.c_int32)
         up = C.POINTER(C.c_uint32)
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = C.c_int
         L.oracle_philox4x32_10.argtypes = [up, up, up]
         L.oracle_patchmatch.argtypes = [P, C.c_int, C.c_int, fp, fp, fp]
         L.oracle_init.argtypes = [P, C.c_int, dp, dp]
@@ -96,8 +124,16 @@ def lib():
         for f in ("oracle_patchmatch", "oracle_init", "oracle_halfsweep", "oracle_eval_cost", "oracle_homography",
                   "oracle_consistency", "oracle_phi_normals", "oracle_fuse"):
             getattr(L, f).restype = C.c_int
-        _lib = L
-    return _lib
+        _libs[path] = L
+    L = _libs[path]
+    if omp:
+        L.oracle_set_threads(int(threads))
+    return L
+
+
+def threads_in_effect(threads: int) -> int:
+    """How many threads a call with ``threads`` runs on (1 for the single-threaded build)."""
+    return int(lib(threads).oracle_set_threads(int(threads) if threads > 1 else 0))
 
 
 def _ptr(a, ct):
@@ -165,33 +201,33 @@ def philox4x32_10(ctr, key):
     return o
 
 
-def patchmatch(pb: Problem, iters: int, fp64: bool = False):
+def patchmatch(pb: Problem, iters: int, fp64: bool = False, threads: int = 1):
     """Full run -> (depth (H,W), normal (H,W,3), cost (H,W)) float32."""
     H, W = pb.H, pb.W
     d = np.zeros((H, W), np.float32)
     n = np.zeros((H, W, 3), np.float32)
     c = np.zeros((H, W), np.float32)
-    rc = lib().oracle_patchmatch(C.byref(pb.s), iters, int(fp64), _ptr(d, C.c_float), _ptr(n, C.c_float),
+    rc = lib(threads).oracle_patchmatch(C.byref(pb.s), iters, int(fp64), _ptr(d, C.c_float), _ptr(n, C.c_float),
                                  _ptr(c, C.c_float))
     if rc != 0:
         raise ValueError("oracle_patchmatch failed (singular reference K?)")
     return d, n, c
 
 
-def init(pb: Problem, fp64: bool = False):
+def init(pb: Problem, fp64: bool = False, threads: int = 1):
     planes = np.zeros((pb.H, pb.W, 4), np.float64)
     cost = np.zeros((pb.H, pb.W), np.float64)
-    if lib().oracle_init(C.byref(pb.s), int(fp64), _ptr(planes, C.c_double), _ptr(cost, C.c_double)) != 0:
+    if lib(threads).oracle_init(C.byref(pb.s), int(fp64), _ptr(planes, C.c_double), _ptr(cost, C.c_double)) != 0:
         raise ValueError("oracle_init failed")
     return planes, cost
 
 
 def halfsweep(pb: Problem, planes, cost, iteration: int, colour: int, fp64: bool = False, subset=None,
-              propagate: bool = True, refine: bool = True):
+              propagate: bool = True, refine: bool = True, threads: int = 1):
     P = np.ascontiguousarray(planes, dtype=np.float64).copy()
     Cc = np.ascontiguousarray(cost, dtype=np.float64).copy()
     sub = None if subset is None else np.ascontiguousarray(subset, dtype=np.int32)
-    rc = lib().oracle_halfsweep(C.byref(pb.s), iteration, colour, int(fp64), _ptr(P, C.c_double),
+    rc = lib(threads).oracle_halfsweep(C.byref(pb.s), iteration, colour, int(fp64), _ptr(P, C.c_double),
                                 _ptr(Cc, C.c_double), None if sub is None else _ptr(sub, C.c_int32),
                                 0 if sub is None else len(sub), int(propagate), int(refine))
     if rc != 0:
@@ -199,7 +235,7 @@ def halfsweep(pb: Problem, planes, cost, iteration: int, colour: int, fp64: bool
     return P, Cc
 
 
-def eval_cost(pb: Problem, planes, fp64: bool = False, subset=None):
+def eval_cost(pb: Problem, planes, fp64: bool = False, subset=None, threads: int = 1):
     """Cost of the given planes -> (cost (H,W), per_view (H,W,n_src), valid (H,W,n_src))."""
     P = np.ascontiguousarray(planes, dtype=np.float64)
     H, W, n = pb.H, pb.W, pb.n_src
@@ -207,7 +243,7 @@ def eval_cost(pb: Problem, planes, fp64: bool = False, subset=None):
     pv = np.full((H, W, n), CMAX, np.float64)
     ok = np.zeros((H, W, n), np.int32)
     sub = None if subset is None else np.ascontiguousarray(subset, dtype=np.int32)
-    rc = lib().oracle_eval_cost(C.byref(pb.s), int(fp64), _ptr(P, C.c_double), _ptr(cost, C.c_double),
+    rc = lib(threads).oracle_eval_cost(C.byref(pb.s), int(fp64), _ptr(P, C.c_double), _ptr(cost, C.c_double),
                                 _ptr(pv, C.c_double), _ptr(ok, C.c_int32),
                                 None if sub is None else _ptr(sub, C.c_int32), 0 if sub is None else len(sub))
     if rc != 0:

@@ -49,6 +49,13 @@
 //    = (pixel index y*W + x, iteration, phase, 0); uniforms (x >> 8) * 2^-24.
 //  * Pixels whose reference window leaves the image are invalid: never updated,
 //    output depth 0, normal 0, cost C_max.
+//
+// Threads.  The same source is also built with OpenMP (liboracle_omp.so): the loops over
+// the pixels of one colour within a half-sweep (and over the pixels of an initialisation
+// or a cost evaluation) are then shared among threads.  Within a half-sweep a pixel reads
+// only the other colour's state and its own, the random numbers are keyed by pixel, and
+// each pixel's arithmetic is unchanged, so the results are bitwise those of one thread.
+// Without OpenMP the pragmas are ignored and the build is the single-threaded one.
 
 #include <cmath>
 #include <cstdint>
@@ -56,6 +63,9 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -533,6 +543,7 @@ template <typename T>
 int run_init(const oracle_problem* pb, double* planes, double* costs) {
   Solver<T> S;
   if (!S.setup(pb)) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
   for (int y = 0; y < S.H; ++y)
     for (int x = 0; x < S.W; ++x) {
       size_t p = (size_t)y * S.W + x;
@@ -566,8 +577,10 @@ int run_halfsweep(const oracle_problem* pb, int iteration, int colour, double* p
     Cn[p] = c;
   };
   if (subset) {
+#pragma omp parallel for schedule(dynamic, 16)
     for (int i = 0; i < n_subset; ++i) visit(subset[i] % S.W, subset[i] / S.W);
   } else {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int y = 0; y < S.H; ++y)
       for (int x = 0; x < S.W; ++x) visit(x, y);
   }
@@ -581,12 +594,14 @@ int run_patchmatch(const oracle_problem* pb, int iters, float* depth, float* nor
   if (!S.setup(pb)) return -1;
   const size_t n = (size_t)S.W * S.H;
   std::vector<T> P(4 * n, T(0)), C(n, (T)Solver<T>::kCmax);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int y = 0; y < S.H; ++y)
     for (int x = 0; x < S.W; ++x)
       if (S.pixel_valid(x, y)) S.init_pixel(x, y, &P[4 * ((size_t)y * S.W + x)], &C[(size_t)y * S.W + x]);
   for (int it = 1; it <= iters; ++it)
     for (int colour = 0; colour < 2; ++colour) {
       // the other colour is read-only during this half-sweep, so in-place updates are exact
+#pragma omp parallel for schedule(dynamic, 1)
       for (int y = 0; y < S.H; ++y)
         for (int x = 0; x < S.W; ++x) {
           if (((x + y) & 1) != colour || !S.pixel_valid(x, y)) continue;
@@ -613,13 +628,11 @@ int run_eval(const oracle_problem* pb, const double* planes, double* cost_out, d
              int32_t* valid, const int32_t* subset, int n_subset) {
   Solver<T> S;
   if (!S.setup(pb)) return -1;
-  std::vector<T> pv(S.n_src);
-  std::vector<int32_t> ok(S.n_src);
   auto visit = [&](size_t p) {
     int x = (int)(p % S.W), y = (int)(p / S.W);
     T c = (T)Solver<T>::kCmax;
-    std::fill(pv.begin(), pv.end(), (T)Solver<T>::kCmax);
-    std::fill(ok.begin(), ok.end(), 0);
+    std::vector<T> pv(S.n_src, (T)Solver<T>::kCmax);
+    std::vector<int32_t> ok(S.n_src, 0);
     if (S.pixel_valid(x, y)) {
       const double* pl = planes + 4 * p;
       V3<T> n{(T)pl[0], (T)pl[1], (T)pl[2]};
@@ -632,9 +645,11 @@ int run_eval(const oracle_problem* pb, const double* planes, double* cost_out, d
       for (int j = 0; j < S.n_src; ++j) valid[p * S.n_src + j] = ok[j];
   };
   if (subset) {
+#pragma omp parallel for schedule(dynamic, 16)
     for (int i = 0; i < n_subset; ++i) visit((size_t)subset[i]);
   } else {
-    for (size_t p = 0; p < (size_t)S.W * S.H; ++p) visit(p);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (long long p = 0; p < (long long)S.W * S.H; ++p) visit((size_t)p);
   }
   return 0;
 }
@@ -773,6 +788,18 @@ double phi_pairwise(double h1, double h2, double k3) {
 extern "C" {
 
 // Philox4x32-10 block: counter ctr[4], key key[2] -> out[4]
+// Threads used by the pixel loops of the OpenMP build (returns the count in effect); the
+// single-threaded build ignores the request and returns 1.
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 void oracle_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
   philox4x32_10(ctr, key, out);
 }
