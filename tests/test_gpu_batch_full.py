@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 import scenegen as sg
+from fp64_error import report as fp64_report
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +20,8 @@ if not torch.cuda.is_available():
 
 import paper_2104_06165_amd as pm  # noqa: E402
 
-SAMPLES_PER_JOB = 60
+SAMPLES_PER_JOB = 250
+THREADS = oracle.default_threads()
 
 
 def say(*a):
@@ -45,6 +47,7 @@ def test_full_batched_workload_sampled():
         say(f"batch of {len(jobs)} done")
         rng = np.random.default_rng(7)
         n_ok = n_all = 0
+        g_all, o64_all = [], []
         for i, j in enumerate(jobs):
             d = j["depth"].cpu().numpy()
             nm = j["normal"].cpu().numpy()
@@ -64,15 +67,20 @@ def test_full_batched_workload_sampled():
             idx = np.flatnonzero(m.ravel())
             sub = rng.choice(idx, size=SAMPLES_PER_JOB, replace=False).astype(np.int32)
             planes = np.concatenate([nm, d[..., None]], -1).astype(np.float64)
-            oc, _, _ = oracle.eval_cost(pb, planes, subset=sub)
+            oc, _, _ = oracle.eval_cost(pb, planes, subset=sub, threads=THREADS)
+            o64, _, _ = oracle.eval_cost(pb, planes, fp64=True, subset=sub, threads=THREADS)
             g = c.ravel()[sub]
             o = oc.ravel()[sub]
             ok = np.abs(g - o) <= 1e-4
             n_ok += int(ok.sum())
             n_all += len(sub)
+            g_all.append(g)
+            o64_all.append(o64.ravel()[sub])
             say(f"job {i} ({d.shape[1]}x{d.shape[0]}, {len(j['srcs'])} sources, s={j['dilation']}): "
                 f"{ok.mean():.4f} of {len(sub)} sampled costs within 1e-4, bitwise {(g == o.astype(np.float32)).mean():.4f}")
         say(f"all jobs: {n_ok} of {n_all} sampled costs within 1e-4")
-        assert n_ok >= n_all - 2  # 1440 samples: two disagreements allowed (ulp-level transcendental differences)
+        fp64_report("all jobs: teacher-forced cost at the sampled pixels", np.concatenate(g_all),
+                    np.concatenate(o64_all))
+        assert n_ok >= 0.999 * n_all
     finally:
         ctx.close()
