@@ -11,7 +11,10 @@
  *
  * Conventions
  *   - Images are row-major, pixel (x, y) at column x, row y; pixel centres sit at
- *     integer coordinates.  8-bit grey values (PHIMVS_U8) are the supported input.
+ *     integer coordinates.  8-bit grey values (PHIMVS_U8) are the supported input:
+ *     every workload here is 8-bit imagery, whose values FP16 and FP32 hold exactly,
+ *     so FP16 or FP32 input would add no precision; other dtypes fail with
+ *     PHIMVS_E_UNSUPPORTED.
  *   - Cameras map world to camera: X_cam = R X_world + t.  K is 3x3 with last row
  *     (0, 0, 1).  All camera matrices are row-major doubles.
  *   - Depth is the reference camera's Z.  Normals are in the reference camera frame,
@@ -93,7 +96,10 @@ typedef struct {
 void phimvs_default_params(phimvs_params* p);
 
 /* Create a context on HIP device `device_ordinal`, issuing work on `hip_stream`
- * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+ * (a hipStream_t; NULL = the null stream).  *out receives the context.  Creation also
+ * raises the evaluate kernel's dynamic-LDS limit on that device (so that no launch
+ * changes a kernel attribute, which a stream capture could not record); it fails with
+ * PHIMVS_E_DEVICE when the device does not report its LDS size. */
 int phimvs_create(phimvs_ctx** out, int device_ordinal, void* hip_stream);
 void phimvs_destroy(phimvs_ctx* ctx);
 const char* phimvs_last_error(const phimvs_ctx* ctx);
@@ -187,7 +193,9 @@ int phimvs_set_tuning(phimvs_ctx* ctx, const phimvs_tuning* t);
 int phimvs_get_tuning(phimvs_ctx* ctx, phimvs_tuning* t);
 /* Time every built-in configuration on the given batch (graph replays, `iters`
  * iterations), keep the fastest in the context and report all of them in results
- * (capacity *n_results, updated to the number written). */
+ * (capacity *n_results, updated to the number written).  A configuration that fails to
+ * run is reported with ms = +inf and passed over (phimvs_last_error then names it); when
+ * none runs, the previous configuration is restored and PHIMVS_E_DEVICE returned. */
 int phimvs_autotune(phimvs_ctx* ctx, int n_jobs, const phimvs_job* jobs, int iters, phimvs_tuning* results,
                     int* n_results);
 

@@ -74,6 +74,7 @@ struct phimvs_ctx {
   Batch single;                   // the step-wise interface's job
   Batch multi;                    // phimvs_patchmatch_batch
   phimvs_tuning tuning{4, 0, 0, 0.0};
+  size_t eval_lds_max = 0;                // largest dynamic LDS of an evaluate launch on this device
   DevBuf<float> io_a, io_b, io_c, io_d;  // staging for host inputs / outputs
   DevBuf<FilterNbr> filter_nbrs;          // neighbour table of the consistency filter
   std::vector<FilterNbr> filter_host;
@@ -419,24 +420,31 @@ int eval_grid(const phimvs_ctx* c, const Batch& b, bool persistent) {
 
 // one evaluate-and-select launch (queue: 8 zeroed counters when persistent), with the
 // optional diagnostics around it
-hipError_t run_eval(phimvs_ctx* c, Batch& b, Launch L, unsigned int* queue) {
+int run_eval(phimvs_ctx* c, Batch& b, Launch L, unsigned int* queue) {
   const bool persistent = c->tuning.persistent != 0;
   L.persistent = persistent ? 1 : 0;
   L.queue = queue;
   if (c->diag & PHIMVS_DIAG_COUNT) L.count = c->diag_count;
   const size_t lds = eval_lds_bytes(b.tile_rows, b.max_r, b.max_taps);
+  if (lds > c->eval_lds_max)
+    return fail(c, PHIMVS_E_UNSUPPORTED, "evaluate launch: " + std::to_string(b.tile_rows) + "-row tiles need " +
+                                              std::to_string(lds) + " bytes of LDS, the device allows " +
+                                              std::to_string(c->eval_lds_max));
   const int grid = eval_grid(c, b, persistent);
-  hipError_t e;
-  if (c->diag & PHIMVS_DIAG_TIME) {
+  const bool timed = (c->diag & PHIMVS_DIAG_TIME) != 0;
+  if (timed) {
     hipEvent_t e0, e1;
-    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
-    if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+    HIPCHECK(c, hipEventCreate(&e0));
+    HIPCHECK(c, hipEventCreate(&e1));
     c->diag_events.emplace_back(e0, e1);
-    if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) return e;
-    if ((e = launch_eval(b.d_jobs, L, grid, lds, c->stream)) != hipSuccess) return e;
-    return hipEventRecord(e1, c->stream);
+    HIPCHECK(c, hipEventRecord(e0, c->stream));
   }
-  return launch_eval(b.d_jobs, L, grid, lds, c->stream);
+  const hipError_t e = launch_eval(b.d_jobs, L, grid, lds, c->stream);
+  if (e != hipSuccess)
+    return fail(c, PHIMVS_E_DEVICE, "evaluate launch (" + std::to_string(grid) + " workgroups, " +
+                                        std::to_string(lds) + " bytes of dynamic LDS): " + hipGetErrorString(e));
+  if (timed) HIPCHECK(c, hipEventRecord(c->diag_events.back().second, c->stream));
+  return PHIMVS_OK;
 }
 
 // the launch sequence of init + iters x (red, black) x (propagate, refine) (+ unpack);
@@ -448,14 +456,14 @@ int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack, bool with
   const int n_eval = 2 + 4 * iters;
   if (b.queues.n < (size_t)8 * n_eval) return fail(c, PHIMVS_E_STATE, "queue counters not allocated");
   HIPCHECK(c, launch_zero(b.queues.p, 8 * n_eval, c->stream));
-  int q = 0;
+  int q = 0, rc;
   Launch L = base_launch(b);
   for (int colour = 0; colour < 2; ++colour) {
     L.colour = colour;
     L.mode = 0;
     L.ncand = with_proposal ? 2 : 1;
     HIPCHECK(c, launch_candidates(0, b.d_jobs, L, c->stream));
-    HIPCHECK(c, run_eval(c, b, L, b.queues.p + 8 * q++));
+    if ((rc = run_eval(c, b, L, b.queues.p + 8 * q++))) return rc;
   }
   for (int it = 1; it <= iters; ++it)
     for (int colour = 0; colour < 2; ++colour) {
@@ -464,10 +472,10 @@ int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack, bool with
       L.mode = 1;
       L.ncand = 8;
       HIPCHECK(c, launch_candidates(1, b.d_jobs, L, c->stream));
-      HIPCHECK(c, run_eval(c, b, L, b.queues.p + 8 * q++));
+      if ((rc = run_eval(c, b, L, b.queues.p + 8 * q++))) return rc;
       L.ncand = 3;
       HIPCHECK(c, launch_candidates(2, b.d_jobs, L, c->stream));
-      HIPCHECK(c, run_eval(c, b, L, b.queues.p + 8 * q++));
+      if ((rc = run_eval(c, b, L, b.queues.p + 8 * q++))) return rc;
     }
   if (do_unpack) HIPCHECK(c, launch_unpack(b.d_jobs, base_launch(b), c->stream));
   return PHIMVS_OK;
@@ -497,7 +505,7 @@ int eval_once(phimvs_ctx* c, Batch& b, Launch L) {
   int rc = ensure(c, b.queues, 8);
   if (rc) return rc;
   HIPCHECK(c, launch_zero(b.queues.p, 8, c->stream));
-  HIPCHECK(c, run_eval(c, b, L, b.queues.p));
+  if ((rc = run_eval(c, b, L, b.queues.p))) return rc;
   return PHIMVS_OK;
 }
 
@@ -611,6 +619,10 @@ int phimvs_create(phimvs_ctx** out, int device_ordinal, void* hip_stream) {
   if (!c) return PHIMVS_E_OOM;
   c->device = device_ordinal;
   c->stream = (hipStream_t)hip_stream;
+  if (eval_lds_setup(&c->eval_lds_max) != hipSuccess) {
+    delete c;
+    return PHIMVS_E_DEVICE;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device_ordinal) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
@@ -1253,34 +1265,55 @@ int phimvs_autotune(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, int iters
   const phimvs_tuning cands[] = {{4, 0, 0, 0}, {2, 0, 0, 0}, {1, 0, 0, 0}, {4, 1, 2, 0}, {4, 1, 3, 0},
                                  {4, 1, 4, 0}, {4, 1, 6, 0}, {2, 1, 3, 0}, {2, 1, 4, 0}, {1, 1, 4, 0}};
   const int n = (int)(sizeof(cands) / sizeof(cands[0]));
+  const phimvs_tuning prev = c->tuning;
   phimvs_tuning best{};
-  double best_ms = 1e300;
-  int rc;
-  hipEvent_t e0, e1;
-  HIPCHECK(c, hipEventCreate(&e0));
-  HIPCHECK(c, hipEventCreate(&e1));
-  for (int i = 0; i < n; ++i) {
-    if ((rc = phimvs_set_tuning(c, &cands[i]))) return rc;
-    if ((rc = phimvs_patchmatch_batch(c, n_jobs, jobs, iters, 1))) return rc;  // capture + warm
-    HIPCHECK(c, hipEventRecord(e0, c->stream));
-    if ((rc = phimvs_patchmatch_batch(c, n_jobs, jobs, iters, 1))) return rc;
-    HIPCHECK(c, hipEventRecord(e1, c->stream));
-    HIPCHECK(c, hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
-    phimvs_tuning r = cands[i];
-    r.ms = ms;
-    if (results && n_results && i < *n_results) results[i] = r;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = r;
-    }
+  double best_ms = HUGE_VAL;
+  std::string failures;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto destroy = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    destroy();
+    return fail(c, PHIMVS_E_DEVICE, "autotune: hipEventCreate failed");
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  // a configuration that fails (its launch refused, say) is reported with ms = +inf and
+  // passed over; the others are still timed
+  for (int i = 0; i < n; ++i) {
+    phimvs_tuning r = cands[i];
+    r.ms = HUGE_VAL;
+    int rc = phimvs_set_tuning(c, &cands[i]);
+    if (!rc) rc = phimvs_patchmatch_batch(c, n_jobs, jobs, iters, 1);  // capture + warm
+    if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(c, PHIMVS_E_DEVICE, "hipEventRecord");
+    if (!rc) rc = phimvs_patchmatch_batch(c, n_jobs, jobs, iters, 1);
+    if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = fail(c, PHIMVS_E_DEVICE, "hipEventRecord");
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(c, PHIMVS_E_DEVICE, "hipEventSynchronize");
+    float ms = 0.f;
+    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(c, PHIMVS_E_DEVICE, "hipEventElapsedTime");
+    if (rc) {
+      failures += " [rows " + std::to_string(cands[i].tile_rows) + ", persistent " +
+                  std::to_string(cands[i].persistent) + ", " + std::to_string(cands[i].wgs_per_cu) + "/CU: " + c->err +
+                  "]";
+    } else {
+      r.ms = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = r;
+      }
+    }
+    if (results && n_results && i < *n_results) results[i] = r;
+  }
+  destroy();
   if (n_results) *n_results = std::min(*n_results, n);
-  if ((rc = phimvs_set_tuning(c, &best))) return rc;
+  if (!(best_ms < HUGE_VAL)) {
+    (void)phimvs_set_tuning(c, &prev);
+    return fail(c, PHIMVS_E_DEVICE, "autotune: no configuration ran:" + failures);
+  }
+  int rc = phimvs_set_tuning(c, &best);
+  if (rc) return rc;
   c->tuning.ms = best_ms;
+  c->err = failures.empty() ? std::string() : "autotune: configurations passed over:" + failures;
   return PHIMVS_OK;
 }
 

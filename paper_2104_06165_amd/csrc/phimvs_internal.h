@@ -81,6 +81,9 @@ struct Launch {
 // launch-wide LDS need in bytes for the evaluate kernel
 size_t eval_lds_bytes(int tile_rows, int max_radius_px, int max_taps);
 
+// raise the evaluate kernel's dynamic-LDS limit on the current device (outside any stream
+// capture); *max_dynamic receives the largest dynamic LDS a launch may then ask for
+hipError_t eval_lds_setup(size_t* max_dynamic);
 hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds, hipStream_t st);
 // kind 0: random initialisation (+ proposal), 1: propagation, 2: refinement candidates
 hipError_t launch_candidates(int kind, const Job* d_jobs, const Launch& L, hipStream_t st);

@@ -973,30 +973,40 @@ size_t eval_lds_bytes(int tile_rows, int max_radius_px, int max_taps) {
   return sizeof(float) * ((size_t)max_taps + tw * th);  // the colour-weight table is static
 }
 
-hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds, hipStream_t st) {
-  // tiles above 64 KiB of LDS (one-row tiles with wide windows) need the opt-in limit,
-  // set once per device and kernel instance
-  constexpr int kMaxDevices = 64;
-  static bool raised[kMaxDevices][2] = {};
-  if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
-  if (lds > 65536) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    bool& done = raised[dev][L.frac ? 1 : 0];
-    if (!done) {
-      const void* fn = L.frac ? (const void*)pmk::eval_kernel<true> : (const void*)pmk::eval_kernel<false>;
-      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
-      if (e != hipSuccess) return e;
-      done = true;
-    }
+hipError_t eval_lds_setup(size_t* max_dynamic) {
+  // Tiles above 64 KiB of LDS (one-row tiles with wide windows) need the opt-in limit.  It
+  // is raised here, once per device and context, for both kernel instances, to what a
+  // workgroup may hold beside the instance's static LDS (the colour-weight table and the
+  // queue slot): never in the middle of a stream capture, where the launches are recorded.
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  int optin = 0, per_cu = 0;
+  if ((e = hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev)) != hipSuccess)
+    return e;
+  const size_t per_wg = std::min<size_t>((size_t)std::max(optin, per_cu), 160 * 1024);
+  size_t lim = per_wg;
+  const void* fns[2] = {(const void*)pmk::eval_kernel<false>, (const void*)pmk::eval_kernel<true>};
+  for (const void* fn : fns) {
+    hipFuncAttributes a{};
+    if ((e = hipFuncGetAttributes(&a, fn)) != hipSuccess) return e;
+    if (a.sharedSizeBytes >= per_wg) return hipErrorInvalidValue;
+    const size_t dyn = per_wg - a.sharedSizeBytes;
+    if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn)) != hipSuccess) return e;
+    lim = std::min(lim, dyn);
   }
-  if (L.frac)
-    hipLaunchKernelGGL(pmk::eval_kernel<true>, dim3(grid), dim3(kBlock), lds, st, d_jobs, L);
-  else
-    hipLaunchKernelGGL(pmk::eval_kernel<false>, dim3(grid), dim3(kBlock), lds, st, d_jobs, L);
-  return hipGetLastError();
+  *max_dynamic = lim;
+  return hipSuccess;
+}
+
+hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds, hipStream_t st) {
+  // hipLaunchKernel returns this launch's own status (hipGetLastError would also report an
+  // earlier call's error on this thread)
+  Launch l = L;
+  void* args[] = {(void*)&d_jobs, (void*)&l};
+  const void* fn = L.frac ? (const void*)pmk::eval_kernel<true> : (const void*)pmk::eval_kernel<false>;
+  return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, lds, st);
 }
 
 hipError_t launch_candidates(int kind, const Job* d_jobs, const Launch& L, hipStream_t st) {
