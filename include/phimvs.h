@@ -280,6 +280,16 @@ int phimvs_fuse(phimvs_ctx* ctx, int n_maps, const phimvs_depth_map* maps, const
  * FP64 fit.  Work is queued on the context's stream; the library keeps scratch of one bit
  * per pixel and direction ((4 W + 2 H) H / 8 bytes, rounded up to 64-bit words). */
 int phimvs_phi_hypotheses(phimvs_ctx* ctx, int width, int height, const float* depth, float* hyp);
+/* The same hypotheses, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): this call makes
+ * no allocation.  Its bitmaps live in a static device array of 2^20 64-bit words (8 MiB)
+ * that every GPU the library runs on holds until the process ends; maps needing more
+ * ((4 W + 2 H) H / 8 bytes, rounded up to words; e.g. 3200 x 2130 needs 4.5 MiB) fail with
+ * PHIMVS_E_UNSUPPORTED.  All calls on one GPU share that GPU's array: calls that overlap
+ * on one GPU (contexts on different streams, or host threads) race and must be ordered by
+ * the caller.  Arguments, outputs and errors as phimvs_phi_hypotheses; the results are
+ * identical to it. */
+int phimvs_phi_hypotheses_noalloc(phimvs_ctx* ctx, int width, int height, const float* depth, float* hyp);
 
 /* Matching cost (Eq. 5, the prepared problem's cost) of every hypothesis: the fronto-
  * parallel plane at the hypothesis depth, i.e. every window point back-projected at that

@@ -31,8 +31,8 @@ EXPORTS = ("phimvs_default_params", "phimvs_create", "phimvs_destroy", "phimvs_l
            "phimvs_patchmatch_batch", "phimvs_set_tuning", "phimvs_get_tuning", "phimvs_autotune",
            "phimvs_diag_enable", "phimvs_diag_read", "phimvs_check_reciprocal",
            "phimvs_default_filter_params", "phimvs_filter", "phimvs_default_fuse_params", "phimvs_fuse",
-           "phimvs_phi_hypotheses", "phimvs_phi_costs", "phimvs_default_phi_params", "phimvs_phi_select",
-           "phimvs_phi_decode_host", "phimvs_phi_normals",
+           "phimvs_phi_hypotheses", "phimvs_phi_hypotheses_noalloc", "phimvs_phi_costs", "phimvs_default_phi_params",
+           "phimvs_phi_select", "phimvs_phi_decode_host", "phimvs_phi_normals",
            # learned initial-plane proposal (include/phimvs_net.h)
            "phimvs_net_create", "phimvs_net_destroy", "phimvs_net_last_error", "phimvs_net_set_stream",
            "phimvs_net_param_count", "phimvs_net_set_params", "phimvs_net_get_params", "phimvs_net_forward",
@@ -178,6 +178,7 @@ def lib():
         L.phimvs_default_fuse_params.restype = None
         L.phimvs_fuse.argtypes = [vp, ip, C.POINTER(_DepthMap), C.POINTER(_FuseParams), fp, fp, fp]
         L.phimvs_phi_hypotheses.argtypes = [vp, ip, ip, fp, fp]
+        L.phimvs_phi_hypotheses_noalloc.argtypes = [vp, ip, ip, fp, fp]
         L.phimvs_phi_costs.argtypes = [vp, fp, fp]
         L.phimvs_default_phi_params.argtypes = [C.POINTER(_PhiParams)]
         L.phimvs_default_phi_params.restype = None
@@ -391,6 +392,16 @@ class Context:
         hyp = torch.empty((4, H, W), dtype=torch.float32, device=self.device)
         self._check(lib().phimvs_phi_hypotheses(self.h, W, H, d.data_ptr(), hyp.data_ptr()))
         return hyp
+
+    def phi_hypotheses_noalloc(self, depth, out):
+        """The same hypotheses into the caller's (4, H, W) float32 tensor ``out``, through the
+        entry point that allocates nothing (its scratch is a fixed device array)."""
+        self._sync_stream()
+        d = depth.contiguous()
+        H, W = d.shape
+        assert out.shape == (4, H, W) and out.dtype == self.torch.float32 and out.is_contiguous()
+        self._check(lib().phimvs_phi_hypotheses_noalloc(self.h, W, H, d.data_ptr(), out.data_ptr()))
+        return out
 
     def phi_costs(self, hyp):
         """Matching cost (4, H, W) of the hypotheses under the prepared problem."""

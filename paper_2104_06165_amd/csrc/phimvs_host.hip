@@ -623,6 +623,9 @@ int phimvs_create(phimvs_ctx** out, int device_ordinal, void* hip_stream) {
     delete c;
     return PHIMVS_E_DEVICE;
   }
+  // the allocation-free entry point's scratch address on this device (looked up once per
+  // device; a failure is kept and reported by that entry point alone)
+  (void)phi_scratch_setup(device_ordinal);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device_ordinal) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = prop.multiProcessorCount;
@@ -1071,6 +1074,24 @@ int phimvs_phi_hypotheses(phimvs_ctx* c, int width, int height, const float* dep
   int rc = ensure(c, c->phi_bits, phi_bits_words(width, height));
   if (rc) return rc;
   HIPCHECK(c, launch_phi_hypotheses(depth, width, height, c->phi_bits.p, hyp, c->stream));
+  return PHIMVS_OK;
+}
+
+int phimvs_phi_hypotheses_noalloc(phimvs_ctx* c, int width, int height, const float* depth, float* hyp) {
+  if (!c) return PHIMVS_E_ARG;
+  if (width < 1 || height < 1 || !depth || !hyp) return fail(c, PHIMVS_E_ARG, "invalid size or null array");
+  const size_t need = phi_bits_words(width, height);
+  if (need > kPhiScratchWords)
+    return fail(c, PHIMVS_E_UNSUPPORTED, "a " + std::to_string(width) + "x" + std::to_string(height) +
+                                             " map needs " + std::to_string(need) + " words of scratch; " +
+                                             "the allocation-free entry point has " +
+                                             std::to_string(kPhiScratchWords));
+  uint64_t* bits = nullptr;
+  const hipError_t e = phi_scratch_get(c->device, &bits);
+  if (e != hipSuccess)
+    return fail(c, PHIMVS_E_DEVICE, std::string("scratch of the allocation-free entry point: ") + hipGetErrorString(e));
+  HIPCHECK(c, hipSetDevice(c->device));
+  HIPCHECK(c, launch_phi_hypotheses(depth, width, height, bits, hyp, c->stream));
   return PHIMVS_OK;
 }
 

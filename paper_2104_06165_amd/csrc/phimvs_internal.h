@@ -136,6 +136,12 @@ struct PhiCam {
 };
 // 64-bit words of the per-direction occupancy bitmaps of a W x H map (the fit's scratch)
 size_t phi_bits_words(int W, int H);
+// the allocation-free entry point's scratch: a static device array of kPhiScratchWords
+// words per GPU; phi_scratch_setup looks up its device address on `device` (which must be
+// current) once per device, phi_scratch_get returns it (no HIP call, no allocation)
+constexpr size_t kPhiScratchWords = (size_t)1 << 20;
+hipError_t phi_scratch_setup(int device);
+hipError_t phi_scratch_get(int device, uint64_t** p);
 hipError_t launch_phi_hypotheses(const float* depth, int W, int H, uint64_t* bits, float* hyp, hipStream_t st);
 hipError_t launch_phi_planes(const float* hyp, size_t n, float* planes, hipStream_t st);
 hipError_t launch_phi_mask_cost(const float* hyp, size_t n, float cmax, float* cost, hipStream_t st);

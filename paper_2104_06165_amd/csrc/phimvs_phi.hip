@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include <climits>
+#include <mutex>
 
 #include "phimvs_internal.h"
 
@@ -240,7 +241,46 @@ __global__ void phi_normals_kernel(const float* __restrict__ depth, int W, int H
 
 }  // namespace pmp
 
+// Scratch of the allocation-free hypothesis entry point: one call's occupancy bitmaps, at
+// most kPhiScratchWords 64-bit words (8 MiB), one copy on every GPU the library runs on,
+// held until the process ends.  Host code never passes `scratch` itself to a kernel (its
+// host-side name is not a device address): it passes the device address that
+// phi_scratch_setup looked up on each device.  Every call on one GPU shares that GPU's
+// copy; every word of the layout is rewritten by each call, so nothing needs clearing.
+static __device__ __align__(256) uint64_t scratch[phimvs_internal::kPhiScratchWords];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+bool g_scratch_done[kMaxScratchDevices] = {};
+hipError_t g_scratch_err[kMaxScratchDevices] = {};
+uint64_t* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
 namespace phimvs_internal {
+
+hipError_t phi_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_done[device]) {
+    // the caller has made `device` current
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? static_cast<uint64_t*>(p) : nullptr;
+    g_scratch_done[device] = true;
+  }
+  return g_scratch_err[device];
+}
+
+hipError_t phi_scratch_get(int device, uint64_t** p) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_done[device]) return hipErrorNotInitialized;
+  if (g_scratch_err[device] != hipSuccess) return g_scratch_err[device];
+  *p = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 size_t phi_bits_words(int W, int H) {
   const pmp::PhiBits B = pmp::phi_bits_layout(nullptr, W, H);
