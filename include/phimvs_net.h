@@ -80,6 +80,16 @@ int phimvs_net_loss_grad(phimvs_net* net, int batch, int height, int width, cons
                          const float* target, const float* mask, const float* depth_range,
                          float normal_weight, double* loss, float* grad);
 
+/* Test and inspection hook: copy a tensor the last pass stored on the device, bfloat16
+ * widened to float32, padding channels dropped, into `out` (device, batch*h*w*C NHWC).
+ * kind 0: the activation entering layer `layer` (0 .. PHIMVS_NET_LAYERS-1; layer 0's is
+ * the bfloat16 input, C = PHIMVS_NET_IN, else C = 32), after phimvs_net_forward or
+ * phimvs_net_loss_grad; kind 1: the gradient of the loss at the output of layer `layer`
+ * (C = 32, or PHIMVS_NET_OUT for the last layer, whose gradient is the loss's own), after
+ * phimvs_net_loss_grad.  PHIMVS_E_STATE before such a pass, PHIMVS_E_ARG for another kind
+ * or layer. */
+int phimvs_net_tensor(phimvs_net* net, int kind, int layer, float* out);
+
 /* One Adam step (Kingma & Ba) with the gradient of the last phimvs_net_loss_grad. */
 int phimvs_net_adam(phimvs_net* net, float lr, float beta1, float beta2, float eps);
 

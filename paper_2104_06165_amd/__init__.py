@@ -37,7 +37,7 @@ EXPORTS = ("phimvs_default_params", "phimvs_create", "phimvs_destroy", "phimvs_l
            "phimvs_net_create", "phimvs_net_destroy", "phimvs_net_last_error", "phimvs_net_set_stream",
            "phimvs_net_param_count", "phimvs_net_set_params", "phimvs_net_get_params", "phimvs_net_forward",
            "phimvs_net_loss_grad", "phimvs_net_adam", "phimvs_net_inputs", "phimvs_net_propose",
-           "phimvs_net_decode", "phimvs_net_targets", "phimvs_patchmatch_proposal")
+           "phimvs_net_decode", "phimvs_net_targets", "phimvs_net_tensor", "phimvs_patchmatch_proposal")
 DIAG_COUNT = 1
 DIAG_TIME = 2
 
@@ -198,6 +198,7 @@ def lib():
         L.phimvs_net_forward.argtypes = [vp, ip, ip, ip, fp, fp]
         L.phimvs_net_loss_grad.argtypes = [vp, ip, ip, ip, fp, fp, fp, fp, C.c_float, dp, fp]
         L.phimvs_net_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
+        L.phimvs_net_tensor.argtypes = [vp, ip, ip, fp]
         L.phimvs_net_inputs.argtypes = [vp, vp, ip, C.POINTER(C.c_int), ip, fp]
         L.phimvs_net_propose.argtypes = [vp, vp, ip, C.POINTER(C.c_int), ip, fp]
         L.phimvs_net_decode.argtypes = [vp, vp, ip, fp, fp]
@@ -672,6 +673,7 @@ class Net:
         B, h, w, _ = xb.shape
         out = torch.empty((B, h, w, self.OUT), dtype=torch.float32, device=self.device)
         self._check(lib().phimvs_net_forward(self.h, B, h, w, xb.data_ptr(), out.data_ptr()))
+        self._last_shape = (B, h, w)
         return out if x.dim() == 4 else out[0]
 
     def loss_grad(self, x, target, mask, depth_range, normal_weight: float = 1.0, want_loss: bool = True,
@@ -688,7 +690,21 @@ class Net:
         self._check(lib().phimvs_net_loss_grad(self.h, B, h, w, x.data_ptr(), target.data_ptr(), mask.data_ptr(),
                                                depth_range.data_ptr(), float(normal_weight),
                                                C.byref(loss) if want_loss else None, _dptr(grad)))
+        self._last_shape = (B, h, w)
         return (loss.value if want_loss else None), grad
+
+    def tensor(self, kind: int, layer: int):
+        """A tensor the last pass stored (bfloat16 widened to float32), (B, h, w, C): kind 0
+        the activation entering ``layer`` (0 = the input), kind 1 the loss gradient at the
+        output of ``layer`` (the last layer's is the loss's own)."""
+        torch = self.torch
+        self._sync_stream()
+        B, h, w = getattr(self, "_last_shape", (0, 0, 0))
+        last = len(self.SHAPES) - 1
+        C_ = (self.IN if layer == 0 else 32) if kind == 0 else (self.OUT if layer == last else 32)
+        out = torch.empty((B, h, w, C_), dtype=torch.float32, device=self.device)
+        self._check(lib().phimvs_net_tensor(self.h, kind, layer, out.data_ptr()))
+        return out
 
     def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
         self._sync_stream()

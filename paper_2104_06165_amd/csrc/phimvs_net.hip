@@ -251,6 +251,13 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, int n_pix, int C0, i
 }
 
 // master fp32 weights [9][CIN][COUT] -> bf16 forward [9][COP][CIP] and flipped [9][CIP][COP]
+__global__ void bf16_unpad_kernel(const uint16_t* __restrict__ x, int n_pix, int CP, int C, float* __restrict__ y) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n_pix * C) return;
+  const size_t p = i / C, c = i - p * C;
+  y[i] = bf2f(x[p * CP + c]);
+}
+
 __global__ void pack_weights_kernel(const float* __restrict__ w, int CIN, int COUT, int CIP, int COP,
                                     uint16_t* __restrict__ fwd, uint16_t* __restrict__ flip) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -464,6 +471,13 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t st) {
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t st) {
   if (a.CI % 16 || a.CO % 16 || a.CI < 16 || a.CO < 16 || a.CI > kMaxCO || a.CO > kMaxCO) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pmn::conv3x3_wgrad_kernel, dim3(a.B * a.h), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf16_unpad(const uint16_t* x, int n_pix, int CP, int C, float* y, hipStream_t st) {
+  const size_t n = (size_t)n_pix * C;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pmn::bf16_unpad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n_pix, CP, C, y);
   return hipGetLastError();
 }
 

@@ -58,7 +58,10 @@ struct phimvs_net {
   uint16_t* wfwd[kLayers] = {};   // [9][COP][CIP] bf16
   uint16_t* wflip[kLayers] = {};  // [9][CIP][COP] bf16, taps mirrored (data gradient)
   Buf<uint16_t> act[kLayers + 1];  // act[0]: input (16 ch); act[l]: output of layer l (32 ch)
-  Buf<uint16_t> g16[2];            // data gradients (ping-pong)
+  Buf<uint16_t> g16[kLayers];      // g16[l]: gradient at the output of layer l (kCop[l] ch)
+  int last_B = 0, last_h = 0, last_w = 0;  // shape of the last forward pass
+  bool have_act = false;   // act[] hold the last forward pass
+  bool have_bwd = false;   // g16[] hold the backward pass of that forward pass
   Buf<float> out32, partial, partial_b, gpad, gbias, loss_partial, tmp_in, tmp_out;
 };
 
@@ -115,6 +118,8 @@ int forward(phimvs_net* n, int B, int h, int w, const float* input, float* outpu
   if ((rc = ensure(n, n->act[0], np * kCip[0]))) return rc;
   for (int l = 1; l < kLayers; ++l)
     if ((rc = ensure(n, n->act[l], np * kCop[l - 1]))) return rc;
+  n->have_act = false;
+  n->have_bwd = false;
   NCHECK(n, launch_to_bf16(input, (int)np, PHIMVS_NET_IN, kCip[0], n->act[0].p, n->stream));
   for (int l = 0; l < kLayers; ++l) {
     ConvArgs a{};
@@ -135,6 +140,10 @@ int forward(phimvs_net* n, int B, int h, int w, const float* input, float* outpu
     a.co_keep = last ? PHIMVS_NET_OUT : 0;
     NCHECK(n, launch_conv(a, n->stream));
   }
+  n->last_B = B;
+  n->last_h = h;
+  n->last_w = w;
+  n->have_act = true;
   return PHIMVS_OK;
 }
 
@@ -250,8 +259,8 @@ int phimvs_net_loss_grad(phimvs_net* n, int batch, int height, int width, const 
 
   const int n_blocks = (int)((np + 255) / 256);
   if ((rc = ensure(n, n->loss_partial, n_blocks))) return rc;
-  for (auto& g : n->g16)
-    if ((rc = ensure(n, g, np * 32))) return rc;
+  for (int l = 0; l < kLayers; ++l)
+    if ((rc = ensure(n, n->g16[l], np * kCop[l]))) return rc;
   LossArgs la{};
   la.n_pix = (int)np;
   la.h = h;
@@ -262,7 +271,7 @@ int phimvs_net_loss_grad(phimvs_net* n, int batch, int height, int width, const 
   la.drange = depth_range;
   la.inv_count = 1.f / (float)np;
   la.lambda = normal_weight;
-  la.grad16 = n->g16[0].p;
+  la.grad16 = n->g16[kLayers - 1].p;
   la.loss_partial = n->loss_partial.p;
   NCHECK(n, launch_loss(la, n->stream));
 
@@ -271,7 +280,6 @@ int phimvs_net_loss_grad(phimvs_net* n, int batch, int height, int width, const 
   if ((rc = ensure(n, n->partial, (size_t)rows * max_w)) || (rc = ensure(n, n->partial_b, (size_t)rows * 32)) ||
       (rc = ensure(n, n->gpad, max_w)) || (rc = ensure(n, n->gbias, 32)))
     return rc;
-  int cur = 0;  // g16[cur]: gradient at the output of layer l
   for (int l = kLayers - 1; l >= 0; --l) {
     WgradArgs wa{};
     wa.B = B;
@@ -280,7 +288,7 @@ int phimvs_net_loss_grad(phimvs_net* n, int batch, int height, int width, const 
     wa.CI = kCip[l];
     wa.CO = kCop[l];
     wa.x = n->act[l].p;
-    wa.g = n->g16[cur].p;
+    wa.g = n->g16[l].p;
     wa.partial = n->partial.p;
     wa.partial_bias = n->partial_b.p;
     NCHECK(n, launch_wgrad(wa, n->stream));
@@ -297,18 +305,18 @@ int phimvs_net_loss_grad(phimvs_net* n, int batch, int height, int width, const 
     a.w = w;
     a.CI = kCop[l];
     a.CO = kCip[l];
-    a.x = n->g16[cur].p;
+    a.x = n->g16[l].p;
     a.wt = n->wflip[l];
     a.bias = nullptr;
     a.relu = 0;
     a.mask16 = n->act[l].p;
-    a.y16 = n->g16[cur ^ 1].p;
+    a.y16 = n->g16[l - 1].p;
     a.y32 = nullptr;
     a.co_keep = 0;
     NCHECK(n, launch_conv(a, n->stream));
-    cur ^= 1;
   }
   n->have_grad = true;
+  n->have_bwd = true;
   if (grad)
     NCHECK(n, hipMemcpyAsync(grad, n->grad, (size_t)total_params() * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
   if (loss) {
@@ -319,6 +327,21 @@ int phimvs_net_loss_grad(phimvs_net* n, int batch, int height, int width, const 
     for (float v : part) s += v;
     *loss = s;
   }
+  return PHIMVS_OK;
+}
+
+int phimvs_net_tensor(phimvs_net* n, int kind, int layer, float* out) {
+  if (!n || !out) return fail(n, PHIMVS_E_ARG, "null argument");
+  if ((kind != 0 && kind != 1) || layer < 0 || layer >= kLayers)
+    return fail(n, PHIMVS_E_ARG, "kind must be 0 or 1 and layer in [0, " + std::to_string(kLayers - 1) + "]");
+  if (kind == 0 && !n->have_act) return fail(n, PHIMVS_E_STATE, "no forward pass yet");
+  if (kind == 1 && !n->have_bwd) return fail(n, PHIMVS_E_STATE, "call phimvs_net_loss_grad first");
+  NCHECK(n, hipSetDevice(n->device));
+  const int np = n->last_B * n->last_h * n->last_w;
+  if (kind == 0)
+    NCHECK(n, launch_bf16_unpad(n->act[layer].p, np, kCip[layer], kCin[layer], out, n->stream));
+  else
+    NCHECK(n, launch_bf16_unpad(n->g16[layer].p, np, kCop[layer], kCout[layer], out, n->stream));
   return PHIMVS_OK;
 }
 

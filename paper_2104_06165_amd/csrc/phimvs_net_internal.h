@@ -77,6 +77,8 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t st);
 hipError_t launch_wgrad(const WgradArgs& a, hipStream_t st);
 hipError_t launch_reduce_rows(const float* partial, int n_rows, int stride, int n, float* out, hipStream_t st);
 hipError_t launch_to_bf16(const float* x, int n_pix, int C0, int CP, uint16_t* y, hipStream_t st);
+// bf16 NHWC with CP channels -> float32 NHWC with the first C channels
+hipError_t launch_bf16_unpad(const uint16_t* x, int n_pix, int CP, int C, float* y, hipStream_t st);
 hipError_t launch_pack_weights(const float* w, int CIN, int COUT, int CIP, int COP, uint16_t* fwd, uint16_t* flip,
                                hipStream_t st);
 // padded gradient gp [9][CIP][COP] (+ bias gb[COP]) -> flat [9][CIN][COUT] then [COUT]

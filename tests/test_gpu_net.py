@@ -89,28 +89,107 @@ def test_forward_zero_params_gives_zero(net):
     assert torch.count_nonzero(net.forward(dev(x))).item() == 0
 
 
-@pytest.mark.parametrize("B,h,w", [(2, 13, 21), (1, 32, 48)])
+def _within_bf16_rounding(gpu, ref, abs_terms, tag):
+    """GPU values stored as bfloat16 after an FP32 sum, against the exact sum of the same
+    bfloat16 operands rounded once to bfloat16: equal unless the FP32 sum lies within its
+    own rounding error of a bfloat16 rounding boundary.  Bars: >= 99.5% bitwise equal, and
+    every value within one bfloat16 unit (2^-7 of its magnitude) plus twice the FP32
+    summation error (3e-5 of the sum of the terms' magnitudes)."""
+    d = np.abs(gpu - ref)
+    eq = (gpu == ref).mean()
+    ok = d <= 2.0 ** -7 * np.abs(ref) + 6e-5 * abs_terms + 1e-30
+    say(f"  {tag}: bitwise {eq:.6f}, max |d| {d.max():.3g}, within bound {ok.mean():.6f}")
+    assert eq >= 0.995 and ok.all()
+
+
+@pytest.mark.parametrize("B,h,w", [(2, 13, 21), (1, 32, 48), (1, 3, 150), (2, 5, 400), (1, 2, 129)])
 def test_loss_and_gradient_parity(net, B, h, w):
-    p = rand_params(10 + B)
-    x, tgt, mask, drange = rand_batch(11 + B, B, h, w)
+    """Every kernel of a training step, layer by layer, element by element: the oracle is
+    given the GPU's own stored bfloat16 activations and back-propagated gradients
+    (``Net.tensor``), so each check sees one kernel's arithmetic and nothing upstream.
+    Rows wider than 64 pixels reach the weight-gradient kernel's later 64-pixel chunks and
+    the halo column at a chunk boundary (widths 129, 150 and 400 are not multiples of 64).
+
+    Weight and bias gradients are FP32 sums (per image row, then the rows in a fixed
+    order) of exact bfloat16 products: each element within 3e-5 of the sum of its terms'
+    magnitudes (the FP32 summation-order error; a missing or extra pixel, tap or channel
+    moves an element by a whole term or more).  Activations, the loss gradient and data
+    gradients are stored as bfloat16: see ``_within_bf16_rounding``.  End to end against
+    the oracle run alone with the same roundings the layers differ further, because an
+    FP32-order difference can flip a stored value's bfloat16 rounding (probability about
+    5e-5 per value) and each flip moves every upstream gradient a little: that comparison
+    is held to a relative norm of 1e-2 per layer."""
+    p = rand_params(10 + B + w)
+    x, tgt, mask, drange = rand_batch(11 + B + w, B, h, w)
     net.set_params(p)
-    loss, g = net.loss_grad(dev(x), dev(tgt), dev(mask), dev(drange), normal_weight=0.5, want_grad=True)
+    X, T, M, D = dev(x), dev(tgt), dev(mask), dev(drange)
+    out = net.forward(X).cpu().numpy().astype(np.float64)
+    loss, g = net.loss_grad(X, T, M, D, normal_weight=0.5, want_grad=True)
     g = g.cpu().numpy().astype(np.float64)
-    rl, rg = cnn.loss_grad(p.astype(np.float64), x.astype(np.float64), tgt.astype(np.float64),
-                           mask.astype(np.float64), drange.astype(np.float64), 0.5, like_gpu=True)
-    say(f"loss gpu {loss:.8g} oracle {rl:.8g}")
-    assert abs(loss - rl) <= 1e-4 * abs(rl) + 1e-7
+    acts = [net.tensor(0, l).cpu().numpy().astype(np.float64) for l in range(5)]
+    grads = [net.tensor(1, l).cpu().numpy().astype(np.float64) for l in range(5)]
+    layers = [(cnn.bf16(wl), cnn.f32(bl)) for wl, bl in cnn.unpack(p.astype(np.float64))]
     offs = np.cumsum([0] + [9 * ci * co + co for ci, co in cnn.SHAPES])
+    # the input as stored, and each layer's forward pass from the stored input of that layer
+    assert np.array_equal(acts[0], cnn.bf16(x))
+    for l in range(4):
+        wl, bl = layers[l]
+        z = cnn.conv3x3(acts[l], wl, bl)
+        _within_bf16_rounding(acts[l + 1], cnn.bf16(np.maximum(z, 0.0)),
+                              cnn.conv3x3(np.abs(acts[l]), np.abs(wl), np.abs(bl)), f"forward layer {l + 1}")
+    wl, bl = layers[4]
+    ref_out = cnn.conv3x3(acts[4], wl, bl)
+    bound = 3e-5 * cnn.conv3x3(np.abs(acts[4]), np.abs(wl), np.abs(bl)) + 1e-30
+    say(f"  forward layer 5 (FP32 out): max |d| / bound {(np.abs(out - ref_out) / bound).max():.3g}")
+    assert np.all(np.abs(out - ref_out) <= bound)
+    # the loss and its gradient with respect to the outputs, from the GPU's outputs
+    rl = cnn.loss(out, tgt.astype(np.float64), mask.astype(np.float64), drange.astype(np.float64), 0.5)
+    say(f"loss gpu {loss:.8g} oracle {rl:.8g}")
+    assert abs(loss - rl) <= 1e-5 * abs(rl) + 1e-7
+    g_out = cnn.loss_output_grad(out, tgt.astype(np.float64), mask.astype(np.float64), drange.astype(np.float64), 0.5)
+    _within_bf16_rounding(grads[4], cnn.bf16(g_out), np.abs(g_out) * 1e-2, "loss gradient")
+    for l in range(4, -1, -1):
+        # weight and bias gradients of layer l from its stored input and output gradient
+        ref_w = cnn.conv3x3_wgrad(acts[l], grads[l])
+        abs_w = cnn.conv3x3_wgrad(np.abs(acts[l]), np.abs(grads[l]))
+        ref_b = grads[l].sum(axis=(0, 1, 2))
+        abs_b = np.abs(grads[l]).sum(axis=(0, 1, 2))
+        ci, co = cnn.SHAPES[l]
+        gw = g[offs[l]:offs[l] + 9 * ci * co].reshape(9, ci, co)
+        gb = g[offs[l] + 9 * ci * co:offs[l + 1]]
+        rw = np.abs(gw - ref_w) / (abs_w + 1e-30)
+        rb = np.abs(gb - ref_b) / (abs_b + 1e-30)
+        say(f"  layer {l + 1} weight / bias gradient: max error {rw.max():.3g} / {rb.max():.3g} of the terms' "
+            f"magnitude sum")
+        assert np.all(np.abs(gw - ref_w) <= 3e-5 * abs_w + 1e-30)
+        assert np.all(np.abs(gb - ref_b) <= 3e-5 * abs_b + 1e-30)
+        if l == 0:
+            break
+        # data gradient into layer l's input, through the ReLU of layer l - 1
+        dg = cnn.conv3x3_dgrad(grads[l], layers[l][0]) * (acts[l] > 0)
+        abs_dg = cnn.conv3x3_dgrad(np.abs(grads[l]), np.abs(layers[l][0])) * (acts[l] > 0)
+        _within_bf16_rounding(grads[l - 1], cnn.bf16(dg), abs_dg, f"data gradient into layer {l + 1}")
+    # end to end against the oracle run on its own with the same roundings, and against float64
+    _, rg = cnn.loss_grad(p.astype(np.float64), x.astype(np.float64), tgt.astype(np.float64),
+                          mask.astype(np.float64), drange.astype(np.float64), 0.5, like_gpu=True)
     for l in range(5):
         a, b = g[offs[l]:offs[l + 1]], rg[offs[l]:offs[l + 1]]
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        say(f"  layer {l + 1}: |grad| {np.linalg.norm(b):.4g}, relative error {rel:.3g}")
+        say(f"  layer {l + 1} end to end: relative error {rel:.3g}")
         assert rel <= 1e-2
-    # and against the pure float64 gradient (no bfloat16 anywhere): the price of the storage format
     _, g64 = cnn.loss_grad(p.astype(np.float64), x, tgt, mask, drange, 0.5)
     rel64 = np.linalg.norm(g - g64) / np.linalg.norm(g64)
     say(f"  whole gradient vs float64 oracle (no bf16): relative error {rel64:.3g}")
     assert rel64 <= 0.1
+
+
+def test_tensor_hook_errors(net):
+    """The read-back hook refuses another kind or layer."""
+    x, tgt, mask, drange = rand_batch(40, 1, 4, 5)
+    net.loss_grad(dev(x), dev(tgt), dev(mask), dev(drange))
+    for kind, layer in ((2, 0), (0, 5), (1, -1)):
+        with pytest.raises(pm.PhimvsError):
+            net.tensor(kind, layer)
 
 
 def test_adam_steps_match_the_oracle(net):
