@@ -54,6 +54,8 @@ struct Batch {
   int total_tiles = 0, total_cblk = 0, max_r = 0, max_taps = 0, tile_rows = 4;
   int xcd_len[8] = {};
   std::string layout_key;        // problems + tile shape the state was built for
+  bool state_exact = false;      // every stored cost is the cost of its stored plane (the library's
+                                 // own initialisation and steps keep this; phimvs_set_state does not)
   // captured launch sequence
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -465,6 +467,8 @@ int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack, bool with
     HIPCHECK(c, launch_candidates(0, b.d_jobs, L, c->stream));
     if ((rc = run_eval(c, b, L, b.queues.p + 8 * q++))) return rc;
   }
+  b.state_exact = true;
+  L.skip_current = 1;
   for (int it = 1; it <= iters; ++it)
     for (int colour = 0; colour < 2; ++colour) {
       L.colour = colour;
@@ -760,6 +764,7 @@ int phimvs_prepare(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int wind
   J.valid_out = nullptr;
   J.depth_out = J.normal_out = J.final_cost_out = J.planes_out = nullptr;
   if ((rc = upload_jobs(c, b))) return rc;
+  b.state_exact = false;
   c->prepared = true;
   return PHIMVS_OK;
 }
@@ -789,6 +794,7 @@ int phimvs_init_planes(phimvs_ctx* c, const float* proposal, int on_device) {
     b.jobs[0].planes_in = nullptr;
     if ((rc = upload_jobs(c, b))) return rc;  // waits for the launches reading the proposal
   }
+  b.state_exact = true;
   return PHIMVS_OK;
 }
 
@@ -803,6 +809,7 @@ int phimvs_step(phimvs_ctx* c, int iteration, int colour, int do_propagate, int 
   L.colour = colour;
   L.iteration = iteration;
   L.mode = 1;
+  L.skip_current = b.state_exact ? 1 : 0;
   if (do_propagate) {
     L.ncand = 8;
     HIPCHECK(c, launch_candidates(1, b.d_jobs, L, c->stream));
@@ -863,6 +870,7 @@ int phimvs_set_state(phimvs_ctx* c, const float* planes, const float* cost, int 
   if ((rc = input_ptr(c, c->io_b, cost, n, on_device, &dc))) return rc;
   HIPCHECK(c, launch_pack(c->single.d_jobs, J.A.W, J.A.H, dp, dc, c->stream));
   if (!on_device) HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->single.state_exact = false;  // the caller's costs need not be its planes' costs
   return PHIMVS_OK;
 }
 

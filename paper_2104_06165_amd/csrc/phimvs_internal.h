@@ -11,6 +11,10 @@
 namespace phimvs_internal {
 
 constexpr int kBlock = 256;        // threads per evaluate workgroup
+// evaluate kernel's compaction arrays in dynamic LDS, in floats: per pixel S_w, mu_a,
+// var_a (3 kBlock), cost per (slot, pixel) (8 kBlock), the (pixel, slot) list as 16-bit
+// entries (4 kBlock) and the waves' counts (8)
+constexpr int kCompactLds = 15 * kBlock + 8;
 constexpr int kMaxTopK = PHIMVS_MAX_SOURCES;
 constexpr int kMaxTaps1D = 31;     // taps per window side
 
@@ -74,6 +78,8 @@ struct Launch {
   int xcd_len[8];                      // evaluate tiles of each XCD's list
   int persistent;                      // evaluate: tiles pulled from per-XCD queues
   int frac;                            // evaluate: some job uses the window-resize scheme
+  int skip_current;                    // propagation candidates: drop those equal to the pixel's current
+                                       // plane (only when every stored cost is its plane's own cost)
   unsigned int* queue;                 // 8 counters, zero at launch (persistent only)
   unsigned long long* count;           // optional: + (pixel, hypothesis) pairs scored
 };

@@ -616,9 +616,17 @@ __global__ __launch_bounds__(128) void cand_init_kernel(const Job* __restrict__ 
   if (J.planes_in) J.cand[plane_sz + cidx] = reinterpret_cast<const float4*>(J.planes_in)[(size_t)y * A.W + x];
 }
 
+__device__ __forceinline__ bool same4(float4 a, float4 b) {
+  return __float_as_uint(a.x) == __float_as_uint(b.x) && __float_as_uint(a.y) == __float_as_uint(b.y) &&
+         __float_as_uint(a.z) == __float_as_uint(b.z) && __float_as_uint(a.w) == __float_as_uint(b.w);
+}
+
 // red/black propagation candidates: per region, the other colour's lowest-cost pixel q
 // (first in enumeration order on ties), its plane re-expressed at p by ray-plane
-// intersection; empty if the plane does not face p's ray or leaves the depth range
+// intersection; empty if the plane does not face p's ray or leaves the depth range.
+// A candidate bitwise equal to an earlier one, or (skip_current) to the pixel's current
+// plane, has that plane's cost, so under the strict-improvement rule it can never be
+// taken: it is left empty, which leaves the selection's result unchanged.
 __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ jobs, Launch L) {
   int jb, x, y, ci;
   if (!cblk_pixel(jobs, L, jb, x, y, ci)) return;
@@ -632,6 +640,8 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
   const GLOBAL float* __restrict__ ocost = gl(A.cost[oc]);
   float rx, ry, rz;
   ray_f(A, x, y, rx, ry, rz);
+  const float4 cur = valid && L.skip_current ? ld4(A.plane[L.colour], cidx) : make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 prev[8];
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
     float4 cand = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
@@ -674,6 +684,13 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
         if ((den < 0.0f) && (dn >= A.d_lo && dn <= A.d_hi)) cand = make_float4(q.x, q.y, q.z, dn);
       }
     }
+    if (!__builtin_isnan(cand.w)) {
+      bool dup = L.skip_current && same4(cand, cur);
+#pragma unroll
+      for (int j = 0; j < g; ++j) dup = dup || same4(cand, prev[j]);
+      if (dup) cand = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
+    }
+    prev[g] = cand;
     st4(J.cand, g * plane_sz + cidx, cand);
   }
 }
@@ -714,12 +731,19 @@ __global__ __launch_bounds__(128) void cand_refine_kernel(const Job* __restrict_
 }
 
 // ---------------------------------------------------------------------------- evaluate and select
-// A tile is tile_rows rows x (256 / tile_rows) compacted pixels of one colour of one job; one
-// lane per pixel.  mode 0: initialisation (slot 0, the random plane, is taken; slot 1, a
-// proposal, replaces it when not more expensive).  mode 1: update (candidates 0..ncand-1 in
-// order replace the current plane on a strictly lower cost; the first of equal costs wins).
-// mode 2: cost of row-major input planes, optionally per source (a plane whose depth is NaN
+// A tile is tile_rows rows x (256 / tile_rows) compacted pixels of one colour of one job.
+// mode 0: initialisation (slot 0, the random plane, is taken; slot 1, a proposal, replaces
+// it when not more expensive).  mode 1: update (candidates 0..ncand-1 in order replace the
+// current plane on a strictly lower cost; the first of equal costs wins).  In both, the
+// tile's non-empty (pixel, slot) pairs form one list in LDS that every lane of the
+// workgroup's waves draws from, whatever its pixel, so that empty slots, left-out
+// duplicates and pixels outside the image take no lane; each pair's cost goes to LDS, and
+// each pixel's own lane then makes the selection in slot order.  mode 2: cost of row-major
+// input planes, one lane per pixel, optionally per source (a plane whose depth is NaN
 // scores C_max with every source invalid).
+//
+// Dynamic LDS: the compaction's arrays (kCompactLds floats), the spatial weights, then the
+// reference tile.
 template <bool FR>
 __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile_x, int tile_y, float* wcol,
                                           float* lds) {
@@ -729,7 +753,11 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   const int TC = kBlock / TR;  // compacted columns per tile
   const int r = A.halo;
   const int TW = 2 * TC + 2 * r, TH = TR + 2 * r;
-  float* wsp = lds;             // n_taps
+  float* ref_lds = lds;                                     // S_w (-1: not usable), mu_a, var_a per pixel
+  float* cost_lds = lds + 3 * kBlock;                       // cost of slot k of pixel p at [k][p]
+  uint16_t* item_lds = reinterpret_cast<uint16_t*>(lds + 11 * kBlock);  // (pixel << 3 | slot)
+  int* wave_total = reinterpret_cast<int*>(lds + 15 * kBlock);
+  float* wsp = lds + kCompactLds;  // n_taps
   float* tile_lds = wsp + A.n_taps;
   const int x_org = tile_x * 2 * TC - r;
   const int y_org = tile_y * TR - r;
@@ -818,29 +846,84 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
 
   const size_t cidx = (size_t)y * A.Wc + ci;
   const size_t plane_sz = (size_t)A.H * A.Wc;
+  // this pixel's reference data for whichever lane scores its candidates
+  ref_lds[threadIdx.x] = rp.ok ? rp.S_w : -1.0f;
+  ref_lds[kBlock + threadIdx.x] = rp.mu_a;
+  ref_lds[2 * kBlock + threadIdx.x] = rp.var_a;
+  unsigned live = 0;  // non-empty slots
+  if (valid)
+    for (int k = 0; k < L.ncand; ++k)
+      if (!__builtin_isnan(gl(J.cand)[k * plane_sz + cidx].w)) live |= 1u << k;
+  // the list: pixel order, slot order within a pixel (exclusive prefix of the counts over
+  // the workgroup: a scan within each wave, then the totals of the earlier waves)
+  const int cnt = __popc(live);
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
+  }
+  const int wave = threadIdx.x >> 6;
+  if (lane == 63) wave_total[wave] = incl;
+  __syncthreads();
+  int n_items = 0, off = incl - cnt;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    n_items += wave_total[w];
+    if (w < wave) off += wave_total[w];
+  }
+  for (unsigned m = live; m; m &= m - 1) item_lds[off++] = (uint16_t)((threadIdx.x << 3) | (__ffs(m) - 1));
+  if (L.count && threadIdx.x == 0) atomicAdd(L.count, (unsigned long long)n_items);
+  __syncthreads();
+  for (int base = wave * 64; base < n_items; base += kBlock) {
+    const int i = base + lane;
+    if (i < n_items) {
+      const int item = item_lds[i];
+      const int p = item >> 3, k = item & 7;
+      const int prow = p / TC, pcol = p - prow * TC;
+      const int py = tile_y * TR + prow;
+      const int pci = tile_x * TC + pcol;
+      const int ppar = (py + colour) & 1;
+      const int px = 2 * pci + ppar;
+      RefPix q;
+      q.x = px;
+      q.y = py;
+      q.X0 = (float)px;
+      q.Y0 = (float)py;
+      q.tbase = (prow + r - A.s * A.R) * TW + 2 * pcol + ppar + r - A.s * A.R;
+      q.tox = x_org;
+      q.toy = y_org;
+      ray_f(A, px, py, q.rx, q.ry, q.rz);
+      q.a_c = tile_lds[(prow + r) * TW + 2 * pcol + ppar + r];
+      const float sw = ref_lds[p];
+      q.ok = sw > 0.0f;
+      q.S_w = q.ok ? sw : 1.0f;
+      q.mu_a = ref_lds[kBlock + p];
+      q.var_a = ref_lds[2 * kBlock + p];
+      const float4 h = ld4(J.cand, k * plane_sz + (size_t)py * A.Wc + pci);
+      cost_lds[k * kBlock + p] =
+          plane_cost<FR>(A, q, tile_lds, TW, wcol, wsp, h.x, h.y, h.z, h.w, nullptr, nullptr);
+    }
+  }
+  __syncthreads();
+  if (!in_img || (L.mode == 1 && !valid)) return;
   float4 best = make_float4(0.f, 0.f, 0.f, 0.f);
   float bc = kCmax;
-  if (L.mode == 1 && valid) {
+  if (L.mode == 1) {
     best = ld4(A.plane[colour], cidx);
     bc = gl(A.cost[colour])[cidx];
   }
+  int pick = -1;
   for (int k = 0; k < L.ncand; ++k) {
-    float4 h = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
-    if (valid) h = ld4(J.cand, k * plane_sz + cidx);
-    const bool has = valid && !__builtin_isnan(h.w);
-    const unsigned long long bal = __ballot(has);
-    if (bal == 0) continue;
-    if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(bal));
-    if (has) {
-      const float c = plane_cost<FR>(A, rp, tile_lds, TW, wcol, wsp, h.x, h.y, h.z, h.w, nullptr, nullptr);
-      const bool take = L.mode == 0 ? (k == 0 || c <= bc) : (c < bc);
-      if (take) {
-        bc = c;
-        best = h;
-      }
+    if (!((live >> k) & 1u)) continue;
+    const float c = cost_lds[k * kBlock + threadIdx.x];
+    const bool take = L.mode == 0 ? (k == 0 || c <= bc) : (c < bc);
+    if (take) {
+      bc = c;
+      pick = k;
     }
   }
-  if (!in_img || (L.mode == 1 && !valid)) return;
+  if (pick >= 0) best = ld4(J.cand, pick * plane_sz + cidx);
   if (!valid) {
     best = make_float4(0.f, 0.f, 0.f, 0.f);
     bc = kCmax;
@@ -970,7 +1053,8 @@ namespace phimvs_internal {
 size_t eval_lds_bytes(int tile_rows, int max_radius_px, int max_taps) {
   const int TC = kBlock / tile_rows;
   const size_t tw = 2 * TC + 2 * max_radius_px, th = tile_rows + 2 * max_radius_px;
-  return sizeof(float) * ((size_t)max_taps + tw * th);  // the colour-weight table is static
+  // the colour-weight table is static
+  return sizeof(float) * ((size_t)kCompactLds + (size_t)max_taps + tw * th);
 }
 
 hipError_t eval_lds_setup(size_t* max_dynamic) {

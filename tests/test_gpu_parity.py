@@ -168,6 +168,34 @@ def test_halfsweep_parity_tiny(ctx, tiny):
         P, Cst = P2, C2
 
 
+def test_halfsweep_after_a_state_whose_costs_are_not_its_planes(ctx, tiny):
+    """A propagation candidate equal to the pixel's current plane is left out only while
+    every stored cost is its plane's own cost (the library's own initialisation and
+    steps).  After set_state with every cost at C_max that no longer holds: such
+    candidates must be scored and taken, as the oracle does."""
+    scene, cfg = tiny
+    pb = _prep(ctx, scene, cfg)
+    P, _ = oracle.init(pb)
+    P, C = oracle.halfsweep(pb, P, oracle.eval_cost(pb, P)[0], 1, 0)
+    P, C = oracle.halfsweep(pb, P, C, 1, 1)
+    Cmax = np.full_like(C, 2.0)
+    m = pb.valid_mask()
+    for it, col in [(2, 0), (2, 1)]:
+        ctx.set_state(torch.tensor(P, dtype=torch.float32, device="cuda"),
+                      torch.tensor(Cmax, dtype=torch.float32, device="cuda"))
+        ctx.step(it, col, refine=False)
+        gp, gc = ctx.get_state()
+        P2, C2 = oracle.halfsweep(pb, P, Cmax, it, col, refine=False)
+        gp = gp.cpu().numpy()
+        same = np.all(gp == P2.astype(np.float32), axis=-1)[m]
+        say(f"propagation {it}/{col} from costs at C_max: planes bitwise {same.mean():.6f}")
+        frac, bit = compare(f"propagation {it}/{col} (costs at C_max)", gc.cpu().numpy(), C2, m, gp[..., 3], P2[..., 3])
+        assert same.mean() >= FRAC and bit >= FRAC
+        # pixels whose current plane came back as a candidate were updated to its cost
+        colour = (np.add.outer(np.arange(pb.H), np.arange(pb.W)) & 1) == col
+        assert (C2[m & colour] < 2.0).mean() > 0.99
+
+
 def test_patchmatch_parity_tiny(ctx, tiny):
     scene, cfg = tiny
     pb = _prep(ctx, scene, cfg)
