@@ -70,6 +70,7 @@ class _Problem(C.Structure):
         ("eps_c", C.c_double),
         ("seed", C.c_uint64),
         ("tap_radius", C.c_int32),
+        ("lanes", C.c_int32),
     ]
 
 
@@ -146,7 +147,7 @@ class Problem:
     def __init__(self, images: Sequence[np.ndarray], K, R, t, depth_range, window: int, dilation: int,
                  top_k: int = 0, bilateral: bool = True, sigma_s: Optional[float] = None,
                  sigma_c: float = 12.0, eps_v: float = 1e-4, eps_c: float = 1e-4, seed: int = 0x5EED,
-                 tap_radius: int = 0):
+                 tap_radius: int = 0, lanes: int = 1):
         self.images = [np.ascontiguousarray(im, dtype=np.float32) for im in images]
         n = len(self.images)
         self.K = np.ascontiguousarray(np.asarray(K, dtype=np.float64).reshape(n, 9))
@@ -158,11 +159,12 @@ class Problem:
         if sigma_s is None:
             sigma_s = (window - 1) / 2.0
         self.window, self.dilation, self.top_k, self.tap_radius = window, dilation, top_k, tap_radius
+        self.lanes = lanes
         self.s = _Problem(n, _ptr(self.w, C.c_int32), _ptr(self.h, C.c_int32), self._imgptrs,
                           _ptr(self.K, C.c_double), _ptr(self.R, C.c_double), _ptr(self.t, C.c_double),
                           float(depth_range[0]), float(depth_range[1]), window, dilation, top_k,
                           1 if bilateral else 0, float(sigma_s), float(sigma_c), float(eps_v), float(eps_c),
-                          int(seed) & 0xFFFFFFFFFFFFFFFF, int(tap_radius))
+                          int(seed) & 0xFFFFFFFFFFFFFFFF, int(tap_radius), int(lanes))
 
     @property
     def W(self):

@@ -45,6 +45,10 @@
 //    at the pixel by ray-plane intersection, and keeps the best candidate if it
 //    strictly lowers the cost.  Refinement of a colour follows its propagation; one
 //    iteration is red then black.
+//  * Summation order: a view's source-side sums (S_b, S_bb, S_ab) run over the taps in
+//    row-major order; with lanes = G > 1 they are formed as G lanes sharing the view form
+//    them (lane g sums the taps t = g mod G in order, then an xor butterfly over offsets
+//    G/2 .. 1), the order of the GPU's split sums.  The reference-side sums stay sequential.
 //  * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed and counter
 //    = (pixel index y*W + x, iteration, phase, 0); uniforms (x >> 8) * 2^-24.
 //  * Pixels whose reference window leaves the image are invalid: never updated,
@@ -156,6 +160,7 @@ typedef struct {
   double sigma_s, sigma_c, eps_v, eps_c;
   uint64_t seed;
   int32_t tap_radius;  // > 0: the window-resize scheme, r_now = tap_radius taps per side
+  int32_t lanes;       // > 1 (a power of two): the source-side tap sums as G lanes form them
 } oracle_problem;
 
 }  // extern "C"
@@ -210,6 +215,7 @@ struct Solver {
 
   bool setup(const oracle_problem* p) {
     pb = p;
+    if (p->lanes > 1 && (p->lanes & (p->lanes - 1))) return false;  // G must be a power of two
     W = p->width[0];
     H = p->height[0];
     n_src = p->n_views - 1;
@@ -390,15 +396,47 @@ struct Solver {
       warp(Hm, (T)x, (T)y, &up, &vp);
       T b_c = sample(view, up, vp);
       T S_b = 0, S_bb = 0, S_ab = 0;
-      for (int k2 = -R, t = 0; k2 <= R; ++k2)
-        for (int k1 = -R; k1 <= R; ++k1, ++t) {
-          warp(Hm, (T)x + off[k1 + R], (T)y + off[k2 + R], &up, &vp);
-          T b = sample(view, up, vp) - b_c;
-          T tb = wk[t] * b;
-          S_b = S_b + tb;
-          S_bb = fmaT(tb, b, S_bb);
-          S_ab = fmaT(wak[t], b, S_ab);
+      if (pb->lanes <= 1) {
+        for (int k2 = -R, t = 0; k2 <= R; ++k2)
+          for (int k1 = -R; k1 <= R; ++k1, ++t) {
+            warp(Hm, (T)x + off[k1 + R], (T)y + off[k2 + R], &up, &vp);
+            T b = sample(view, up, vp) - b_c;
+            T tb = wk[t] * b;
+            S_b = S_b + tb;
+            S_bb = fmaT(tb, b, S_bb);
+            S_ab = fmaT(wak[t], b, S_ab);
+          }
+      } else {
+        // G lanes share the view: lane g sums the taps t = g, g + G, g + 2G, ... (row-major
+        // tap index, in that order); then at each offset o = G/2, G/4, ..., 1 every lane adds
+        // the partial sum of lane g xor o to its own, after which all lanes hold the total
+        const int G = pb->lanes;
+        std::vector<T> pb_(G, T(0)), pbb(G, T(0)), pab(G, T(0));
+        for (int k2 = -R, t = 0; k2 <= R; ++k2)
+          for (int k1 = -R; k1 <= R; ++k1, ++t) {
+            warp(Hm, (T)x + off[k1 + R], (T)y + off[k2 + R], &up, &vp);
+            T b = sample(view, up, vp) - b_c;
+            T tb = wk[t] * b;
+            const int g = t % G;
+            pb_[g] = pb_[g] + tb;
+            pbb[g] = fmaT(tb, b, pbb[g]);
+            pab[g] = fmaT(wak[t], b, pab[g]);
+          }
+        for (int o = G / 2; o >= 1; o /= 2) {
+          std::vector<T> nb(G), nbb(G), nab(G);
+          for (int g = 0; g < G; ++g) {
+            nb[g] = pb_[g] + pb_[g ^ o];
+            nbb[g] = pbb[g] + pbb[g ^ o];
+            nab[g] = pab[g] + pab[g ^ o];
+          }
+          pb_.swap(nb);
+          pbb.swap(nbb);
+          pab.swap(nab);
         }
+        S_b = pb_[0];
+        S_bb = pbb[0];
+        S_ab = pab[0];
+      }
       T mu_b = S_b / S_w;
       T var_b = S_bb / S_w - mu_b * mu_b;
       T cov = S_ab / S_w - mu_a * mu_b;

@@ -123,9 +123,11 @@ def test_zncc_bounded_and_symmetric():
 
 @pytest.mark.parametrize("dilation,window", [(1, 7), (2, 9), (3, 7)])
 @pytest.mark.parametrize("bilateral", [False, True])
-def test_zncc_matches_library_correlation(dilation, window, bilateral):
+@pytest.mark.parametrize("lanes", [1, 4, 16])
+def test_zncc_matches_library_correlation(dilation, window, bilateral, lanes):
     """Integer-translation homography: the warped window is a shifted dilated window of the
-    source, so 1 - C_j must be numpy's (weighted) Pearson correlation of the two patches."""
+    source, so 1 - C_j must be numpy's (weighted) Pearson correlation of the two patches,
+    however the source-side tap sums are split over lanes."""
     h, w = 40, 44
     A = _textured(h, w, 7)
     B = _textured(h, w, 8)
@@ -134,7 +136,7 @@ def test_zncc_matches_library_correlation(dilation, window, bilateral):
     Kj = _K(w, h, dcx=D)
     sig_s, sig_c = 4.0, 12.0
     pb = _pose_problem([A, B], [K0, Kj], window=window, dilation=dilation, bilateral=bilateral,
-                       sigma_s=sig_s, sigma_c=sig_c)
+                       sigma_s=sig_s, sigma_c=sig_c, lanes=lanes)
     _, pv, ok = oracle.eval_cost(pb, _fronto(h, w), fp64=True)
     R = (window - 1) // (2 * dilation)
     ks = np.arange(-R, R + 1) * dilation
@@ -157,6 +159,35 @@ def test_zncc_matches_library_correlation(dilation, window, bilateral):
         assert abs((1 - pv[y, x, 0]) - z) < 1e-10
         checked += 1
     assert checked == 40
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16])
+def test_lane_split_sums_differ_from_one_sum_by_rounding_only(small_scene, lanes):
+    """Splitting each view's tap sums over G lanes changes only the FP32 rounding: costs of
+    random and ground-truth planes within 1e-5 of the single-sum costs (FP32), within 1e-12
+    in FP64; identical patches still give C = 0 exactly; G not a power of two is refused."""
+    sc = small_scene
+    one = oracle.Problem.from_scene(sc, 7, 1, top_k=0)
+    many = oracle.Problem.from_scene(sc, 7, 1, top_k=0, lanes=lanes)
+    P, _ = oracle.init(one)
+    gt = np.zeros(P.shape)
+    gt[..., :3] = sc.gt_normal
+    gt[..., 3] = sc.gt_depth
+    m = one.valid_mask()
+    for planes in (P, gt):
+        a = oracle.eval_cost(one, planes)[0][m]
+        b = oracle.eval_cost(many, planes)[0][m]
+        assert np.abs(a - b).max() <= 1e-5
+        a64 = oracle.eval_cost(one, planes, fp64=True)[0][m]
+        b64 = oracle.eval_cost(many, planes, fp64=True)[0][m]
+        assert np.abs(a64 - b64).max() <= 1e-12
+    A = _textured(24, 28, 1)
+    K = _K(28, 24)
+    same = _pose_problem([A, A], [K, K], window=7, lanes=lanes)
+    _, pv, ok = oracle.eval_cost(same, _fronto(24, 28))
+    assert np.all(pv[same.valid_mask()] == 0.0)
+    with pytest.raises(ValueError):
+        oracle.eval_cost(oracle.Problem.from_scene(sc, 7, 1, lanes=lanes + 1 if lanes > 2 else 3), P)
 
 
 def test_dilation_equals_dense_window_on_decimated_images():
