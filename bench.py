@@ -491,6 +491,86 @@ def learned_vs_random(ctx, net, scene, srcs, solver, params, valid, textured, ra
     return out
 
 
+def bench_ceiling(args):
+    """How much any initialisation could gain under the equal-cost metric on the 3200x2130
+    workload: synthetic proposals handed to the same gated initialisation (true planes;
+    true depth with 2% and 5% multiplicative noise, true or perturbed normals; the 4x4
+    block mean of the true depth as fronto-parallel planes, plain and quantised to 32
+    inverse-depth levels), each run for k = 0..iters iterations, against the random run's
+    final mean cost + 1%.  Seeded noise (numpy, seed 7)."""
+    import torch
+
+    import paper_2104_06165_amd as pm
+    import scenegen as sg
+
+    scene = sg.workload_scene("highres", device="cuda")
+    sol = sg.SOLVER["highres"]
+    srcs = list(range(1, len(scene.images)))
+    win, dil, iters = sol["window"], sol["dilation"], sol["iters"]
+    params = pm.Params(top_k=sol["top_k"], bilateral=True, sigma_spatial_px=(win - 1) / 2.0, seed=sg.PM_SEED)
+    ctx = pm.Context(0)
+    ctx.set_scene(scene)
+    H, W = scene.images[0].shape
+    r = dil * ((win - 1) // (2 * dil))
+    valid = np.zeros((H, W), bool)
+    valid[r:H - r, r:W - r] = True
+    K = scene.cams[0].K
+    ys, xs = np.mgrid[0:H, 0:W]
+    rays = np.stack([xs, ys, np.ones_like(xs)], -1).astype(np.float64) @ np.linalg.inv(K).T
+    rng = np.random.default_rng(7)
+
+    def facing(n):
+        n = n / np.linalg.norm(n, axis=-1, keepdims=True)
+        flip = (n * rays).sum(-1) > 0
+        n[flip] = -n[flip]
+        return n
+
+    lo, hi = scene.depth_range
+    gt_d, gt_n = scene.gt_depth.astype(np.float64), scene.gt_normal.astype(np.float64)
+    bm = gt_d[:H - H % 4, :W - W % 4].reshape(H // 4, 4, W // 4, 4).mean(axis=(1, 3))
+    block = np.pad(np.repeat(np.repeat(bm, 4, 0), 4, 1), ((0, H % 4), (0, W % 4)), mode="edge")
+    inv = 1.0 / block
+    q = np.round((inv - 1.0 / hi) / ((1.0 / lo - 1.0 / hi) / 31)) * ((1.0 / lo - 1.0 / hi) / 31) + 1.0 / hi
+    fronto = facing(np.broadcast_to(np.array([0.0, 0.0, -1.0]), (H, W, 3)).copy())
+    kinds = {
+        "true planes": (gt_n, gt_d),
+        "true depth x (1 + 2% noise), true normals": (gt_n, gt_d * (1 + 0.02 * rng.standard_normal((H, W)))),
+        "true depth x (1 + 5% noise), normals +-0.2": (facing(gt_n + rng.uniform(-0.2, 0.2, (H, W, 3))),
+                                                     gt_d * (1 + 0.05 * rng.standard_normal((H, W)))),
+        "4x4-block mean depth, fronto-parallel": (fronto, block),
+        "the same quantised to 32 inverse-depth levels": (fronto, 1.0 / q),
+    }
+
+    def mean_cost(c):
+        return float(c.cpu().numpy()[valid].mean())
+
+    rand = [mean_cost(ctx.patchmatch(0, srcs, win, dil, k, params)[2]) for k in range(iters + 1)]
+    target = 1.01 * rand[-1]
+    rows = [{"proposal": "random (the method's own initialisation)", "mean_cost": rand,
+             "iters_to_target": next(k for k in range(iters + 1) if rand[k] <= target)}]
+    for name, (n, d) in kinds.items():
+        planes = np.concatenate([n, np.clip(d, lo, hi)[..., None]], -1).astype(np.float32)
+        prop = torch.from_numpy(np.ascontiguousarray(planes)).cuda()
+        mc = []
+        for k in range(iters + 1):
+            mc.append(mean_cost(ctx.patchmatch_proposal(0, srcs, win, dil, k, prop, params)[2]))
+            if mc[-1] <= target:
+                break
+        rows.append({"proposal": name, "mean_cost": mc,
+                     "iters_to_target": len(mc) - 1 if mc[-1] <= target else None})
+        log(f"[bench] {name}: {rows[-1]['iters_to_target']} iterations ({', '.join(f'{v:.4f}' for v in mc)})")
+    ctx.close()
+    line = {"metric": "iterations to the random run's final mean cost + 1% from synthetic initial proposals",
+            "value": min(r["iters_to_target"] for r in rows if r["iters_to_target"] is not None),
+            "unit": "iterations", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": f"synthetic (seeded piecewise-planar scene, seed {sg.SCENE_SEEDS['highres']}; noise seed 7)",
+            "config": {"workload": "ceiling: 1 reference + 10 sources at 3200x2130, 31x31 at dilation 3, top-5, "
+                                   "8 iterations, gated initialisation from synthetic proposals"},
+            "target_mean_cost": target, "table": rows}
+    print(json.dumps(line), flush=True)
+
+
 def bench_taps(args):
     """Split of the evaluate kernel's time on the 3200x2130 workload (10 sources, top-5, 8
     iterations) into a part per window tap and a fixed part per (pixel, hypothesis, view):
@@ -596,13 +676,15 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="highres",
-                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize", "taps", "train"])
+                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize", "taps", "train", "ceiling"])
     ap.add_argument("--cpu-iters", type=int, default=1,
                     help="iterations of the single-threaded oracle's sample (the all-thread runs take the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy"),
                     help="parameters of the proposal network for the learned-versus-random comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-versus-random comparison")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes sharing each pixel (2..16: split tap sums, for small references); 0: one lane")
     ap.add_argument("--tuning", default="", metavar="ROWS,PERSISTENT,WGS",
                     help="batched workload: use this launch configuration instead of autotuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -639,6 +721,8 @@ def main():
         return bench_taps(args)
     if wl == "train":
         return bench_train(args)
+    if wl == "ceiling":
+        return bench_ceiling(args)
     scene_name = "mid" if wl.startswith("mid") else wl
     solver = sg.SOLVER[wl]
     cfg = sg.CONFIGS[scene_name]
@@ -652,7 +736,7 @@ def main():
     n_src = len(scene.images) - 1
     srcs = list(range(1, n_src + 1))
     params = pm.Params(top_k=solver["top_k"], bilateral=True, sigma_spatial_px=(solver["window"] - 1) / 2.0,
-                       seed=sg.PM_SEED)
+                       seed=sg.PM_SEED, lanes=args.lanes)
     H, W = scene.images[0].shape
     out = (torch.empty((H, W), dtype=torch.float32, device="cuda"),
            torch.empty((H, W, 3), dtype=torch.float32, device="cuda"),
@@ -730,7 +814,7 @@ def main():
                    "width": W, "height": H, "n_src": n_src, "window": solver["window"],
                    "dilation": solver["dilation"], "top_k": solver["top_k"], "iters": solver["iters"],
                    "planes": cfg.n_planes, "images": "8-bit texel quads (sources), fp16 copy (reference) in HBM",
-                   "cost": "fp32"},
+                   "cost": "fp32", "lanes_per_pixel": max(1, args.lanes)},
         "ms_per_step_min": min(step_ms),
         "ms_per_step_median": float(np.median(step_ms)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",

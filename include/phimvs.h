@@ -91,6 +91,14 @@ typedef struct {
                                r_orig / r_now (not necessarily an integer), reference values
                                interpolated bilinearly, the colour weight taken at the nearest integer
                                grey difference; needs dilation 1 and r_now <= r_orig (default 0)       */
+  int32_t lanes;            /* 0 or 1: one lane scores a pixel's hypothesis, its taps summed in order.
+                               2, 4, 8 or 16: G lanes share each pixel, lane g summing the taps
+                               t = g, g + G, ... and the lanes' partial sums combined by an xor
+                               butterfly (offsets G/2 .. 1).  For small references, whose pixels
+                               alone do not fill the GPU; the order of the sums is part of the
+                               result (it changes the FP32 rounding only).  Single-job calls only
+                               (a batch job with lanes > 1, or combined with tap_radius > 0, fails
+                               with PHIMVS_E_UNSUPPORTED) (default 0)                              */
 } phimvs_params;
 
 void phimvs_default_params(phimvs_params* p);

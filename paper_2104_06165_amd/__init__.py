@@ -56,7 +56,7 @@ class _Image(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("top_k", C.c_int32), ("bilateral", C.c_int32), ("sigma_spatial_px", C.c_double),
                 ("sigma_color", C.c_double), ("eps_var", C.c_double), ("eps_cost", C.c_double),
-                ("seed", C.c_uint64), ("tap_radius", C.c_int32)]
+                ("seed", C.c_uint64), ("tap_radius", C.c_int32), ("lanes", C.c_int32)]
 
 
 class _Job(C.Structure):
@@ -125,11 +125,12 @@ class Params:
     eps_cost: float = 1e-4
     seed: int = 0x5EED
     tap_radius: int = 0  # > 0: the window-resize scheme with this many taps per side
+    lanes: int = 0  # 2..16: that many lanes share each pixel (split tap sums), for small references
 
     def _c(self) -> _Params:
         return _Params(int(self.top_k), 1 if self.bilateral else 0, float(self.sigma_spatial_px),
                        float(self.sigma_color), float(self.eps_var), float(self.eps_cost),
-                       int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.tap_radius))
+                       int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.tap_radius), int(self.lanes))
 
 
 _lib = None

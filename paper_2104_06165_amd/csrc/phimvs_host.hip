@@ -215,7 +215,7 @@ std::string problem_key(const Problem& P) {
                   std::to_string(P.p.top_k) + "," + std::to_string(P.p.bilateral) + "," + std::to_string(P.p.seed) +
                   "," + std::to_string(P.p.sigma_color) + "," + std::to_string(P.p.sigma_spatial_px) + "," +
                   std::to_string(P.p.eps_var) + "," + std::to_string(P.p.eps_cost) + "," +
-                  std::to_string(P.p.tap_radius);
+                  std::to_string(P.p.tap_radius) + "," + std::to_string(P.p.lanes);
   for (int s : P.srcs) k += ";" + std::to_string(s);
   return k;
 }
@@ -247,6 +247,10 @@ int validate_problem(phimvs_ctx* c, const Problem& P) {
     if (p.tap_radius > 15) return fail(c, PHIMVS_E_UNSUPPORTED, "at most 31 taps per window side");
     if ((P.window - 1) / 2 > 29) return fail(c, PHIMVS_E_UNSUPPORTED, "window radius above 29 px");
   }
+  if (p.lanes < 0 || p.lanes > 16 || (p.lanes & (p.lanes - 1)))
+    return fail(c, PHIMVS_E_ARG, "lanes must be 0, 1, 2, 4, 8 or 16");
+  if (p.lanes > 1 && p.tap_radius > 0)
+    return fail(c, PHIMVS_E_UNSUPPORTED, "lanes > 1 with the window-resize scheme");
   const int n = (int)P.srcs.size();
   if (p.top_k < 0 || p.top_k > n) return fail(c, PHIMVS_E_ARG, "top_k must be in [0, n_srcs]");
   if (!std::isfinite(p.sigma_spatial_px) || !(std::isfinite(p.sigma_color) && p.sigma_color > 0))
@@ -282,6 +286,7 @@ int setup_job(phimvs_ctx* c, const Problem& P, Job& J, JobState& S) {
   A.top_k = p.top_k;
   A.bilateral = p.bilateral ? 1 : 0;
   A.n_taps = (2 * R + 1) * (2 * R + 1);
+  A.lanes = p.lanes > 1 ? p.lanes : 1;
   double K0i[9];
   inv33(V0.K, K0i);
   for (int i = 0; i < 9; ++i) {
@@ -427,7 +432,10 @@ int run_eval(phimvs_ctx* c, Batch& b, Launch L, unsigned int* queue) {
   L.persistent = persistent ? 1 : 0;
   L.queue = queue;
   if (c->diag & PHIMVS_DIAG_COUNT) L.count = c->diag_count;
-  const size_t lds = eval_lds_bytes(b.tile_rows, b.max_r, b.max_taps);
+  const bool split = b.jobs.size() == 1 && b.jobs[0].A.lanes > 1;
+  const Args& A0 = b.jobs[0].A;
+  const size_t lds = split ? eval_lanes_lds_bytes(A0.lanes, A0.halo, A0.n_taps)
+                           : eval_lds_bytes(b.tile_rows, b.max_r, b.max_taps);
   if (lds > c->eval_lds_max)
     return fail(c, PHIMVS_E_UNSUPPORTED, "evaluate launch: " + std::to_string(b.tile_rows) + "-row tiles need " +
                                               std::to_string(lds) + " bytes of LDS, the device allows " +
@@ -441,7 +449,8 @@ int run_eval(phimvs_ctx* c, Batch& b, Launch L, unsigned int* queue) {
     c->diag_events.emplace_back(e0, e1);
     HIPCHECK(c, hipEventRecord(e0, c->stream));
   }
-  const hipError_t e = launch_eval(b.d_jobs, L, grid, lds, c->stream);
+  const hipError_t e = split ? launch_eval_lanes(b.d_jobs, L, A0.lanes, A0.H, A0.Wc, lds, c->stream)
+                              : launch_eval(b.d_jobs, L, grid, lds, c->stream);
   if (e != hipSuccess)
     return fail(c, PHIMVS_E_DEVICE, "evaluate launch (" + std::to_string(grid) + " workgroups, " +
                                         std::to_string(lds) + " bytes of dynamic LDS): " + hipGetErrorString(e));
@@ -611,6 +620,7 @@ void phimvs_default_params(phimvs_params* p) {
   p->eps_cost = 1e-4;
   p->seed = 0x5EED;
   p->tap_radius = 0;
+  p->lanes = 0;
 }
 
 int phimvs_create(phimvs_ctx** out, int device_ordinal, void* hip_stream) {
@@ -1200,6 +1210,8 @@ int phimvs_patchmatch_batch(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, i
     Problem P = make_problem(j.ref, j.srcs, j.n_srcs, j.window, j.dilation, &j.params);
     int rc = validate_problem(c, P);
     if (rc) return fail(c, rc, "job " + std::to_string(i) + ": " + c->err);
+    if (P.p.lanes > 1)
+      return fail(c, PHIMVS_E_UNSUPPORTED, "job " + std::to_string(i) + ": lanes > 1 is for single-job calls");
     probs.push_back(P);
     key += "|" + problem_key(P);
   }

@@ -36,6 +36,7 @@ struct Args {
   int frac;                // window-resize scheme: interpolated reference taps at fractional offsets
   int rv;                  // validity radius: a pixel is valid when its window (x +- rv) is inside
   int halo;                // reference-tile halo in pixels
+  int lanes;               // lanes sharing a pixel (1, or 2..16: split tap sums, single-job launches)
   float off[kMaxTaps1D];   // tap offsets k = 0 .. 2R: s (k - R), in FP32
   float Kinv[9];
   double Kinv_d[9];
@@ -91,6 +92,11 @@ size_t eval_lds_bytes(int tile_rows, int max_radius_px, int max_taps);
 // capture); *max_dynamic receives the largest dynamic LDS a launch may then ask for
 hipError_t eval_lds_setup(size_t* max_dynamic);
 hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds, hipStream_t st);
+// single-job evaluate launch with `lanes` (2, 4, 8, 16) lanes per pixel (job 0 of H rows,
+// Wc compacted columns); its LDS need for a reference-tile halo and tap count
+size_t eval_lanes_lds_bytes(int lanes, int radius_px, int n_taps);
+hipError_t launch_eval_lanes(const Job* d_jobs, const Launch& L, int lanes, int H, int Wc, size_t lds,
+                             hipStream_t st);
 // kind 0: random initialisation (+ proposal), 1: propagation, 2: refinement candidates
 hipError_t launch_candidates(int kind, const Job* d_jobs, const Launch& L, hipStream_t st);
 hipError_t launch_unpack(const Job* d_jobs, const Launch& L, hipStream_t st);

@@ -350,10 +350,81 @@ __device__ __forceinline__ void tap_pass(const Args& A, int J0, const RefPix& rp
   row(k2, qa, fxa, fya, qb, fxb, fyb);
 }
 
+// The same sums with LANES lanes sharing the pixel: lane g (its position within its aligned
+// group of LANES lanes) sums the taps t = g, g + LANES, ... in order, every tap computed
+// exactly as in tap_pass (the same fma chains; tap_pass only hoists the row's part), and the
+// partial sums are then combined by an xor butterfly: at offset o = LANES/2, ..., 1 every
+// lane adds the partial sum of lane g xor o to its own.  Addition commutes, so all lanes of
+// the group end with the same, bitwise equal, totals.  Lanes of one group always share
+// their pixel and candidate, so a butterfly partner is always active.
+template <int G, bool EXACT, bool CLAMP, int LANES>
+__device__ __forceinline__ void tap_pass_lanes(const Args& A, int J0, const RefPix& rp, const float* __restrict__ tile,
+                                               int TW, const float* __restrict__ wcol, const float* __restrict__ wsp,
+                                               const float (&Hm)[G][9], const float (&bc)[G], float (&Sb)[G],
+                                               float (&Sbb)[G], float (&Sab)[G]) {
+  const int R = A.R, s = A.s;
+  const int n = 2 * R + 1;
+  const int T = n * n;
+  const int g = (int)(threadIdx.x % LANES);
+  uint32_t Wq[G];
+  v4i32 rs[G];
+  float Wm1[G], Hm1[G];
+#pragma unroll
+  for (int v = 0; v < G; ++v) {
+    Sb[v] = 0.0f;
+    Sbb[v] = 0.0f;
+    Sab[v] = 0.0f;
+    Wq[v] = (uint32_t)A.src[J0 + v].W;
+    rs[v] = quad_rsrc(A.src[J0 + v].quad, (uint32_t)A.src[J0 + v].W * (uint32_t)A.src[J0 + v].H);
+    Wm1[v] = A.src[J0 + v].Wm1;
+    Hm1[v] = A.src[J0 + v].Hm1;
+  }
+  for (int t = g; t < T; t += LANES) {
+    const int k2 = t / n, k1 = t - k2 * n;
+    const float X = rp.X0 + (float)(s * (k1 - R));
+    const float Y = rp.Y0 + (float)(s * (k2 - R));
+    const float a4 = tile[rp.tbase + (k2 * TW + k1) * s] - rp.a_c;  // 4 (a - a_c)
+    const float w = colour_weight<false>(wcol, a4) * wsp[t];
+    const float wa = w * a4;
+    uint32_t q[G];
+    float fx[G], fy[G];
+#pragma unroll
+    for (int v = 0; v < G; ++v) {
+      const float u = __builtin_fmaf(Hm[v][0], X, __builtin_fmaf(Hm[v][1], Y, Hm[v][2]));
+      const float vv = __builtin_fmaf(Hm[v][3], X, __builtin_fmaf(Hm[v][4], Y, Hm[v][5]));
+      const float ww = __builtin_fmaf(Hm[v][6], X, __builtin_fmaf(Hm[v][7], Y, Hm[v][8]));
+      const float r = EXACT ? 1.0f / ww : rcp_nr(ww);
+      const float up = CLAMP ? clampf(u * r, Wm1[v]) : u * r;
+      const float vp = CLAMP ? clampf(vv * r, Hm1[v]) : vv * r;
+      fx[v] = __builtin_amdgcn_fractf(up);
+      fy[v] = __builtin_amdgcn_fractf(vp);
+      const uint32_t x0 = (uint32_t)up, y0 = (uint32_t)vp;
+      q[v] = (uint32_t)struct_buffer_load_i32(rs[v], (int)(__umul24(y0, Wq[v]) + x0), 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < G; ++v) {
+      const float b = __builtin_fmaf(bilerp_scaled(q[v], fx[v], fy[v]), 0x1p24f, -bc[v]);
+      const float tb = w * b;
+      Sb[v] = Sb[v] + tb;
+      Sbb[v] = __builtin_fmaf(tb, b, Sbb[v]);
+      Sab[v] = __builtin_fmaf(wa, b, Sab[v]);
+    }
+  }
+#pragma unroll
+  for (int o = LANES / 2; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int v = 0; v < G; ++v) {
+      Sb[v] = Sb[v] + __shfl_xor(Sb[v], o);
+      Sbb[v] = Sbb[v] + __shfl_xor(Sbb[v], o);
+      Sab[v] = Sab[v] + __shfl_xor(Sab[v], o);
+    }
+  }
+}
+
 // Views J0 .. J0+G-1: build H_j = M_j + e_j m^T, apply the border rule at the window
 // corners, take the centre sample, run the tap pass and finish each view's ZNCC.
 // c[g] / ok[g] receive 1 - Z and the validity.
-template <int G, bool FR>
+template <int G, bool FR, int LANES>
 __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& rp, const Hyp& h,
                                            const float* __restrict__ tile, int TW, const float* __restrict__ wcol,
                                            const float* __restrict__ wsp, float (&c)[G], bool (&ok)[G]) {
@@ -431,7 +502,14 @@ __device__ __forceinline__ void view_group(const Args& A, int J0, const RefPix& 
   }
   if (__ballot(any_ok) == 0) return;
   float Sb[G], Sbb[G], Sab[G];
-  if (FR && A.frac) {
+  if constexpr (LANES > 1) {
+    if (__ballot(need_exact) != 0)
+      tap_pass_lanes<G, true, true, LANES>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+    else if (__ballot(need_clamp) != 0)
+      tap_pass_lanes<G, false, true, LANES>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+    else
+      tap_pass_lanes<G, false, false, LANES>(A, J0, rp, tile, TW, wcol, wsp, Hm, bc, Sb, Sbb, Sab);
+  } else if (FR && A.frac) {
     // the window-resize scheme: computed tap positions X0 + off[k] are monotone in k, so they
     // stay between the corners' and the bounds above hold for them as for integer spacing
     if (__ballot(need_exact) != 0)
@@ -478,7 +556,7 @@ __device__ __forceinline__ void topk_insert(float (&top)[kMaxTopK], float c) {
 // Cost (Eq. 5 over the best-K valid sources) of plane (n, d) at pixel rp.  Sources are
 // scored two at a time; per_view / valid (global, optional) receive 1 - Z and the flag of
 // each source.  FR: the job may use the window-resize scheme (A.frac decides).
-template <bool FR>
+template <bool FR, int LANES = 1>
 __device__ __forceinline__ float plane_cost(const Args& A, const RefPix& rp, const float* __restrict__ tile, int TW,
                             const float* __restrict__ wcol, const float* __restrict__ wsp, float nx, float ny,
                             float nz, float d, float* per_view, uint8_t* valid) {
@@ -505,11 +583,11 @@ __device__ __forceinline__ float plane_cost(const Args& A, const RefPix& rp, con
     const int gn = NV - j0 < 2 ? 1 : 2;
     if (any) {
       if (gn == 2) {
-        view_group<2, FR>(A, j0, rp, h, tile, TW, wcol, wsp, c, ok);
+        view_group<2, FR, LANES>(A, j0, rp, h, tile, TW, wcol, wsp, c, ok);
       } else {
         float c1[1];
         bool ok1[1];
-        view_group<1, FR>(A, j0, rp, h, tile, TW, wcol, wsp, c1, ok1);
+        view_group<1, FR, LANES>(A, j0, rp, h, tile, TW, wcol, wsp, c1, ok1);
         c[0] = c1[0];
         ok[0] = ok1[0];
       }
@@ -972,6 +1050,137 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
   }
 }
 
+// Small references, whose pixels alone do not fill the GPU: LANES lanes share each pixel,
+// its tap sums split as in tap_pass_lanes.  A workgroup covers 256 / LANES compacted pixels
+// of one row of one colour of job 0 (single-job launches); every lane of a pixel's group
+// scores the same hypotheses and reaches the same costs, and the group's first lane
+// writes.  Modes as in eval_tile; the reference-side sums stay sequential per pixel.
+template <int LANES>
+__global__ __launch_bounds__(kBlock) void eval_lanes_kernel(const Job* __restrict__ jobs, Launch L) {
+  __shared__ float wcol[256];
+  extern __shared__ float lds[];
+  const Job& J = jobs[0];
+  const Args& A = J.A;
+  constexpr int P = kBlock / LANES;
+  const int tiles_x = (A.Wc + P - 1) / P;
+  const int tile_y = (int)blockIdx.x / tiles_x, tile_x = (int)blockIdx.x - tile_y * tiles_x;
+  const int r = A.halo;
+  const int TW = 2 * P + 2 * r, TH = 1 + 2 * r;
+  float* wsp = lds;
+  float* tile_lds = wsp + A.n_taps;
+  const int x_org = tile_x * 2 * P - r, y_org = tile_y - r;
+  for (int i = threadIdx.x; i < 256; i += kBlock) wcol[i] = gl(A.wcol)[i];
+  for (int i = threadIdx.x; i < A.n_taps; i += kBlock) wsp[i] = gl(A.wsp)[i];
+  for (int i = threadIdx.x; i < TW * TH; i += kBlock) {
+    const int ty = i / TW, tx = i - ty * TW;
+    const int gx = min(max(x_org + tx, 0), A.W - 1);
+    const int gy = min(max(y_org + ty, 0), A.H - 1);
+    const unsigned short hb = gl(reinterpret_cast<const unsigned short*>(A.ref))[(size_t)gy * A.W + gx];
+    tile_lds[i] = 4.0f * __half2float(__ushort_as_half(hb));  // 4x the grey value, exact
+  }
+  __syncthreads();
+
+  const int slot = (int)threadIdx.x / LANES, g = (int)threadIdx.x % LANES;
+  const int lane = threadIdx.x & 63;
+  const int colour = L.colour;
+  const int y = tile_y;
+  const int ci = tile_x * P + slot;
+  const int par = (y + colour) & 1;
+  const int x = 2 * ci + par;
+  const bool in_img = y < A.H && ci < A.Wc && x < A.W;
+  const bool valid = in_img && pixel_valid(A, x, y);
+  RefPix rp;
+  rp.x = x;
+  rp.y = y;
+  rp.X0 = (float)x;
+  rp.Y0 = (float)y;
+  rp.ok = false;
+  rp.tbase = (r - A.s * A.R) * TW + 2 * slot + par + r - A.s * A.R;  // first tap (-R, -R)
+  rp.tox = x_org;
+  rp.toy = y_org;
+  ray_f(A, x, y, rp.rx, rp.ry, rp.rz);
+  rp.a_c = 0.0f;
+  rp.S_w = 1.0f;
+  rp.mu_a = 0.0f;
+  rp.var_a = 0.0f;
+  if (valid) {
+    rp.a_c = tile_lds[r * TW + 2 * slot + par + r];
+    float S_w = 0.0f, S_a4 = 0.0f, S_aa16 = 0.0f;
+    int t = 0;
+    for (int k2 = 0; k2 <= 2 * A.R; ++k2) {
+      const float* trow = tile_lds + rp.tbase + k2 * A.s * TW;
+      for (int k1 = 0; k1 <= 2 * A.R; ++k1, ++t) {
+        const float a4 = trow[k1 * A.s] - rp.a_c;
+        const float w = colour_weight<false>(wcol, a4) * wsp[t];
+        const float wa4 = w * a4;
+        S_w = S_w + w;
+        S_a4 = S_a4 + wa4;
+        S_aa16 = __builtin_fmaf(wa4, a4, S_aa16);
+      }
+    }
+    rp.S_w = S_w;
+    rp.mu_a = (S_a4 * 0.25f) / S_w;
+    rp.var_a = (S_aa16 * 0.0625f) / S_w - rp.mu_a * rp.mu_a;
+    rp.ok = rp.var_a >= A.eps_v;
+  }
+  const bool writer = g == 0;
+
+  if (L.mode == 2) {
+    if (in_img) {
+      const size_t p = (size_t)y * A.W + x;
+      float c = kCmax;
+      float* pv = J.per_view_out && writer ? J.per_view_out + p * A.n_src : nullptr;
+      uint8_t* vm = J.valid_out && writer ? J.valid_out + p * A.n_src : nullptr;
+      float4 pl = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (valid) pl = ld4(reinterpret_cast<const float4*>(J.planes_in), p);
+      const bool score = valid && !__builtin_isnan(pl.w);
+      const unsigned long long bal = __ballot(score && writer);
+      if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(bal));
+      if (score) {
+        c = plane_cost<false, LANES>(A, rp, tile_lds, TW, wcol, wsp, pl.x, pl.y, pl.z, pl.w, pv, vm);
+      } else {
+        for (int j = 0; j < A.n_src; ++j) {
+          if (pv) gl(pv)[j] = kCmax;
+          if (vm) gl(vm)[j] = 0;
+        }
+      }
+      if (writer) gl(J.cost_out)[p] = c;
+    }
+    return;
+  }
+
+  const size_t cidx = (size_t)y * A.Wc + ci;
+  const size_t plane_sz = (size_t)A.H * A.Wc;
+  float4 best = make_float4(0.f, 0.f, 0.f, 0.f);
+  float bc = kCmax;
+  if (L.mode == 1 && valid) {
+    best = ld4(A.plane[colour], cidx);
+    bc = gl(A.cost[colour])[cidx];
+  }
+  for (int k = 0; k < L.ncand; ++k) {
+    float4 h = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
+    if (valid) h = ld4(J.cand, k * plane_sz + cidx);
+    const bool has = valid && !__builtin_isnan(h.w);
+    if (__ballot(has) == 0) continue;
+    if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(__ballot(has && writer)));
+    if (has) {
+      const float c = plane_cost<false, LANES>(A, rp, tile_lds, TW, wcol, wsp, h.x, h.y, h.z, h.w, nullptr, nullptr);
+      const bool take = L.mode == 0 ? (k == 0 || c <= bc) : (c < bc);
+      if (take) {
+        bc = c;
+        best = h;
+      }
+    }
+  }
+  if (!in_img || (L.mode == 1 && !valid) || !writer) return;
+  if (!valid) {
+    best = make_float4(0.f, 0.f, 0.f, 0.f);
+    bc = kCmax;
+  }
+  st4(A.plane[colour], cidx, best);
+  gl(A.cost[colour])[cidx] = bc;
+}
+
 // ---------------------------------------------------------------------------- image preparation
 // 8-bit image -> fp16 copy (reference tiles) and 8-bit texel quads (bilinear gathers)
 __global__ void build_view_kernel(const uint8_t* __restrict__ img, int64_t stride, int W, int H,
@@ -1071,7 +1280,9 @@ hipError_t eval_lds_setup(size_t* max_dynamic) {
     return e;
   const size_t per_wg = std::min<size_t>((size_t)std::max(optin, per_cu), 160 * 1024);
   size_t lim = per_wg;
-  const void* fns[2] = {(const void*)pmk::eval_kernel<false>, (const void*)pmk::eval_kernel<true>};
+  const void* fns[6] = {(const void*)pmk::eval_kernel<false>,    (const void*)pmk::eval_kernel<true>,
+                        (const void*)pmk::eval_lanes_kernel<2>,  (const void*)pmk::eval_lanes_kernel<4>,
+                        (const void*)pmk::eval_lanes_kernel<8>,  (const void*)pmk::eval_lanes_kernel<16>};
   for (const void* fn : fns) {
     hipFuncAttributes a{};
     if ((e = hipFuncGetAttributes(&a, fn)) != hipSuccess) return e;
@@ -1091,6 +1302,27 @@ hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds,
   void* args[] = {(void*)&d_jobs, (void*)&l};
   const void* fn = L.frac ? (const void*)pmk::eval_kernel<true> : (const void*)pmk::eval_kernel<false>;
   return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, lds, st);
+}
+
+size_t eval_lanes_lds_bytes(int lanes, int radius_px, int n_taps) {
+  const int P = kBlock / lanes;
+  return sizeof(float) * ((size_t)n_taps + (size_t)(2 * P + 2 * radius_px) * (size_t)(1 + 2 * radius_px));
+}
+
+hipError_t launch_eval_lanes(const Job* d_jobs, const Launch& L, int lanes, int H, int Wc, size_t lds,
+                             hipStream_t st) {
+  const int P = kBlock / lanes;
+  const long long grid = (long long)H * ((Wc + P - 1) / P);
+  if (grid < 1 || grid > 0x7fffffff) return hipErrorInvalidValue;
+  Launch l = L;
+  void* args[] = {(void*)&d_jobs, (void*)&l};
+  const void* fn = lanes == 2 ? (const void*)pmk::eval_lanes_kernel<2>
+                   : lanes == 4 ? (const void*)pmk::eval_lanes_kernel<4>
+                   : lanes == 8 ? (const void*)pmk::eval_lanes_kernel<8>
+                   : lanes == 16 ? (const void*)pmk::eval_lanes_kernel<16>
+                                 : nullptr;
+  if (!fn) return hipErrorInvalidValue;
+  return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kBlock), args, lds, st);
 }
 
 hipError_t launch_candidates(int kind, const Job* d_jobs, const Launch& L, hipStream_t st) {
