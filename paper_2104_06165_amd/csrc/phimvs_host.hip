@@ -42,6 +42,7 @@ struct JobState {
   DevBuf<float4> plane[2];
   DevBuf<float> cost[2];
   DevBuf<float4> cand;
+  DevBuf<float4> hist;           // 2 colours x 8 candidates per pixel
   DevBuf<float> wcol, wsp;
 };
 
@@ -56,6 +57,8 @@ struct Batch {
   std::string layout_key;        // problems + tile shape the state was built for
   bool state_exact = false;      // every stored cost is the cost of its stored plane (the library's
                                  // own initialisation and steps keep this; phimvs_set_state does not)
+  bool hist_valid[2] = {false, false};  // hist[c] holds the last propagation launch of colour c since the
+                                        // state was initialised by the library (no phimvs_set_state since)
   // captured launch sequence
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -348,8 +351,10 @@ int setup_job(phimvs_ctx* c, const Problem& P, Job& J, JobState& S) {
     A.plane[k] = S.plane[k].p;
     A.cost[k] = S.cost[k].p;
   }
-  if ((rc = ensure(c, S.cand, 8 * ncol))) return rc;
+  if ((rc = ensure(c, S.cand, 8 * ncol)) || (rc = ensure(c, S.hist, 16 * ncol))) return rc;
   J.cand = S.cand.p;
+  J.hist[0] = S.hist.p;
+  J.hist[1] = S.hist.p + 8 * ncol;
   J.planes_in = nullptr;
   J.cost_out = J.per_view_out = nullptr;
   J.valid_out = nullptr;
@@ -469,6 +474,7 @@ int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack, bool with
   HIPCHECK(c, launch_zero(b.queues.p, 8 * n_eval, c->stream));
   int q = 0, rc;
   Launch L = base_launch(b);
+  b.hist_valid[0] = b.hist_valid[1] = false;
   for (int colour = 0; colour < 2; ++colour) {
     L.colour = colour;
     L.mode = 0;
@@ -484,12 +490,15 @@ int issue_sequence(phimvs_ctx* c, Batch& b, int iters, bool do_unpack, bool with
       L.iteration = it;
       L.mode = 1;
       L.ncand = 8;
+      L.hist_mode = it == 1 ? 1 : 2;
       HIPCHECK(c, launch_candidates(1, b.d_jobs, L, c->stream));
       if ((rc = run_eval(c, b, L, b.queues.p + 8 * q++))) return rc;
       L.ncand = 3;
+      L.hist_mode = 0;
       HIPCHECK(c, launch_candidates(2, b.d_jobs, L, c->stream));
       if ((rc = run_eval(c, b, L, b.queues.p + 8 * q++))) return rc;
     }
+  b.hist_valid[0] = b.hist_valid[1] = iters >= 1;
   if (do_unpack) HIPCHECK(c, launch_unpack(b.d_jobs, base_launch(b), c->stream));
   return PHIMVS_OK;
 }
@@ -775,6 +784,7 @@ int phimvs_prepare(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int wind
   J.depth_out = J.normal_out = J.final_cost_out = J.planes_out = nullptr;
   if ((rc = upload_jobs(c, b))) return rc;
   b.state_exact = false;
+  b.hist_valid[0] = b.hist_valid[1] = false;
   c->prepared = true;
   return PHIMVS_OK;
 }
@@ -805,6 +815,7 @@ int phimvs_init_planes(phimvs_ctx* c, const float* proposal, int on_device) {
     if ((rc = upload_jobs(c, b))) return rc;  // waits for the launches reading the proposal
   }
   b.state_exact = true;
+  b.hist_valid[0] = b.hist_valid[1] = false;
   return PHIMVS_OK;
 }
 
@@ -822,8 +833,12 @@ int phimvs_step(phimvs_ctx* c, int iteration, int colour, int do_propagate, int 
   L.skip_current = b.state_exact ? 1 : 0;
   if (do_propagate) {
     L.ncand = 8;
+    L.hist_mode = b.hist_valid[colour] ? 2 : 1;
+    b.hist_valid[colour] = false;  // until the selection that the recorded candidates went through is done
     HIPCHECK(c, launch_candidates(1, b.d_jobs, L, c->stream));
     if ((rc = eval_once(c, b, L))) return rc;
+    b.hist_valid[colour] = true;
+    L.hist_mode = 0;
   }
   if (do_refine) {
     L.ncand = 3;
@@ -881,6 +896,8 @@ int phimvs_set_state(phimvs_ctx* c, const float* planes, const float* cost, int 
   HIPCHECK(c, launch_pack(c->single.d_jobs, J.A.W, J.A.H, dp, dc, c->stream));
   if (!on_device) HIPCHECK(c, hipStreamSynchronize(c->stream));
   c->single.state_exact = false;  // the caller's costs need not be its planes' costs
+  // a cost the caller raised can make a candidate offered earlier win again
+  c->single.hist_valid[0] = c->single.hist_valid[1] = false;
   return PHIMVS_OK;
 }
 

@@ -54,6 +54,8 @@ struct Args {
 struct Job {
   Args A;
   float4* cand;            // candidate planes, slot-major: slot k at cand + k * H * Wc
+  float4* hist[2];         // per colour: the 8 candidates the last propagation launch of that colour
+                           // offered each pixel, slot-major like cand
   const float* planes_in;  // init: optional proposal; evaluation: planes to score (row-major H*W*4)
   float* cost_out;         // evaluation outputs (row-major)
   float* per_view_out;
@@ -81,6 +83,8 @@ struct Launch {
   int frac;                            // evaluate: some job uses the window-resize scheme
   int skip_current;                    // propagation candidates: drop those equal to the pixel's current
                                        // plane (only when every stored cost is its plane's own cost)
+  int hist_mode;                       // propagation candidates: 0 none; 1 record the candidates offered;
+                                       // 2 also drop those the previous launch of the colour offered
   unsigned int* queue;                 // 8 counters, zero at launch (persistent only)
   unsigned long long* count;           // optional: + (pixel, hypothesis) pairs scored
 };

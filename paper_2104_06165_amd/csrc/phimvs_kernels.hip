@@ -704,7 +704,12 @@ __device__ __forceinline__ bool same4(float4 a, float4 b) {
 // intersection; empty if the plane does not face p's ray or leaves the depth range.
 // A candidate bitwise equal to an earlier one, or (skip_current) to the pixel's current
 // plane, has that plane's cost, so under the strict-improvement rule it can never be
-// taken: it is left empty, which leaves the selection's result unchanged.
+// taken: it is left empty, which leaves the selection's result unchanged.  The same holds
+// for a candidate that the previous propagation launch of this colour offered the pixel
+// (hist_mode 2): that launch left the pixel's stored cost at or below the candidate's
+// cost (it was either not taken, or taken and the pixel's cost is its cost or lower), and a
+// stored cost only decreases afterwards, under the library's own steps.  hist_mode >= 1
+// records this launch's candidates, as computed, for the next launch of the colour.
 __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ jobs, Launch L) {
   int jb, x, y, ci;
   if (!cblk_pixel(jobs, L, jb, x, y, ci)) return;
@@ -719,7 +724,7 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
   float rx, ry, rz;
   ray_f(A, x, y, rx, ry, rz);
   const float4 cur = valid && L.skip_current ? ld4(A.plane[L.colour], cidx) : make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 prev[8];
+  float4 prev[8], fresh[8];
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
     float4 cand = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
@@ -762,6 +767,7 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
         if ((den < 0.0f) && (dn >= A.d_lo && dn <= A.d_hi)) cand = make_float4(q.x, q.y, q.z, dn);
       }
     }
+    fresh[g] = cand;
     if (!__builtin_isnan(cand.w)) {
       bool dup = L.skip_current && same4(cand, cur);
 #pragma unroll
@@ -769,8 +775,27 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
       if (dup) cand = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
     }
     prev[g] = cand;
-    st4(J.cand, g * plane_sz + cidx, cand);
   }
+  float4* hist = J.hist[L.colour];
+  if (valid && L.hist_mode == 2) {
+    float4 old[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) old[k] = ld4(hist, k * plane_sz + cidx);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      if (__builtin_isnan(prev[g].w)) continue;
+      bool seen = false;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) seen = seen || same4(prev[g], old[k]);
+      if (seen) prev[g] = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
+    }
+  }
+  if (valid && L.hist_mode >= 1) {
+#pragma unroll
+    for (int g = 0; g < 8; ++g) st4(hist, g * plane_sz + cidx, fresh[g]);
+  }
+#pragma unroll
+  for (int g = 0; g < 8; ++g) st4(J.cand, g * plane_sz + cidx, prev[g]);
 }
 
 // random refinement candidates (Sec. III-C): Delta_d in [-d_hi/4, d_hi/4], Delta_theta in

@@ -169,12 +169,18 @@ def test_halfsweep_parity_tiny(ctx, tiny):
 
 
 def test_halfsweep_after_a_state_whose_costs_are_not_its_planes(ctx, tiny):
-    """A propagation candidate equal to the pixel's current plane is left out only while
-    every stored cost is its plane's own cost (the library's own initialisation and
-    steps).  After set_state with every cost at C_max that no longer holds: such
-    candidates must be scored and taken, as the oracle does."""
+    """A propagation candidate equal to the pixel's current plane, or to one that the
+    previous propagation of its colour offered, is left out only while every stored cost
+    is its plane's own cost and no candidate offered earlier can beat it (the library's
+    own initialisation and steps).  After set_state with every cost at C_max neither
+    holds: such candidates must be scored and taken, as the oracle does.  The library's
+    own steps run first, so that both colours have a record of offered candidates that
+    set_state has to discard."""
     scene, cfg = tiny
     pb = _prep(ctx, scene, cfg)
+    ctx.init_planes()
+    ctx.step(1, 0)
+    ctx.step(1, 1)
     P, _ = oracle.init(pb)
     P, C = oracle.halfsweep(pb, P, oracle.eval_cost(pb, P)[0], 1, 0)
     P, C = oracle.halfsweep(pb, P, C, 1, 1)
@@ -194,6 +200,32 @@ def test_halfsweep_after_a_state_whose_costs_are_not_its_planes(ctx, tiny):
         # pixels whose current plane came back as a candidate were updated to its cost
         colour = (np.add.outer(np.arange(pb.H), np.arange(pb.W)) & 1) == col
         assert (C2[m & colour] < 2.0).mean() > 0.99
+
+
+def test_steps_match_the_whole_run(ctx, tiny):
+    """The library's own steps after init_planes, with a set_state of the library's own
+    state between two of them, give bitwise the whole run's result (the run issues the
+    same launches; set_state only switches off the exact skipping of candidates that
+    cannot win, which does not change any result)."""
+    scene, cfg = tiny
+    iters = 3
+    pb = _prep(ctx, scene, cfg)
+    d_run, _, c_run = ctx.patchmatch(0, list(range(1, len(scene.images))), cfg["window"], cfg["dilation"],
+                                     iters, params_for(cfg["window"], cfg["top_k"]))
+    d_run, c_run = d_run.clone(), c_run.clone()
+    _prep(ctx, scene, cfg)
+    ctx.init_planes()
+    for it in range(1, iters + 1):
+        for col in (0, 1):
+            ctx.step(it, col)
+            if (it, col) == (2, 0):
+                ctx.set_state(*ctx.get_state())
+    gp, gc = ctx.get_state()
+    m = torch.from_numpy(pb.valid_mask()).cuda()
+    same_d = (gp[..., 3] == d_run)[m].float().mean().item()
+    same_c = (gc == c_run)[m].float().mean().item()
+    say(f"steps vs whole run ({iters} iterations): depth bitwise {same_d:.6f}, cost bitwise {same_c:.6f}")
+    assert same_d == 1.0 and same_c == 1.0
 
 
 def test_patchmatch_parity_tiny(ctx, tiny):
