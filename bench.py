@@ -13,6 +13,7 @@ from the exact number of hypotheses scored) and the CPU oracle timed on a bounde
 sample of the same workload.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -683,6 +684,11 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2104_06165_amd", "weights", "proposal_net.npy"),
                     help="parameters of the proposal network for the learned-versus-random comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-versus-random comparison")
+    ap.add_argument("--score-all", type=int, default=0, choices=(0, 1, 2),
+                    help="0: leave out every propagation candidate that cannot win (default); 1: not those "
+                         "offered by the previous propagation of the colour; 2: score every candidate")
+    ap.add_argument("--no-skip-counts", action="store_true",
+                    help="do not count the hypotheses of the other score_all settings (extra untimed runs)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes sharing each pixel (2..16: split tap sums, for small references); 0: one lane")
     ap.add_argument("--tuning", default="", metavar="ROWS,PERSISTENT,WGS",
@@ -736,7 +742,7 @@ def main():
     n_src = len(scene.images) - 1
     srcs = list(range(1, n_src + 1))
     params = pm.Params(top_k=solver["top_k"], bilateral=True, sigma_spatial_px=(solver["window"] - 1) / 2.0,
-                       seed=sg.PM_SEED, lanes=args.lanes)
+                       seed=sg.PM_SEED, lanes=args.lanes, score_all=args.score_all)
     H, W = scene.images[0].shape
     out = (torch.empty((H, W), dtype=torch.float32, device="cuda"),
            torch.empty((H, W, 3), dtype=torch.float32, device="cuda"),
@@ -745,10 +751,20 @@ def main():
     def run():
         return ctx.patchmatch(0, srcs, solver["window"], solver["dilation"], solver["iters"], params, out=out)
 
-    # exact number of hypotheses scored per depth map (deterministic: counter-based RNG)
+    # exact number of hypotheses scored per depth map (deterministic: counter-based RNG), also
+    # with fewer of the candidates that cannot win left out (same results, more work)
     ctx.diag_enable(pm.DIAG_COUNT)
     run()
     n_hyp, _, _ = ctx.diag_read()
+    hyp_by_level = {}
+    for level in (0, 1, 2):
+        if level == args.score_all or args.no_skip_counts:
+            hyp_by_level[level] = n_hyp
+            continue
+        ctx.diag_enable(pm.DIAG_COUNT)  # resets the count
+        ctx.patchmatch(0, srcs, solver["window"], solver["dilation"], solver["iters"],
+                       dataclasses.replace(params, score_all=level), out=out)
+        hyp_by_level[level], _, _ = ctx.diag_read()
     ctx.diag_enable(0)
     for i in range(args.warmup):
         run()
@@ -827,6 +843,7 @@ def main():
                      "kernel_share_of_step": kernel_ms / (elapsed * 1e3)},
         "pcie_inclusive_ms": pcie_ms,
         "hypotheses_per_step": n_hyp,
+        "hypotheses_per_step_by_score_all": {str(k): v for k, v in sorted(hyp_by_level.items())},
         "cost_evals_per_s": n_hyp * n_src / (ms_per_step * 1e-3),
         "tap_views_per_s": n_hyp * n_src * taps / (ms_per_step * 1e-3),
         "quality": {"mean_cost": float(c[valid].mean()),

@@ -99,6 +99,13 @@ typedef struct {
                                result (it changes the FP32 rounding only).  Single-job calls only
                                (a batch job with lanes > 1, or combined with tap_radius > 0, fails
                                with PHIMVS_E_UNSUPPORTED) (default 0)                              */
+  int32_t score_all;        /* 0: propagation candidates that cannot win are left out unscored: one
+                               equal to an earlier candidate of the pixel, to its current plane, or to
+                               a candidate the previous propagation of its colour offered it (each has
+                               a cost no lower than the pixel's stored cost, and only a strictly lower
+                               cost is taken, so no result changes).  1: all but the last kind are left
+                               out.  2: every candidate is scored.  Results are bitwise the same under
+                               every setting; only the work differs (default 0)                     */
 } phimvs_params;
 
 void phimvs_default_params(phimvs_params* p);

@@ -56,7 +56,8 @@ class _Image(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("top_k", C.c_int32), ("bilateral", C.c_int32), ("sigma_spatial_px", C.c_double),
                 ("sigma_color", C.c_double), ("eps_var", C.c_double), ("eps_cost", C.c_double),
-                ("seed", C.c_uint64), ("tap_radius", C.c_int32), ("lanes", C.c_int32)]
+                ("seed", C.c_uint64), ("tap_radius", C.c_int32), ("lanes", C.c_int32),
+                ("score_all", C.c_int32)]
 
 
 class _Job(C.Structure):
@@ -126,11 +127,13 @@ class Params:
     seed: int = 0x5EED
     tap_radius: int = 0  # > 0: the window-resize scheme with this many taps per side
     lanes: int = 0  # 2..16: that many lanes share each pixel (split tap sums), for small references
+    score_all: int = 0  # 0: leave out candidates that cannot win; 1: not those offered before; 2: none
 
     def _c(self) -> _Params:
         return _Params(int(self.top_k), 1 if self.bilateral else 0, float(self.sigma_spatial_px),
                        float(self.sigma_color), float(self.eps_var), float(self.eps_cost),
-                       int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.tap_radius), int(self.lanes))
+                       int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.tap_radius), int(self.lanes),
+                       int(self.score_all))
 
 
 _lib = None
@@ -221,7 +224,7 @@ def default_params() -> Params:
     p = _Params()
     lib().phimvs_default_params(C.byref(p))
     return Params(p.top_k, bool(p.bilateral), p.sigma_spatial_px, p.sigma_color, p.eps_var, p.eps_cost, p.seed,
-                  p.tap_radius)
+                  p.tap_radius, p.lanes, p.score_all)
 
 
 def _dptr(t) -> Optional[int]:

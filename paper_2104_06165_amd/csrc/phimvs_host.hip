@@ -218,7 +218,8 @@ std::string problem_key(const Problem& P) {
                   std::to_string(P.p.top_k) + "," + std::to_string(P.p.bilateral) + "," + std::to_string(P.p.seed) +
                   "," + std::to_string(P.p.sigma_color) + "," + std::to_string(P.p.sigma_spatial_px) + "," +
                   std::to_string(P.p.eps_var) + "," + std::to_string(P.p.eps_cost) + "," +
-                  std::to_string(P.p.tap_radius) + "," + std::to_string(P.p.lanes);
+                  std::to_string(P.p.tap_radius) + "," + std::to_string(P.p.lanes) + "," +
+                  std::to_string(P.p.score_all);
   for (int s : P.srcs) k += ";" + std::to_string(s);
   return k;
 }
@@ -252,6 +253,7 @@ int validate_problem(phimvs_ctx* c, const Problem& P) {
   }
   if (p.lanes < 0 || p.lanes > 16 || (p.lanes & (p.lanes - 1)))
     return fail(c, PHIMVS_E_ARG, "lanes must be 0, 1, 2, 4, 8 or 16");
+  if (p.score_all < 0 || p.score_all > 2) return fail(c, PHIMVS_E_ARG, "score_all must be 0, 1 or 2");
   if (p.lanes > 1 && p.tap_radius > 0)
     return fail(c, PHIMVS_E_UNSUPPORTED, "lanes > 1 with the window-resize scheme");
   const int n = (int)P.srcs.size();
@@ -290,6 +292,7 @@ int setup_job(phimvs_ctx* c, const Problem& P, Job& J, JobState& S) {
   A.bilateral = p.bilateral ? 1 : 0;
   A.n_taps = (2 * R + 1) * (2 * R + 1);
   A.lanes = p.lanes > 1 ? p.lanes : 1;
+  A.score_all = p.score_all;
   double K0i[9];
   inv33(V0.K, K0i);
   for (int i = 0; i < 9; ++i) {
@@ -630,6 +633,7 @@ void phimvs_default_params(phimvs_params* p) {
   p->seed = 0x5EED;
   p->tap_radius = 0;
   p->lanes = 0;
+  p->score_all = 0;
 }
 
 int phimvs_create(phimvs_ctx** out, int device_ordinal, void* hip_stream) {

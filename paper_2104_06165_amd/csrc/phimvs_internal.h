@@ -37,6 +37,9 @@ struct Args {
   int rv;                  // validity radius: a pixel is valid when its window (x +- rv) is inside
   int halo;                // reference-tile halo in pixels
   int lanes;               // lanes sharing a pixel (1, or 2..16: split tap sums, single-job launches)
+  int score_all;           // propagation candidates left out when they cannot win: 0 all such (equal
+                           // to an earlier one, to the current plane, or to one the previous launch of
+                           // the colour offered); 1 not the last kind; 2 none
   float off[kMaxTaps1D];   // tap offsets k = 0 .. 2R: s (k - R), in FP32
   float Kinv[9];
   double Kinv_d[9];

@@ -723,7 +723,10 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
   const GLOBAL float* __restrict__ ocost = gl(A.cost[oc]);
   float rx, ry, rz;
   ray_f(A, x, y, rx, ry, rz);
-  const float4 cur = valid && L.skip_current ? ld4(A.plane[L.colour], cidx) : make_float4(0.f, 0.f, 0.f, 0.f);
+  const bool skip_dup = A.score_all < 2;
+  const bool skip_cur = skip_dup && L.skip_current;
+  const int hist_mode = A.score_all == 0 ? L.hist_mode : 0;
+  const float4 cur = valid && skip_cur ? ld4(A.plane[L.colour], cidx) : make_float4(0.f, 0.f, 0.f, 0.f);
   float4 prev[8], fresh[8];
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
@@ -768,8 +771,8 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
       }
     }
     fresh[g] = cand;
-    if (!__builtin_isnan(cand.w)) {
-      bool dup = L.skip_current && same4(cand, cur);
+    if (skip_dup && !__builtin_isnan(cand.w)) {
+      bool dup = skip_cur && same4(cand, cur);
 #pragma unroll
       for (int j = 0; j < g; ++j) dup = dup || same4(cand, prev[j]);
       if (dup) cand = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
@@ -777,7 +780,7 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
     prev[g] = cand;
   }
   float4* hist = J.hist[L.colour];
-  if (valid && L.hist_mode == 2) {
+  if (valid && hist_mode == 2) {
     float4 old[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) old[k] = ld4(hist, k * plane_sz + cidx);
@@ -790,7 +793,7 @@ __global__ __launch_bounds__(128) void cand_prop_kernel(const Job* __restrict__ 
       if (seen) prev[g] = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
     }
   }
-  if (valid && L.hist_mode >= 1) {
+  if (valid && hist_mode >= 1) {
 #pragma unroll
     for (int g = 0; g < 8; ++g) st4(hist, g * plane_sz + cidx, fresh[g]);
   }

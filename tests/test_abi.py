@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_params_and_null_context_errors():
     p = pm.default_params()
     assert p.top_k == 0 and p.bilateral and p.sigma_color == 12.0 and p.eps_var == 1e-4 and p.seed == 0x5EED
-    assert p.tap_radius == 0
+    assert p.tap_radius == 0 and p.lanes == 0 and p.score_all == 0
     L = pm.lib()
     # calls on a null context fail with PHIMVS_E_ARG instead of crashing
     assert L.phimvs_prepare(None, 0, None, 0, 7, 1, None) == -1
@@ -52,3 +52,24 @@ def test_default_params_and_null_context_errors():
     assert L.phimvs_net_adam(None, 1e-3, 0.9, 0.999, 1e-8) == -1
     assert L.phimvs_net_last_error(None) == b"null network"
     assert L.phimvs_net_create(ctypes.byref(out), -1, None) == -3
+
+
+def test_params_layout_matches_the_header(tmp_path):
+    """The binding's phimvs_params mirrors the header's struct field by field (offsets
+    and size as the C compiler lays them out)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in pm._Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"phimvs.h\"\nint main(void) {\n"
+                   "  printf(\"%zu\\n\", sizeof(phimvs_params));\n" +
+                   "".join(f"  printf(\"%zu\\n\", offsetof(phimvs_params, {f}));\n" for f in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(pm._Params)
+    assert got[1:] == [getattr(pm._Params, f).offset for f in fields]

@@ -160,3 +160,22 @@ def test_batch_argument_errors(ctx, mv):
         ctx.set_tuning(pm.Tuning(3, False, 0))
     with pytest.raises(pm.PhimvsError):
         ctx.set_tuning(pm.Tuning(4, True, 0))
+
+
+def test_batch_with_mixed_candidate_skipping(ctx, mv):
+    """Jobs of one batch may leave out different kinds of candidates that cannot win
+    (phimvs_params.score_all 0, 1, 2): each job's result is still bitwise its single run
+    with every such candidate left out."""
+    iters = 3
+    jobs = jobs_of(mv)
+    ctx.set_tuning(pm.Tuning(4, False, 0))
+    ref = single_runs(ctx, jobs, iters)
+    mixed = []
+    for i, j in enumerate(jobs):
+        p = j["params"]
+        mixed.append(dict(j, params=pm.Params(top_k=p.top_k, seed=p.seed, score_all=i % 3)))
+    outs = ctx.patchmatch_batch(mixed, iters, use_graph=False)
+    torch.cuda.synchronize()
+    for i, ((d, n, c), (rd, rn, rc)) in enumerate(zip(outs, ref)):
+        assert torch.equal(d, rd) and torch.equal(n, rn) and torch.equal(c, rc), f"job {i} (score_all {i % 3})"
+    say(f"{len(jobs)} jobs with score_all 0/1/2 mixed: bitwise equal to their single runs")
