@@ -166,7 +166,7 @@ def bench_batched(args):
         best, allr = ctx.get_tuning(), []
         log(f"[bench] launch configuration fixed: rows{rows}/p{persistent}/{wgs}")
     else:
-        best, allr = ctx.autotune(jobs, iters=1)
+        best, allr = ctx.autotune(jobs, iters=args.autotune_iters)
         log("[bench] autotune: " + ", ".join(f"rows{r.tile_rows}/p{int(r.persistent)}/{r.wgs_per_cu}={r.ms:.1f}ms"
                                              for r in allr))
     outs = [dict(depth=torch.empty(mv.images[j["ref"]].shape, dtype=torch.float32, device="cuda"),
@@ -687,12 +687,15 @@ def main():
     ap.add_argument("--score-all", type=int, default=0, choices=(0, 1, 2),
                     help="0: leave out every propagation candidate that cannot win (default); 1: not those "
                          "offered by the previous propagation of the colour; 2: score every candidate")
+    ap.add_argument("--autotune-iters", type=int, default=3,
+                    help="batched workload: iterations per autotuner trial (from the second on, the "
+                         "propagation launches leave out candidates offered before, as in a full run)")
     ap.add_argument("--no-skip-counts", action="store_true",
                     help="do not count the hypotheses of the other score_all settings (extra untimed runs)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes sharing each pixel (2..16: split tap sums, for small references); 0: one lane")
     ap.add_argument("--tuning", default="", metavar="ROWS,PERSISTENT,WGS",
-                    help="batched workload: use this launch configuration instead of autotuning")
+                    help="evaluate-kernel launch configuration (batched workload: instead of autotuning)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration) and exit")
     args = ap.parse_args()
@@ -739,6 +742,9 @@ def main():
 
     ctx = pm.Context(0)
     ctx.set_scene(scene)
+    if args.tuning:
+        rows, persistent, wgs = (int(v) for v in args.tuning.split(","))
+        ctx.set_tuning(pm.Tuning(rows, bool(persistent), wgs))
     n_src = len(scene.images) - 1
     srcs = list(range(1, n_src + 1))
     params = pm.Params(top_k=solver["top_k"], bilateral=True, sigma_spatial_px=(solver["window"] - 1) / 2.0,
@@ -830,7 +836,8 @@ def main():
                    "width": W, "height": H, "n_src": n_src, "window": solver["window"],
                    "dilation": solver["dilation"], "top_k": solver["top_k"], "iters": solver["iters"],
                    "planes": cfg.n_planes, "images": "8-bit texel quads (sources), fp16 copy (reference) in HBM",
-                   "cost": "fp32", "lanes_per_pixel": max(1, args.lanes)},
+                   "cost": "fp32", "lanes_per_pixel": max(1, args.lanes),
+                   "tuning": ctx.get_tuning().__dict__},
         "ms_per_step_min": min(step_ms),
         "ms_per_step_median": float(np.median(step_ms)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",

@@ -196,7 +196,8 @@ int phimvs_patchmatch_batch(phimvs_ctx* ctx, int n_jobs, const phimvs_job* jobs,
 /* Launch configuration of the evaluate-and-select kernel: tile_rows (4, 2 or 1) rows of
  * 256 / tile_rows same-colour pixels per workgroup; persistent != 0 runs a fixed grid
  * of wgs_per_cu workgroups per compute unit pulling tiles from per-XCD queues, else
- * one workgroup per tile.  ms is the time measured by phimvs_autotune. */
+ * one workgroup per tile.  ms is the time measured by phimvs_autotune.  A new context
+ * starts with tile_rows 4, persistent, 4 workgroups per compute unit. */
 typedef struct {
   int32_t tile_rows;
   int32_t persistent;

@@ -78,7 +78,7 @@ struct phimvs_ctx {
   bool prepared = false;
   Batch single;                   // the step-wise interface's job
   Batch multi;                    // phimvs_patchmatch_batch
-  phimvs_tuning tuning{4, 0, 0, 0.0};
+  phimvs_tuning tuning{4, 1, 4, 0.0};  // persistent, 4 workgroups per CU (the occupancy limit)
   size_t eval_lds_max = 0;                // largest dynamic LDS of an evaluate launch on this device
   DevBuf<float> io_a, io_b, io_c, io_d;  // staging for host inputs / outputs
   DevBuf<FilterNbr> filter_nbrs;          // neighbour table of the consistency filter
