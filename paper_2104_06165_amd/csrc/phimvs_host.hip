@@ -64,6 +64,7 @@ struct Batch {
   hipGraphExec_t exec = nullptr;
   std::string graph_key;
   DevBuf<unsigned int> queues;   // 8 counters per evaluate launch
+  std::vector<unsigned char> uploaded;  // bytes of the table last copied to d_jobs
 };
 
 }  // namespace
@@ -138,23 +139,32 @@ void release_graph(Batch& b) {
   b.graph_key.clear();
 }
 
+void release_state(JobState& s) {
+  for (int k = 0; k < 2; ++k) {
+    release(s.plane[k]);
+    release(s.cost[k]);
+  }
+  release(s.cand);
+  release(s.hist);
+  release(s.wcol);
+  release(s.wsp);
+}
+
+// n job slots, freeing the device state of the slots dropped
+void resize_jobs(Batch& b, size_t n) {
+  for (size_t i = n; i < b.state.size(); ++i) release_state(b.state[i]);
+  b.state.resize(n);
+  b.jobs.resize(n);
+}
+
 void release_batch(Batch& b) {
   release_graph(b);
-  for (auto& s : b.state) {
-    for (int k = 0; k < 2; ++k) {
-      release(s.plane[k]);
-      release(s.cost[k]);
-    }
-    release(s.cand);
-    release(s.wcol);
-    release(s.wsp);
-  }
-  b.state.clear();
-  b.jobs.clear();
+  resize_jobs(b, 0);
   b.layout_key.clear();
   if (b.d_jobs) (void)hipFree(b.d_jobs);
   b.d_jobs = nullptr;
   b.d_cap = 0;
+  b.uploaded.clear();
   release(b.queues);
 }
 
@@ -404,15 +414,21 @@ void layout(Batch& b, int tile_rows) {
 
 int upload_jobs(phimvs_ctx* c, Batch& b) {
   const size_t bytes = b.jobs.size() * sizeof(Job);
+  const unsigned char* host = reinterpret_cast<const unsigned char*>(b.jobs.data());
+  // the device already holds this table: nothing to copy and no queued work to wait for
+  if (b.d_jobs && b.uploaded.size() == bytes && std::memcmp(b.uploaded.data(), host, bytes) == 0)
+    return PHIMVS_OK;
   if (b.d_cap < bytes) {
     if (b.d_jobs) HIPCHECK(c, hipFree(b.d_jobs));
     b.d_jobs = nullptr;
+    b.uploaded.clear();
     HIPCHECK(c, hipMalloc((void**)&b.d_jobs, bytes));
     b.d_cap = bytes;
   }
   // the table is read by work already queued: wait for it before overwriting
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   HIPCHECK(c, hipMemcpy(b.d_jobs, b.jobs.data(), bytes, hipMemcpyHostToDevice));
+  b.uploaded.assign(host, host + bytes);
   return PHIMVS_OK;
 }
 
@@ -547,12 +563,89 @@ Problem make_problem(int ref, const int* srcs, int n_srcs, int window, int dilat
 
 // one depth map through the single-job batch: prepare, then the whole launch sequence;
 // proposal (planes layout, optional) gates the random initialisation
+// the single-view problem: device state (kept when the problem is unchanged) and the job
+// table with no outputs; upload: copy the table to the device now (else the caller does,
+// after setting the outputs)
+int prepare_single(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, int dilation,
+                   const phimvs_params* pp, bool upload) {
+  if (!c) return PHIMVS_E_ARG;
+  c->prepared = false;
+  if (n_srcs < 0 || (n_srcs > 0 && !srcs)) return fail(c, PHIMVS_E_ARG, "need at least one source view");
+  Problem P = make_problem(ref, srcs, n_srcs, window, dilation, pp);
+  int rc = validate_problem(c, P);
+  if (rc) return rc;
+  HIPCHECK(c, hipSetDevice(c->device));
+  Batch& b = c->single;
+  const std::string key = problem_key(P) + "@" + std::to_string(c->tuning.tile_rows);
+  if (key != b.layout_key || b.jobs.size() != 1) {
+    release_graph(b);
+    resize_jobs(b, 1);
+    if ((rc = setup_job(c, P, b.jobs[0], b.state[0]))) return rc;
+    layout(b, c->tuning.tile_rows);
+    b.layout_key = key;
+  }
+  Job& J = b.jobs[0];
+  J.planes_in = nullptr;
+  J.cost_out = J.per_view_out = nullptr;
+  J.valid_out = nullptr;
+  J.depth_out = J.normal_out = J.final_cost_out = J.planes_out = nullptr;
+  if (upload && (rc = upload_jobs(c, b))) return rc;
+  b.state_exact = false;
+  b.hist_valid[0] = b.hist_valid[1] = false;
+  c->prepared = true;
+  return PHIMVS_OK;
+}
+
+// after the sequence has been issued (or its graph launched): what it leaves in the state
+void sequence_done(Batch& b, int iters) {
+  b.state_exact = true;
+  b.hist_valid[0] = b.hist_valid[1] = iters >= 1;
+}
+
+// The iteration sequence through a hipGraph: recorded once per gkey (which names
+// everything the recorded launches hold: geometry, iterations, launch configuration,
+// buffers), replayed on later calls.  The job table is read at run time, so its outputs may
+// change between replays.
+int run_sequence_graph(phimvs_ctx* c, Batch& b, const std::string& gkey, int iters) {
+  int rc;
+  if (b.exec && b.graph_key == gkey) {
+    HIPCHECK(c, hipGraphLaunch(b.exec, c->stream));
+    sequence_done(b, iters);
+    return PHIMVS_OK;
+  }
+  release_graph(b);
+  // record on a private stream (the caller's may be the null stream, which cannot be
+  // captured); the graph is then launched on the caller's stream, after its prior work
+  if (!c->capture_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  hipStream_t user = c->stream;
+  c->stream = c->capture_stream;
+  hipError_t eb = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) {
+    c->stream = user;
+    return fail(c, PHIMVS_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
+  }
+  rc = issue_sequence(c, b, iters, true);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+  c->stream = user;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  HIPCHECK(c, ec);
+  b.graph = g;
+  HIPCHECK(c, hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+  b.graph_key = gkey;
+  HIPCHECK(c, hipGraphLaunch(b.exec, c->stream));
+  return PHIMVS_OK;
+}
+
 int run_single(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, int dilation, int iters,
                const phimvs_params* p, const float* proposal, float* depth, float* normal, float* cost,
                int on_device) {
   if (!c) return PHIMVS_E_ARG;
   if (iters < 0) return fail(c, PHIMVS_E_ARG, "iters must be >= 0");
-  int rc = phimvs_prepare(c, ref, srcs, n_srcs, window, dilation, p);
+  int rc = prepare_single(c, ref, srcs, n_srcs, window, dilation, p, false);
   if (rc) return rc;
   Batch& b = c->single;
   Job& J = b.jobs[0];
@@ -578,12 +671,23 @@ int run_single(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, 
     J.final_cost_out = cost ? c->io_c.p : nullptr;
   }
   J.planes_in = prop;
-  // the table is complete before the sequence starts, so the call does not wait for it
+  // the table is complete before the sequence starts (unchanged from the last call: not
+  // copied again, and nothing waited for)
   rc = upload_jobs(c, b);
   J.planes_in = nullptr;  // the next upload drops the caller's pointer
   if (rc) return rc;
   if ((rc = ensure(c, b.queues, (size_t)8 * (2 + 4 * iters)))) return rc;
-  if ((rc = issue_sequence(c, b, iters, true, prop != nullptr))) return rc;
+  if (prop || c->diag) {
+    rc = issue_sequence(c, b, iters, true, prop != nullptr);
+  } else {
+    char ptrs[64];
+    std::snprintf(ptrs, sizeof ptrs, "#%p#%p", (void*)b.d_jobs, (void*)b.queues.p);
+    const std::string gkey = b.layout_key + "#" + std::to_string(iters) + "#" +
+                             std::to_string(c->tuning.persistent) + "#" + std::to_string(c->tuning.wgs_per_cu) +
+                             ptrs;
+    rc = run_sequence_graph(c, b, gkey, iters);
+  }
+  if (rc) return rc;
   if (!on_device) {
     if (normal) HIPCHECK(c, hipMemcpyAsync(normal, c->io_a.p, 3 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     if (depth) HIPCHECK(c, hipMemcpyAsync(depth, c->io_b.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
@@ -764,33 +868,7 @@ int phimvs_set_views(phimvs_ctx* c, int n_views, const phimvs_image* images, con
 
 int phimvs_prepare(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, int dilation,
                    const phimvs_params* pp) {
-  if (!c) return PHIMVS_E_ARG;
-  c->prepared = false;
-  if (n_srcs < 0 || (n_srcs > 0 && !srcs)) return fail(c, PHIMVS_E_ARG, "need at least one source view");
-  Problem P = make_problem(ref, srcs, n_srcs, window, dilation, pp);
-  int rc = validate_problem(c, P);
-  if (rc) return rc;
-  HIPCHECK(c, hipSetDevice(c->device));
-  Batch& b = c->single;
-  const std::string key = problem_key(P) + "@" + std::to_string(c->tuning.tile_rows);
-  if (key != b.layout_key || b.jobs.size() != 1) {
-    release_graph(b);
-    b.jobs.resize(1);
-    b.state.resize(1);
-    if ((rc = setup_job(c, P, b.jobs[0], b.state[0]))) return rc;
-    layout(b, c->tuning.tile_rows);
-    b.layout_key = key;
-  }
-  Job& J = b.jobs[0];
-  J.planes_in = nullptr;
-  J.cost_out = J.per_view_out = nullptr;
-  J.valid_out = nullptr;
-  J.depth_out = J.normal_out = J.final_cost_out = J.planes_out = nullptr;
-  if ((rc = upload_jobs(c, b))) return rc;
-  b.state_exact = false;
-  b.hist_valid[0] = b.hist_valid[1] = false;
-  c->prepared = true;
-  return PHIMVS_OK;
+  return prepare_single(c, ref, srcs, n_srcs, window, dilation, pp, true);
 }
 
 int phimvs_init_planes(phimvs_ctx* c, const float* proposal, int on_device) {
@@ -1239,8 +1317,7 @@ int phimvs_patchmatch_batch(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, i
   int rc;
   if (key != b.layout_key) {
     release_graph(b);
-    b.jobs.resize(n_jobs);
-    b.state.resize(n_jobs);
+    resize_jobs(b, (size_t)n_jobs);
     for (int i = 0; i < n_jobs; ++i)
       if ((rc = setup_job(c, probs[i], b.jobs[i], b.state[i]))) return rc;
     layout(b, c->tuning.tile_rows);
@@ -1262,35 +1339,7 @@ int phimvs_patchmatch_batch(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, i
   const std::string gkey = key + "#" + std::to_string(iters) + "#" + std::to_string(c->tuning.persistent) + "#" +
                            std::to_string(c->tuning.wgs_per_cu);
   if (!use_graph || c->diag) return issue_sequence(c, b, iters, true);
-  if (b.exec && b.graph_key == gkey) {
-    HIPCHECK(c, hipGraphLaunch(b.exec, c->stream));
-    return PHIMVS_OK;
-  }
-  release_graph(b);
-  // record on a private stream (the caller's may be the null stream, which cannot be
-  // captured); the graph is then launched on the caller's stream, after its prior work
-  if (!c->capture_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
-  hipStream_t user = c->stream;
-  c->stream = c->capture_stream;
-  hipError_t eb = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
-  if (eb != hipSuccess) {
-    c->stream = user;
-    return fail(c, PHIMVS_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
-  }
-  rc = issue_sequence(c, b, iters, true);
-  hipGraph_t g = nullptr;
-  const hipError_t ec = hipStreamEndCapture(c->stream, &g);
-  c->stream = user;
-  if (rc) {
-    if (g) (void)hipGraphDestroy(g);
-    return rc;
-  }
-  HIPCHECK(c, ec);
-  b.graph = g;
-  HIPCHECK(c, hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
-  b.graph_key = gkey;
-  HIPCHECK(c, hipGraphLaunch(b.exec, c->stream));
-  return PHIMVS_OK;
+  return run_sequence_graph(c, b, gkey, iters);
 }
 
 int phimvs_set_tuning(phimvs_ctx* c, const phimvs_tuning* t) {

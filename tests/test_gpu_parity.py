@@ -228,6 +228,45 @@ def test_steps_match_the_whole_run(ctx, tiny):
     assert same_d == 1.0 and same_c == 1.0
 
 
+def test_repeated_runs_replay_the_eager_result(ctx, tiny):
+    """A single-view run is recorded into a hipGraph on its first call and replayed on
+    later ones (the job table, which holds the outputs, is read at run time).  Each replay,
+    with other eager work and synchronisations between them and with new output tensors on
+    one of them, gives bitwise the result of the eager sequence (diagnostics on: eager)."""
+    scene, cfg = tiny
+    ctx.set_scene(scene)
+    srcs = list(range(1, len(scene.images)))
+    prm = params_for(cfg["window"], cfg["top_k"])
+    ctx.diag_enable(pm.DIAG_COUNT)
+    ref = [t.clone() for t in ctx.patchmatch(0, srcs, cfg["window"], cfg["dilation"], cfg["iters"], prm)]
+    ctx.diag_enable(0)
+    out = tuple(torch.full_like(t, -1.0) for t in ref)
+    for rep in range(4):
+        if rep == 2:
+            out = tuple(torch.full_like(t, -1.0) for t in ref)  # outputs move: the table is copied again
+        got = ctx.patchmatch(0, srcs, cfg["window"], cfg["dilation"], cfg["iters"], prm, out=out)
+        torch.cuda.synchronize()
+        same = all(torch.equal(a, b) for a, b in zip(got, ref))
+        say(f"run {rep + 1} after the eager one: bitwise {same}")
+        assert same
+        # eager work of the program's own between the replays
+        ctx.eval_cost(torch.zeros((scene.images[0].shape[0], scene.images[0].shape[1], 4), device="cuda"))
+        for t in out:
+            t.fill_(-1.0)
+        torch.cuda.synchronize()
+    # the state a replay leaves behind serves the next steps as the eager run's does
+    _prep(ctx, scene, cfg)
+    ctx.patchmatch(0, srcs, cfg["window"], cfg["dilation"], cfg["iters"], prm, out=out)
+    ctx.step(cfg["iters"] + 1, 0)
+    gp, gc = ctx.get_state()
+    ctx.diag_enable(pm.DIAG_COUNT)
+    ctx.patchmatch(0, srcs, cfg["window"], cfg["dilation"], cfg["iters"], prm, out=out)
+    ctx.diag_enable(0)
+    ctx.step(cfg["iters"] + 1, 0)
+    ep, ec = ctx.get_state()
+    assert torch.equal(gp, ep) and torch.equal(gc, ec)
+
+
 def test_patchmatch_parity_tiny(ctx, tiny):
     scene, cfg = tiny
     pb = _prep(ctx, scene, cfg)
