@@ -561,8 +561,6 @@ Problem make_problem(int ref, const int* srcs, int n_srcs, int window, int dilat
   return P;
 }
 
-// one depth map through the single-job batch: prepare, then the whole launch sequence;
-// proposal (planes layout, optional) gates the random initialisation
 // the single-view problem: device state (kept when the problem is unchanged) and the job
 // table with no outputs; upload: copy the table to the device now (else the caller does,
 // after setting the outputs)
@@ -640,6 +638,9 @@ int run_sequence_graph(phimvs_ctx* c, Batch& b, const std::string& gkey, int ite
   return PHIMVS_OK;
 }
 
+// one depth map through the single-job batch: prepare, then the whole launch sequence
+// (replayed from a graph when there is no proposal); proposal (planes layout, optional)
+// gates the random initialisation
 int run_single(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, int dilation, int iters,
                const phimvs_params* p, const float* proposal, float* depth, float* normal, float* cost,
                int on_device) {
