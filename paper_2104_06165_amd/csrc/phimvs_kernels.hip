@@ -1190,7 +1190,9 @@ __global__ __launch_bounds__(kBlock) void eval_lanes_kernel(const Job* __restric
     if (valid) h = ld4(J.cand, k * plane_sz + cidx);
     const bool has = valid && !__builtin_isnan(h.w);
     if (__ballot(has) == 0) continue;
-    if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(__ballot(has && writer)));
+    // the ballot over the whole wave, before only its first lane goes on to count
+    const unsigned long long scored = __ballot(has && writer);
+    if (L.count && lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(scored));
     if (has) {
       const float c = plane_cost<false, LANES>(A, rp, tile_lds, TW, wcol, wsp, h.x, h.y, h.z, h.w, nullptr, nullptr);
       const bool take = L.mode == 0 ? (k == 0 || c <= bc) : (c < bc);

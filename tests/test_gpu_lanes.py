@@ -82,6 +82,34 @@ def test_teacher_forced_stages(ctx, tiny, lanes):
     assert pb_ >= FRAC and cb >= FRAC
 
 
+@pytest.mark.parametrize("lanes", [2, 16])
+def test_hypothesis_count_matches_one_lane(ctx, tiny, lanes):
+    """The diagnostic count of scored (pixel, hypothesis) pairs is the same whether one
+    lane or G lanes score each pixel: from the same state the candidate kernels offer the
+    same candidates (an initialisation, then a half-sweep from the oracle's state)."""
+    scene, cfg = tiny
+    win, dil, K = cfg["window"], cfg["dilation"], cfg["top_k"]
+    ctx.set_scene(scene)
+    srcs = list(range(1, len(scene.images)))
+    pb = problem(scene, win, dil, K, 0)
+    P, C = oracle.init(pb)
+    counts = {}
+    for g in (0, lanes):
+        ctx.prepare(0, srcs, win, dil, params(win, K, g))
+        ctx.diag_enable(pm.DIAG_COUNT)
+        ctx.init_planes()
+        n_init, _, _ = ctx.diag_read()
+        ctx.set_state(torch.tensor(P, dtype=torch.float32, device="cuda"),
+                      torch.tensor(C, dtype=torch.float32, device="cuda"))
+        ctx.diag_enable(pm.DIAG_COUNT)
+        ctx.step(1, 0)
+        n_step, _, _ = ctx.diag_read()
+        ctx.diag_enable(0)
+        counts[g] = (n_init, n_step)
+    say(f"G={lanes}: scored pairs (initialisation, half-sweep) {counts[lanes]}, one lane {counts[0]}")
+    assert counts[lanes] == counts[0] and counts[0][1] > counts[0][0] > 0
+
+
 @pytest.mark.parametrize("lanes", [4, 16])
 def test_tiny_run(ctx, tiny, lanes):
     scene, cfg = tiny

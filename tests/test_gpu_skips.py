@@ -4,7 +4,8 @@ current plane, or to a candidate that the previous propagation of the pixel's co
 offered it has a cost no lower than the pixel's stored cost; only a strictly lower cost
 is taken.  On the 3200x2130 workload (10 sources, 11x11 taps, 8 iterations) the three
 settings give bitwise the same depth, normal and cost at every pixel, while the number
-of hypotheses scored falls (reported, and asserted to fall at each step)."""
+of hypotheses scored falls (reported, and asserted to fall at each step); so do they on
+the 160x120 workload, with one lane per pixel and with 16 lanes sharing each pixel."""
 import sys
 
 import pytest
@@ -25,8 +26,8 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("workload", ["tiny", "highres"])
-def test_skipping_changes_no_result(workload):
+@pytest.mark.parametrize("workload,lanes", [("tiny", 0), ("tiny", 16), ("highres", 0)])
+def test_skipping_changes_no_result(workload, lanes):
     scene = sg.workload_scene(workload, device="cuda")
     sol = sg.SOLVER[workload]
     ctx = pm.Context(0)
@@ -36,14 +37,14 @@ def test_skipping_changes_no_result(workload):
         res, hyps = [], []
         for level in (2, 1, 0):
             p = pm.Params(top_k=sol["top_k"], sigma_spatial_px=(sol["window"] - 1) / 2.0, seed=sg.PM_SEED,
-                          score_all=level)
+                          score_all=level, lanes=lanes)
             ctx.diag_enable(pm.DIAG_COUNT)
             d, n, c = ctx.patchmatch(0, srcs, sol["window"], sol["dilation"], sol["iters"], p)
             n_hyp, _, _ = ctx.diag_read()
             ctx.diag_enable(0)
             res.append((d.clone(), n.clone(), c.clone()))
             hyps.append(n_hyp)
-        say(f"{workload}: hypotheses scored per depth map: every candidate {hyps[0]}, without duplicates and "
+        say(f"{workload} (lanes {lanes}): hypotheses scored per depth map: every candidate {hyps[0]}, without duplicates and "
             f"current planes {hyps[1]} ({hyps[1] / hyps[0]:.3f}), also without candidates offered before "
             f"{hyps[2]} ({hyps[2] / hyps[0]:.3f})")
         for level, (d, n, c) in zip((1, 0), res[1:]):
