@@ -295,9 +295,10 @@ def consistency(depths, normals, K, R, t, ref: int, nbrs, tau_d: float = 0.02, t
     td = np.ascontiguousarray(np.asarray(t, np.float64).reshape(n, 3))
     nb = np.ascontiguousarray(nbrs, dtype=np.int32)
     Hr, Wr = int(H[ref]), int(W[ref])
-    od = np.zeros((Hr, Wr), np.float32)
-    on = np.zeros((Hr, Wr, 3), np.float32)
-    oc = np.zeros((Hr, Wr), np.uint8)
+    # every output element is written by the oracle: NaN / 255 beforehand would show one that is not
+    od = np.full((Hr, Wr), np.nan, np.float32)
+    on = np.full((Hr, Wr, 3), np.nan, np.float32)
+    oc = np.full((Hr, Wr), 255, np.uint8)
     rc = lib().oracle_consistency(n, _ptr(W, C.c_int32), _ptr(H, C.c_int32), _ptr(Kd, C.c_double),
                                   _ptr(Rd, C.c_double), _ptr(td, C.c_double), dptr, nptr, ref, _ptr(nb, C.c_int32),
                                   len(nb), tau_d, tau_n_deg, tau_r, min_consistent, _ptr(od, C.c_float),
@@ -336,7 +337,7 @@ def phi_hypotheses(depth):
     """Plane-hypothesis depths (Sec. III-E) of the pixels without depth: (H, W, 4), 0 = none."""
     d = np.ascontiguousarray(depth, dtype=np.float32)
     H, W = d.shape
-    hyp = np.zeros((H, W, 4), np.float32)
+    hyp = np.full((H, W, 4), np.nan, np.float32)  # every element is written
     lib().oracle_phi_hypotheses(_ptr(d, C.c_float), W, H, _ptr(hyp, C.c_float))
     return hyp
 
@@ -358,7 +359,7 @@ def phi_normals(depth, K):
     d = np.ascontiguousarray(depth, dtype=np.float32)
     Kd = np.ascontiguousarray(np.asarray(K, np.float64).reshape(9))
     H, W = d.shape
-    n = np.zeros((H, W, 3), np.float32)
+    n = np.full((H, W, 3), np.nan, np.float32)  # every element is written
     if lib().oracle_phi_normals(_ptr(d, C.c_float), W, H, _ptr(Kd, C.c_double), _ptr(n, C.c_float)) != 0:
         raise ValueError("singular K")
     return n

@@ -123,3 +123,102 @@ def test_unusable_neighbours_and_minimum_count():
     d0[0, 0] = 0.0
     od2, _, oc2 = oracle.consistency({0: d0, 1: d, 3: d}, {0: n, 1: n, 3: n}, K, R, t, 0, [1, 3])
     assert oc2[0, 0] == 0 and od2[0, 0] == 0 and oc2[1, 1] == 2
+
+
+@pytest.mark.parametrize("eps,ok", [(0.019, True), (-0.019, True), (0.021, False), (-0.021, False)])
+def test_depth_sampled_bilinearly_at_subpixel_positions(eps, ok):
+    """Same pose, the neighbour's principal point shifted by (0.3, 0.6): reference pixel x
+    lands on (x + 0.3, y + 0.6) of the neighbour, whose depth map is a bilinear function of
+    the pixel coordinates, so its bilinear interpolation there is exact.  With the
+    reference depth (1 + eps) times that value the depth test passes iff |eps| < 0.02 (the
+    re-projection comes back to x exactly and the normals agree)."""
+    K0, R0, t0 = cam(F, W, H)
+    K1 = K0.copy()
+    K1[0, 2] += 0.3
+    K1[1, 2] += 0.6
+    K, R, t = stack([(K0, R0, t0), (K1, R0, t0)])
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+
+    def dj(u, v):
+        return 4.0 + 0.05 * u + 0.2 * v + 0.003 * u * v
+
+    d1 = dj(xx, yy).astype(np.float32)
+    d0 = (dj(xx + 0.3, yy + 0.6) * (1 + eps)).astype(np.float32)
+    _, n = plane_maps(W, H, 4.0)
+    _, _, oc = oracle.consistency({0: d0, 1: d1}, {0: n, 1: n}, K, R, t, 0, [1], min_consistent=1)
+    inner = np.zeros((H, W), bool)
+    inner[:H - 1, :W - 1] = True  # the bilinear cell lies inside
+    assert np.all(oc[inner] == (1 if ok else 0))
+    assert np.all(oc[~inner] == 0)
+
+
+def _rot(yaw, pitch):
+    cy, sy, cp, sp = np.cos(yaw), np.sin(yaw), np.cos(pitch), np.sin(pitch)
+    Ry = np.array([[cy, 0.0, -sy], [0.0, 1.0, 0.0], [sy, 0.0, cy]])
+    Rx = np.array([[1.0, 0.0, 0.0], [0.0, cp, -sp], [0.0, sp, cp]])
+    return Rx @ Ry
+
+
+@pytest.mark.parametrize("frame,ok", [("own", True), ("reference", False)])
+def test_normals_compared_in_world_coordinates(frame, ok):
+    """A slanted plane seen from two cameras at the same centre, the second turned by 12
+    degrees of yaw and 35 of pitch.  Each view's depth is the plane's exact depth on its
+    rays; its normal is the plane normal in its own camera frame.  Compared in world
+    coordinates the normals agree and every pixel whose re-projection lands inside is
+    consistent; the second view's normals left in the reference frame (off by the 37
+    degree rotation) fail the 30 degree test everywhere."""
+    Wb, Hb, f = 64, 48, 60.0
+    K0, _, _ = cam(f, Wb, Hb)
+    R1 = _rot(np.radians(12.0), np.radians(35.0))
+    K, R, t = stack([(K0, np.eye(3), np.zeros(3)), (K0, R1, np.zeros(3))])
+    n0 = np.array([0.35, -0.45, -1.0])
+    n0 /= np.linalg.norm(n0)
+    c = 5.0  # plane n0 . X = -c in the reference (world) frame
+    yy, xx = np.mgrid[0:Hb, 0:Wb].astype(np.float64)
+    rays = np.stack([xx, yy, np.ones_like(xx)], -1) @ np.linalg.inv(K0).T
+
+    def depth_in(Rj):
+        nj = Rj @ n0  # the plane in camera j's frame: nj . X = -c (no translation)
+        return ((-c / (rays @ nj)) * rays[..., 2]).astype(np.float32), nj.astype(np.float32)
+
+    d0, nn0 = depth_in(np.eye(3))
+    d1, nn1 = depth_in(R1)
+    assert np.all(d0 > 0) and np.all(d1 > 0)
+    N0 = np.broadcast_to(nn0, (Hb, Wb, 3)).copy()
+    N1 = np.broadcast_to(nn1 if frame == "own" else nn0, (Hb, Wb, 3)).copy()
+    _, _, oc = oracle.consistency({0: d0, 1: d1}, {0: N0, 1: N1}, K, R, t, 0, [1], min_consistent=1,
+                                  tau_d=0.02, tau_r=1.0)
+    X = rays * d0[..., None].astype(np.float64) / rays[..., 2:3]
+    p = (X @ R1.T) @ K0.T
+    u, v = p[..., 0] / p[..., 2], p[..., 1] / p[..., 2]
+    inside = (u >= 0) & (u <= Wb - 2) & (v >= 0) & (v <= Hb - 2)
+    assert inside.sum() > 200
+    if ok:
+        assert np.all(oc[inside] == 1)
+    else:
+        assert np.all(oc == 0)
+    assert np.degrees(np.arccos(np.clip(nn0 @ nn1, -1, 1))) > 30.0
+
+
+@pytest.mark.parametrize("disp,parity", [(2.4, 0), (2.6, 1)])
+def test_normal_taken_at_the_rounded_row(disp, parity):
+    """The same as for columns, with a vertical baseline: the neighbour's normal is read in
+    row floor(v + 1/2); odd rows hold a normal that fails the test."""
+    Hb = 60
+    Z = 4.0
+    b = disp * Z / F
+    K0, R0, _ = cam(F, W, Hb)
+    t1 = -R0 @ np.array([0.0, b, 0.0])
+    K, R, t = stack([(K0, R0, np.zeros(3)), (K0, R0, t1)])
+    d, n = plane_maps(W, Hb, Z)
+    nb = n.copy()
+    a = np.radians(40.0)
+    nb[1::2, :] = [0.0, np.sin(a), -np.cos(a)]  # odd rows fail the normal test
+    _, _, oc = oracle.consistency({0: d, 1: d}, {0: n, 1: nb}, K, R, t, 0, [1], min_consistent=1)
+    ys = np.arange(Hb)
+    v = ys - disp
+    inside = (v >= 0) & (v <= Hb - 1)
+    rounded_even = (np.floor(v + 0.5).astype(int) % 2) == 0
+    assert np.all(oc[inside & rounded_even, :] == 1)
+    assert np.all(oc[inside & ~rounded_even, :] == 0)
+    assert np.all(rounded_even[inside] == ((ys[inside] + parity) % 2 == 0))

@@ -122,6 +122,50 @@ def test_map_on_chains_matches_enumeration():
         assert list(lab[0]) == [c[0] for c in best]
 
 
+def test_map_on_a_grid_matches_enumeration():
+    """Exact MAP on 2 x 3 grids (right and down edges) against an enumeration written out
+    here; hypotheses over [1, 6] so that relative differences above 1 (the truncation of
+    Eq. 8) occur."""
+    r = np.random.default_rng(2)
+    k1, k2, k3 = 1.0, 0.1, 2.0
+    H, W = 2, 3
+    for trial in range(12):
+        d = np.zeros((H, W), np.float32)
+        if trial % 4 == 0:
+            d[1, 2] = 2.5  # a fixed node
+        hyp = r.uniform(1, 6, (H, W, 4)).astype(np.float32)
+        hyp[r.random((H, W, 4)) < 0.4] = 0  # missing states
+        hyp[d > 0] = 0
+        hyp[0, 0, 0] = 1.2  # every free node keeps a state
+        for y in range(H):
+            for x in range(W):
+                if d[y, x] == 0 and not (hyp[y, x] > 0).any():
+                    hyp[y, x, 1] = 3.0
+        cost = r.uniform(0, 2, (H, W, 4)).astype(np.float32)
+        lab, e = oracle.phi_map_bruteforce(d, hyp, cost, k1, k2, k3)
+
+        def states(y, x):
+            if d[y, x] > 0:
+                return [(-1, float(d[y, x]), 0.0)]
+            return [(k, float(hyp[y, x, k]), np.log((2.0 - float(cost[y, x, k])) / k1 + k2)) for k in range(4)
+                    if hyp[y, x, k] > 0]
+
+        def pw(a, b):
+            rel = (a - b) / b if a > b else (b - a) / a
+            return np.log((k3 - min(1.0, rel)) ** 2)
+
+        nodes = [(y, x) for y in range(H) for x in range(W)]
+        edges = [(i, j) for i, (y, x) in enumerate(nodes) for j, (y2, x2) in enumerate(nodes)
+                 if (y2 == y and x2 == x + 1) or (x2 == x and y2 == y + 1)]
+
+        def energy(c):
+            return sum(s[2] for s in c) + sum(pw(c[i][1], c[j][1]) for i, j in edges)
+
+        best = max(itertools.product(*[states(y, x) for y, x in nodes]), key=energy)
+        assert np.isclose(e, energy(best), rtol=1e-12)
+        assert list(lab.ravel()) == [s[0] for s in best]
+
+
 def test_normals_of_a_rendered_plane():
     H, W, f = 30, 40, 50.0
     K = np.array([[f, 0, (W - 1) / 2], [0, f, (H - 1) / 2], [0, 0, 1.0]])
@@ -140,3 +184,7 @@ def test_normals_of_a_rendered_plane():
     inner[10, 10] = False
     np.testing.assert_allclose(out[inner], np.broadcast_to(n, (inner.sum(), 3)), atol=2e-5)
     assert np.all(out[10, 10] == 0) and np.all(out[0] == 0) and np.all(out[10, 11] == 0)
+    # the hole's 4-neighbours and the image's border rows and columns get no normal
+    for yy_, xx_ in ((9, 10), (11, 10), (10, 9), (10, 11)):
+        assert np.all(out[yy_, xx_] == 0)
+    assert np.all(out[-1] == 0) and np.all(out[:, 0] == 0) and np.all(out[:, -1] == 0)

@@ -174,13 +174,17 @@ def test_lane_split_sums_differ_from_one_sum_by_rounding_only(small_scene, lanes
     gt[..., :3] = sc.gt_normal
     gt[..., 3] = sc.gt_depth
     m = one.valid_mask()
+    differ = 0
     for planes in (P, gt):
         a = oracle.eval_cost(one, planes)[0][m]
         b = oracle.eval_cost(many, planes)[0][m]
         assert np.abs(a - b).max() <= 1e-5
+        differ += int((a != b).sum())
         a64 = oracle.eval_cost(one, planes, fp64=True)[0][m]
         b64 = oracle.eval_cost(many, planes, fp64=True)[0][m]
         assert np.abs(a64 - b64).max() <= 1e-12
+    # the split order is really taken: its FP32 rounding shows on some pixels
+    assert differ > 0
     A = _textured(24, 28, 1)
     K = _K(28, 24)
     same = _pose_problem([A, A], [K, K], window=7, lanes=lanes)
@@ -313,6 +317,10 @@ def test_aggregate_closed_form():
     assert oracle.aggregate(c, [0, 0, 0, 0]) == 2.0
     assert abs(oracle.aggregate([0.0, 0.3], [1, 1], eps_c=1e-4) - 2 / (1e4 + 1 / 0.3)) < 1e-15
     assert abs(oracle.aggregate([0.3, 0.3, 0.9], [1, 1, 1], top_k=2) - 0.3) < 1e-15
+    # the FP32 form: the same values within FP32 rounding
+    assert abs(oracle.aggregate(c, v, top_k=0, fp64=False) - scipy.stats.hmean([0.2, 0.5, 0.1])) < 1e-6
+    assert abs(oracle.aggregate(c, v, top_k=2, fp64=False) - scipy.stats.hmean([0.1, 0.2])) < 1e-6
+    assert oracle.aggregate(c, [0, 0, 0, 0], fp64=False) == 2.0
 
 
 # ----------------------------------------------------------------------------- search behaviour
@@ -360,8 +368,84 @@ def test_init_distribution(small_scene):
     # phi uniform on [-pi/2, pi/2] => the angle to the optical axis, acos|n_z|, is uniform on [0, pi/2]
     ang = np.arccos(np.clip(np.abs(n[:, 2]), 0, 1))
     assert scipy.stats.kstest(ang / (np.pi / 2), "uniform").pvalue > 1e-3
+    # theta uniform on [0, 2 pi] => the azimuth, taken modulo pi (the camera-facing flip
+    # adds pi), is uniform on [0, pi)
+    az = np.mod(np.arctan2(n[:, 1], n[:, 0]), np.pi)
+    assert scipy.stats.kstest(az / np.pi, "uniform").pvalue > 1e-3
     c = cost[m]
     assert np.all((c >= 0) & (c <= 2))
+
+
+def _uniforms(seed, x, y, W, iteration, phase):
+    """The four uniforms of pixel (x, y) (reading s27), from the KAT-pinned Philox block."""
+    o = oracle.philox4x32_10([y * W + x, iteration, phase, 0], [seed & 0xFFFFFFFF, seed >> 32])
+    return [(int(v) >> 8) * 2.0 ** -24 for v in o]
+
+
+def _facing(theta, phi, ray):
+    n = np.array([math.cos(theta) * math.sin(phi), math.sin(theta) * math.sin(phi), math.cos(phi)])
+    return -n if n @ ray > 0 else n
+
+
+def test_draws_map_to_the_documented_initial_planes(small_scene):
+    """Initialisation (Sec. III-B, readings s18 and s27), FP64: pixel (x, y) draws its four
+    uniforms from counter (y W + x, 0, 0, 0); d = d_lo + u0 (d_hi - d_lo), theta = 2 pi u1,
+    phi = pi (u2 - 1/2), the normal turned to face the camera."""
+    pb = oracle.Problem.from_scene(small_scene, 7, 1)
+    P, _ = oracle.init(pb, fp64=True)
+    lo, hi = small_scene.depth_range
+    Kinv = np.linalg.inv(small_scene.cams[0].K)
+    seed = pb.s.seed
+    ys, xs = np.nonzero(pb.valid_mask())
+    for i in np.random.default_rng(4).choice(len(xs), 50, replace=False):
+        x, y = int(xs[i]), int(ys[i])
+        u = _uniforms(seed, x, y, pb.W, 0, 0)
+        assert abs(P[y, x, 3] - (lo + u[0] * (hi - lo))) <= 1e-12 * hi
+        n = _facing(2 * math.pi * u[1], math.pi * (u[2] - 0.5), Kinv @ [x, y, 1.0])
+        np.testing.assert_allclose(P[y, x, :3], n, atol=1e-12)
+
+
+def test_draws_map_to_the_documented_refinement_candidates(small_scene):
+    """Random refinement (Sec. III-C, readings s12, s13, s15, s27), FP64: at iteration it
+    pixel (x, y) draws from counter (y W + x, it, 1, 0); d_new = d + (2 u0 - 1) d_hi / 4,
+    theta_new = atan2(n_y, n_x) + (2 u1 - 1) pi / 2, phi_new = acos(n_z) + (2 u2 - 1) pi / 12;
+    the candidates (d_new, n), (d, n_new), (d_new, n_new), the first two using d_new only
+    inside the depth range, are scored here through the oracle's cost of a single plane,
+    and the pixel must end with the first strictly best of them (or keep its plane)."""
+    pb = oracle.Problem.from_scene(small_scene, 7, 1, top_k=1)
+    P, C = oracle.init(pb, fp64=True)
+    it = 3
+    P2, C2 = oracle.halfsweep(pb, P, C, it, 0, fp64=True, propagate=False, refine=True)
+    lo, hi = small_scene.depth_range
+    Kinv = np.linalg.inv(small_scene.cams[0].K)
+    seed = pb.s.seed
+    m = pb.valid_mask() & _colour_mask(pb.H, pb.W, 0)
+    ys, xs = np.nonzero(m)
+    changed = 0
+    for i in np.random.default_rng(5).choice(len(xs), 40, replace=False):
+        x, y = int(xs[i]), int(ys[i])
+        u = _uniforms(seed, x, y, pb.W, it, 1)
+        n_old, d_old = P[y, x, :3], P[y, x, 3]
+        d_new = d_old + (2 * u[0] - 1) * (hi * 0.25)
+        d_ok = lo <= d_new <= hi
+        theta = math.atan2(n_old[1], n_old[0]) + (2 * u[1] - 1) * (math.pi / 2)
+        phi = math.acos(min(max(n_old[2], -1.0), 1.0)) + (2 * u[2] - 1) * (math.pi / 12)
+        n_new = _facing(theta, phi, Kinv @ [x, y, 1.0])
+        cands = [(n_old, d_new, d_ok), (n_new, d_old, True), (n_new, d_new, d_ok)]
+        best_c, best = C[y, x], (n_old, d_old)
+        for n, d, ok in cands:
+            if not ok:
+                continue
+            Q = P.copy()
+            Q[y, x, :3], Q[y, x, 3] = n, d
+            c = oracle.eval_cost(pb, Q, fp64=True, subset=[y * pb.W + x])[0][y, x]
+            if c < best_c:
+                best_c, best = c, (n, d)
+        np.testing.assert_allclose(P2[y, x, :3], best[0], atol=1e-12)
+        assert abs(P2[y, x, 3] - best[1]) <= 1e-12 * hi
+        assert C2[y, x] == best_c
+        changed += int(best_c < C[y, x])
+    assert changed > 5
 
 
 def test_halfsweeps_never_raise_cost_and_leave_other_colour(small_scene):
@@ -551,6 +635,120 @@ def test_zero_baseline_keeps_init():
     assert keep.sum() > 0.9 * m.sum()
     assert np.array_equal(d[keep], P[..., 3][keep].astype(np.float32))
     assert np.array_equal(n[keep], P[..., :3][keep].astype(np.float32))
+
+
+def _propagation_offsets():
+    """The neighbourhood of the red/black propagation as read from the cited sampling
+    scheme (reading s16), written as geometry: per axis direction e, a near "V" region of
+    the other colour's pixels o with o . e > 0, |o x e| < o . e and |o|_1 odd and <= 5, and
+    a far strip of the pixels k e, k = 7, 9, ..., 25."""
+    regions = []
+    for e in ((0, -1), (0, 1), (-1, 0), (1, 0)):
+        near = []
+        for dx in range(-6, 7):
+            for dy in range(-6, 7):
+                along = dx * e[0] + dy * e[1]
+                across = abs(dx * e[1] - dy * e[0])
+                l1 = abs(dx) + abs(dy)
+                if along > 0 and across < along and l1 % 2 == 1 and l1 <= 5:
+                    near.append((dx, dy))
+        regions.append(near)
+    for e in ((0, -1), (0, 1), (-1, 0), (1, 0)):
+        regions.append([(k * e[0], k * e[1]) for k in range(7, 26, 2)])
+    return regions
+
+
+def _probe_problem():
+    """Zero-baseline 64x64 problem (every camera-facing plane in range scores eps_c), a
+    probe pixel at its centre, and a state in which no neighbour offers a usable plane: the
+    other colour holds planes whose re-expression at any pixel lies far beyond the depth
+    range."""
+    h = w = 64
+    pb = _zero_baseline_problem(h, w, f=0.9 * w, depth_range=(1.0, 20.0))
+    P = np.zeros((h, w, 4))
+    P[..., 2] = -1.0
+    P[..., 3] = 200.0
+    C = np.full((h, w), 1.0)
+    px, py = 32, 32
+    C[py, px] = 2.0
+    return pb, P, C, px, py
+
+
+def test_propagation_neighbourhood_geometry():
+    """Sec. III-C propagation (reading s16): a pixel is offered a neighbour's plane exactly
+    when that neighbour lies in one of its 8 regions.  Black-box probe: one usable plane at
+    a single offset, everything else unusable; the probe pixel (stored cost C_max) must take
+    it for the 76 offsets of the regions and for no other offset of the other colour within
+    27 pixels."""
+    pb, P, C, px, py = _probe_problem()
+    regions = _propagation_offsets()
+    expected = {o for r in regions for o in r}
+    assert len(expected) == 76
+    sub = [py * pb.W + px]
+    taken = set()
+    for dy in range(-27, 28):
+        for dx in range(-27, 28):
+            if (abs(dx) + abs(dy)) % 2 == 0:
+                continue
+            P2, C2 = P.copy(), C.copy()
+            P2[py + dy, px + dx] = (0.0, 0.0, -1.0, 5.0)
+            C2[py + dy, px + dx] = 0.0
+            Po, Co = oracle.halfsweep(pb, P2, C2, 1, 0, subset=sub, propagate=True, refine=False)
+            if Co[py, px] < 2.0:
+                taken.add((dx, dy))
+                assert Po[py, px, 2] == -1.0 and 4.0 < Po[py, px, 3] < 6.0
+    assert taken == expected
+
+
+def test_propagation_takes_each_regions_lowest_cost_neighbour():
+    """Per region the neighbour offered is the other colour's lowest-cost pixel: with two
+    pixels of one region holding planes, the usable plane is taken only when its holder has
+    the lower stored cost (the other holds an unusable plane)."""
+    pb, P, C, px, py = _probe_problem()
+    sub = [py * pb.W + px]
+    for region in _propagation_offsets():
+        (ax, ay), (bx, by) = region[0], region[-1]
+        for good_cost, other_cost, expect in ((0.3, 0.6, True), (0.6, 0.3, False)):
+            P2, C2 = P.copy(), C.copy()
+            P2[py + ay, px + ax] = (0.0, 0.0, -1.0, 5.0)
+            C2[py + ay, px + ax] = good_cost
+            C2[py + by, px + bx] = other_cost
+            _, Co = oracle.halfsweep(pb, P2, C2, 1, 0, subset=sub, propagate=True, refine=False)
+            assert (Co[py, px] < 2.0) == expect
+
+
+def test_subset_evaluation_equals_the_full_pass(small_scene):
+    """Evaluating or half-sweeping a list of pixels gives at those pixels what the pass over
+    the whole image gives, and leaves every other pixel as it was."""
+    pb = oracle.Problem.from_scene(small_scene, 7, 1, top_k=1)
+    P, C = oracle.init(pb)
+    m = pb.valid_mask()
+    ys, xs = np.nonzero(m & _colour_mask(pb.H, pb.W, 1))
+    pick = np.random.default_rng(3).choice(len(xs), 60, replace=False)
+    sub = (ys[pick] * pb.W + xs[pick]).astype(np.int32)
+    full_c = oracle.eval_cost(pb, P)[0]
+    sub_c = oracle.eval_cost(pb, P, subset=sub)[0]
+    at = (ys[pick], xs[pick])
+    assert np.array_equal(sub_c[at], full_c[at])
+    Pf, Cf = oracle.halfsweep(pb, P, C, 1, 1)
+    Ps, Cs = oracle.halfsweep(pb, P, C, 1, 1, subset=sub)
+    assert np.array_equal(Ps[at], Pf[at]) and np.array_equal(Cs[at], Cf[at])
+    rest = np.ones((pb.H, pb.W), bool)
+    rest[at] = False
+    assert np.array_equal(Ps[rest], P[rest]) and np.array_equal(Cs[rest], C[rest])
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_stored_costs_are_the_stored_planes_costs(small_scene, fp64):
+    """After initialisation and after every half-sweep (propagation and refinement) each
+    pixel's stored cost is the cost of its stored plane, evaluated afresh."""
+    pb = oracle.Problem.from_scene(small_scene, 7, 1, top_k=1)
+    P, C = oracle.init(pb, fp64=fp64)
+    m = pb.valid_mask()
+    for it in (1, 2):
+        for col in (0, 1):
+            P, C = oracle.halfsweep(pb, P, C, it, col, fp64=fp64)
+            assert np.array_equal(oracle.eval_cost(pb, P, fp64=fp64)[0][m], C[m])
 
 
 def test_propagation_floods_a_seeded_plane():
