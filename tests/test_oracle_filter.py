@@ -222,3 +222,37 @@ def test_normal_taken_at_the_rounded_row(disp, parity):
     assert np.all(oc[inside & rounded_even, :] == 1)
     assert np.all(oc[inside & ~rounded_even, :] == 0)
     assert np.all(rounded_even[inside] == ((ys[inside] + parity) % 2 == 0))
+
+
+@pytest.mark.parametrize("deg", [20.0, 37.0])
+def test_normals_tilted_out_of_the_horizontal_plane(deg):
+    """Same camera, both views holding the normal (0, sin a, -cos a): the normals are equal,
+    so every pixel is consistent whatever the tilt (the dot product takes x with x, y with
+    y and z with z)."""
+    K, R, t = stack([cam(F, W, H)] * 2)
+    d, _ = plane_maps(W, H, 4.0)
+    a = np.radians(deg)
+    n = np.broadcast_to(np.array([0.0, np.sin(a), -np.cos(a)], np.float32), (H, W, 3)).copy()
+    _, _, oc = oracle.consistency({0: d, 1: d}, {0: n, 1: n}, K, R, t, 0, [1], min_consistent=1)
+    assert np.all(oc == 1)
+
+
+def test_a_hole_texel_voids_the_four_cells_that_hold_it():
+    """The neighbour's principal point shifted by (0.5, 0.5): pixel (x, y) interpolates the
+    cell of texels x..x+1, y..y+1 with weights 1/2.  A single hole texel (depth 0) at
+    (hx, hy) makes the neighbour unusable at exactly the four pixels whose cells hold it,
+    one for each corner of the cell."""
+    K0, R0, t0 = cam(F, W, H)
+    K1 = K0.copy()
+    K1[0, 2] += 0.5
+    K1[1, 2] += 0.5
+    K, R, t = stack([(K0, R0, t0), (K1, R0, t0)])
+    d, n = plane_maps(W, H, 4.0)
+    hy, hx = 20, 30
+    d1 = d.copy()
+    d1[hy, hx] = 0.0
+    _, _, oc = oracle.consistency({0: d, 1: d1}, {0: n, 1: n}, K, R, t, 0, [1], min_consistent=1)
+    expect = np.zeros((H, W), np.uint8)
+    expect[:H - 1, :W - 1] = 1  # cells inside the image
+    expect[hy - 1:hy + 1, hx - 1:hx + 1] = 0
+    assert np.array_equal(oc, expect)

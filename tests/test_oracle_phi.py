@@ -125,32 +125,34 @@ def test_map_on_chains_matches_enumeration():
 def test_map_on_a_grid_matches_enumeration():
     """Exact MAP on 2 x 3 grids (right and down edges) against an enumeration written out
     here; hypotheses over [1, 6] so that relative differences above 1 (the truncation of
-    Eq. 8) occur."""
+    Eq. 8) occur; k3 = 2 and 2.5; some grids with a node that has no hypothesis (isolated)."""
     r = np.random.default_rng(2)
-    k1, k2, k3 = 1.0, 0.1, 2.0
+    k1, k2 = 1.0, 0.1
     H, W = 2, 3
-    for trial in range(12):
+    for trial in range(16):
+        k3 = 2.0 if trial % 2 == 0 else 2.5
         d = np.zeros((H, W), np.float32)
         if trial % 4 == 0:
             d[1, 2] = 2.5  # a fixed node
         hyp = r.uniform(1, 6, (H, W, 4)).astype(np.float32)
         hyp[r.random((H, W, 4)) < 0.4] = 0  # missing states
         hyp[d > 0] = 0
-        hyp[0, 0, 0] = 1.2  # every free node keeps a state
-        for y in range(H):
-            for x in range(W):
-                if d[y, x] == 0 and not (hyp[y, x] > 0).any():
-                    hyp[y, x, 1] = 3.0
+        hyp[0, 0, 0] = 1.2
+        if trial % 3 == 1:
+            hyp[1, 0] = 0  # a free node without any hypothesis: isolated from the model
         cost = r.uniform(0, 2, (H, W, 4)).astype(np.float32)
         lab, e = oracle.phi_map_bruteforce(d, hyp, cost, k1, k2, k3)
 
         def states(y, x):
             if d[y, x] > 0:
                 return [(-1, float(d[y, x]), 0.0)]
-            return [(k, float(hyp[y, x, k]), np.log((2.0 - float(cost[y, x, k])) / k1 + k2)) for k in range(4)
-                    if hyp[y, x, k] > 0]
+            s_ = [(k, float(hyp[y, x, k]), np.log((2.0 - float(cost[y, x, k])) / k1 + k2)) for k in range(4)
+                  if hyp[y, x, k] > 0]
+            return s_ or [(-1, 0.0, 0.0)]
 
         def pw(a, b):
+            if a <= 0 or b <= 0:
+                return 0.0  # an edge to an isolated node carries nothing
             rel = (a - b) / b if a > b else (b - a) / a
             return np.log((k3 - min(1.0, rel)) ** 2)
 
