@@ -237,15 +237,18 @@ def test_normals_tilted_out_of_the_horizontal_plane(deg):
     assert np.all(oc == 1)
 
 
-def test_a_hole_texel_voids_the_four_cells_that_hold_it():
-    """The neighbour's principal point shifted by (0.5, 0.5): pixel (x, y) interpolates the
-    cell of texels x..x+1, y..y+1 with weights 1/2.  A single hole texel (depth 0) at
-    (hx, hy) makes the neighbour unusable at exactly the four pixels whose cells hold it,
-    one for each corner of the cell."""
+@pytest.mark.parametrize("sx,sy", [(0.5, 0.5), (0.5, 1e-6), (1e-6, 0.5)])
+def test_a_hole_texel_voids_the_four_cells_that_hold_it(sx, sy):
+    """The neighbour's principal point shifted by (sx, sy): pixel (x, y) interpolates the
+    cell of texels x..x+1, y..y+1.  A single hole texel (depth 0) at (hx, hy) makes the
+    neighbour unusable at exactly the four pixels whose cells hold it, one for each corner
+    of the cell.  With a shift of 1e-6 along one axis the far corners weigh almost nothing,
+    so the interpolated depth would pass the depth test: there the corner check alone
+    decides."""
     K0, R0, t0 = cam(F, W, H)
     K1 = K0.copy()
-    K1[0, 2] += 0.5
-    K1[1, 2] += 0.5
+    K1[0, 2] += sx
+    K1[1, 2] += sy
     K, R, t = stack([(K0, R0, t0), (K1, R0, t0)])
     d, n = plane_maps(W, H, 4.0)
     hy, hx = 20, 30
