@@ -177,6 +177,22 @@ def test_plane_homography_maps_points_of_the_plane():
         np.testing.assert_allclose(q[:2] / q[2], p[:2] / p[2], atol=1e-9)
 
 
+def test_plane_homography_with_a_moved_reference():
+    """The same with the reference camera itself moved and turned (its pose enters the
+    relative transform)."""
+    K0, R0, t0 = _cam(100, 64, 48, 0.15, [0.3, -0.2, 0.5])
+    K1, R1, t1 = _cam(120, 80, 60, -0.25, [1.1, 0.3, 0.2])
+    Hm = cnn.plane_homography(K0, R0, t0, K1, R1, t1, 5.5)
+    r = rng(14)
+    for _ in range(20):
+        u, v = r.uniform(0, 63), r.uniform(0, 47)
+        X = 5.5 * np.linalg.inv(K0) @ np.array([u, v, 1.0])
+        Xw = R0.T @ (X - t0)
+        p = K1 @ (R1 @ Xw + t1)
+        q = Hm @ np.array([u, v, 1.0])
+        np.testing.assert_allclose(q[:2] / q[2], p[:2] / p[2], atol=1e-9)
+
+
 def test_nearest_sources_by_camera_centre():
     Rs, ts = [], []
     for x in [0.0, 3.0, -1.0, 0.5, 2.0, -0.2]:
@@ -184,6 +200,104 @@ def test_nearest_sources_by_camera_centre():
         Rs.append(R)
         ts.append(t)
     assert cnn.nearest_sources(Rs, ts, 0, [1, 2, 3, 4, 5]) == [5, 3, 2, 4]
+    # the reference away from the origin: distances are to its centre
+    Rs, ts = [], []
+    for x in [5.0, 8.0, 4.0, 5.5, 7.0, 4.8]:
+        K, R, t = _cam(100, 64, 48, 0.1, [x, 1.0, -2.0])
+        Rs.append(R)
+        ts.append(t)
+    assert cnn.nearest_sources(Rs, ts, 0, [1, 2, 3, 4, 5]) == [5, 3, 2, 4]
+
+
+@pytest.mark.parametrize("H,W", [(36, 44), (37, 45)])
+def test_proposal_inputs_warp_general_poses(H, W):
+    """Reference moved and turned, six sources around it: channels 1-4 hold the four
+    nearest sources (by camera centre, in that order), each sampled where the point of the
+    reference plane Z = (d_lo + d_hi) / 2 behind block centre (4X + 1.5, 4Y + 1.5)
+    projects, computed here through world coordinates; the sources are affine ramps in
+    their pixel coordinates, so bilinear sampling is exact; outside a source: 0."""
+    f = 50.0
+    K0, R0, t0 = _cam(f, W, H, 0.1, [0.4, -0.3, 0.2])
+    poses = [(-0.05, [0.9, -0.3, 0.2]), (0.2, [0.1, -0.1, 0.1]), (0.15, [0.4, 0.5, 0.2]), (0.0, [2.5, -0.3, 0.2]),
+             (0.12, [0.4, -0.3, -0.5]), (0.3, [-0.9, -0.3, 0.2])]
+    Ks, Rs, ts, images = [K0], [R0], [t0], [np.full((H, W), 100.0)]
+    coef = []
+    for j, (yaw, pos) in enumerate(poses):
+        Ws, Hs = W + 3 * j, H + 2 * j
+        Kj, Rj, tj = _cam(f * (1 + 0.1 * j), Ws, Hs, yaw, pos)
+        a, b, c = 20.0 + 10 * j, 1.5 + 0.2 * j, -0.8 + 0.3 * j
+        yy, xx = np.mgrid[0:Hs, 0:Ws].astype(np.float64)
+        Ks.append(Kj)
+        Rs.append(Rj)
+        ts.append(tj)
+        images.append(a + b * xx + c * yy)
+        coef.append((a, b, c))
+    lo, hi = 1.5, 9.5
+    out = cnn.proposal_inputs(images, Ks, Rs, ts, (lo, hi), 0, [1, 2, 3, 4, 5, 6])
+    h, w = -(-H // 4), -(-W // 4)
+    assert out.shape == (h, w, 5)
+    c0 = -R0.T @ t0
+    dist = [np.sum((-Rs[s].T @ ts[s] - c0) ** 2) for s in range(1, 7)]
+    order = [1 + int(i) for i in np.argsort(dist, kind="stable")[:4]]
+    dmid = 0.5 * (lo + hi)
+    checked = 0
+    for k, s in enumerate(order):
+        a, b, c = coef[s - 1]
+        Hs, Ws = images[s].shape
+        for Y in range(h):
+            for X in range(w):
+                x = np.array([4 * X + 1.5, 4 * Y + 1.5, 1.0])
+                Xw = R0.T @ (dmid * (np.linalg.inv(K0) @ x) - t0)
+                p = Ks[s] @ (Rs[s] @ Xw + ts[s])
+                u, v = p[0] / p[2], p[1] / p[2]
+                inside = p[2] > 0 and 0 <= u <= Ws - 1 and 0 <= v <= Hs - 1
+                want = (a + b * u + c * v - 127.5) / 64.0 if inside else 0.0
+                assert abs(out[Y, X, 1 + k] - want) < 1e-9
+                checked += inside
+    assert checked > 2 * h * w
+
+
+def test_decode_upsamples_random_outputs_bilinearly():
+    """Random raw outputs (normals of any length): each output channel is interpolated
+    linearly at ((y - 1.5) / 4, (x - 1.5) / 4) clamped to the grid (scipy's order-1
+    map_coordinates), depth through the scaled sigmoid, the normal normalised and turned
+    to face the camera."""
+    H, W = 19, 26
+    h, w = 5, 7
+    K, _, _ = _cam(30, W, H, 0.0, [0, 0, 0])
+    r = rng(21)
+    out = r.normal(size=(h, w, 4)) * np.array([1.5, 2.0, 2.0, 2.0])
+    planes = cnn.decode(out, K, (2.0, 10.0), H, W)
+    Y, X = np.meshgrid(np.clip((np.arange(H) - 1.5) / 4, 0, h - 1), np.clip((np.arange(W) - 1.5) / 4, 0, w - 1),
+                       indexing="ij")
+    o = np.stack([ndi.map_coordinates(out[..., c], [Y.ravel(), X.ravel()], order=1).reshape(H, W)
+                  for c in range(4)], -1)
+    np.testing.assert_allclose(planes[..., 3], 2.0 + 8.0 / (1 + np.exp(-o[..., 0])), rtol=1e-12)
+    n = o[..., 1:] / np.linalg.norm(o[..., 1:], axis=-1, keepdims=True)
+    rays = np.stack(list(np.meshgrid(np.arange(W), np.arange(H))) + [np.ones((H, W))], -1) @ np.linalg.inv(K).T
+    n[(n * rays).sum(-1) > 0] *= -1
+    np.testing.assert_allclose(planes[..., :3], n, atol=1e-12)
+
+
+def test_targets_of_ramps():
+    """Depth and normals varying per pixel: block (X, Y) averages the depths of pixels
+    4X + 1 .. 4X + 2, 4Y + 1 .. 4Y + 2 (clamped) and normalises the sum of their normals."""
+    H, W = 14, 17
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    depth = 2.0 + 0.1 * xx + 0.05 * yy + 0.01 * xx * yy
+    normal = np.stack([0.02 * xx, -0.03 * yy, -np.ones_like(xx)], -1)
+    cost = np.full((H, W), 0.2)
+    tgt, mask = cnn.targets(depth, normal, cost, 0.5)
+    h, w = 4, 5
+    assert np.all(mask == 1)
+    for Y in range(h):
+        for X in range(w):
+            ys = np.minimum([4 * Y + 1, 4 * Y + 2], H - 1)
+            xs = np.minimum([4 * X + 1, 4 * X + 2], W - 1)
+            blk = np.ix_(ys, xs)
+            assert np.isclose(tgt[Y, X, 0], depth[blk].mean(), rtol=1e-14)
+            ns = normal[blk].reshape(-1, 3).sum(0)
+            np.testing.assert_allclose(tgt[Y, X, 1:], ns / np.linalg.norm(ns), atol=1e-14)
 
 
 def test_proposal_inputs_identity_source_and_ramp():
@@ -209,6 +323,8 @@ def test_proposal_inputs_identity_source_and_ramp():
     # edge blocks repeat the last column / row: mean over clamped coordinates
     xs = np.minimum(np.arange(4 * (w - 1), 4 * w), W - 1)
     assert np.isclose(out[0, w - 1, 0] * 64 + 127.5, (3.0 * xs.mean() + 2.0 * 1.5 + 10.0))
+    ys = np.minimum(np.arange(4 * (h - 1), 4 * h), H - 1)
+    assert np.isclose(out[h - 1, 0, 0] * 64 + 127.5, (3.0 * 1.5 + 2.0 * ys.mean() + 10.0))
     # identity homography for the identical source: channel 1 = reference bilinear at block centres
     cy, cx = np.mgrid[0:h, 0:w].astype(np.float64) * 4 + 1.5
     inside = (cx <= W - 1) & (cy <= H - 1)
