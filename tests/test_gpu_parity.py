@@ -234,7 +234,7 @@ def test_repeated_runs_replay_the_eager_result(ctx, tiny):
     with other eager work and synchronisations between them and with new output tensors on
     one of them, gives bitwise the result of the eager sequence (diagnostics on: eager)."""
     scene, cfg = tiny
-    ctx.set_scene(scene)
+    _prep(ctx, scene, cfg)  # also gives the binding the reference's size for eval_cost
     srcs = list(range(1, len(scene.images)))
     prm = params_for(cfg["window"], cfg["top_k"])
     ctx.diag_enable(pm.DIAG_COUNT)
@@ -265,6 +265,32 @@ def test_repeated_runs_replay_the_eager_result(ctx, tiny):
     ctx.step(cfg["iters"] + 1, 0)
     ep, ec = ctx.get_state()
     assert torch.equal(gp, ep) and torch.equal(gc, ec)
+
+
+def test_host_outputs_equal_device_outputs(ctx, tiny):
+    """phimvs_patchmatch with host output arrays (staged through the library's device
+    buffers, the sequence replayed from its graph on the second call) gives bitwise the
+    device-output result."""
+    import ctypes
+    scene, cfg = tiny
+    ctx.set_scene(scene)
+    srcs = list(range(1, len(scene.images)))
+    prm = params_for(cfg["window"], cfg["top_k"])
+    d, n, c = (t.cpu().numpy() for t in ctx.patchmatch(0, srcs, cfg["window"], cfg["dilation"], cfg["iters"], prm))
+    H, W = d.shape
+    L = pm.lib()
+    sa = (ctypes.c_int * len(srcs))(*srcs)
+    p = prm._c()
+    for call in range(2):
+        hd = np.full((H, W), -1.0, np.float32)
+        hn = np.full((H, W, 3), -1.0, np.float32)
+        hc = np.full((H, W), -1.0, np.float32)
+        rc = L.phimvs_patchmatch(ctx.h, 0, sa, len(srcs), cfg["window"], cfg["dilation"], cfg["iters"],
+                                 ctypes.byref(p), hd.ctypes.data, hn.ctypes.data, hc.ctypes.data, 0)
+        assert rc == 0, L.phimvs_last_error(ctx.h)
+        same = np.array_equal(hd, d) and np.array_equal(hn, n) and np.array_equal(hc, c)
+        say(f"host outputs, call {call + 1}: bitwise {same}")
+        assert same
 
 
 def test_patchmatch_parity_tiny(ctx, tiny):
