@@ -119,6 +119,9 @@ def lib(threads: int = 1):
         L.oracle_phi_map_bruteforce.argtypes = [fp, fp, fp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                                 C.c_double, ip]
         L.oracle_phi_map_bruteforce.restype = C.c_double
+        L.oracle_phi_trws.argtypes = [fp, fp, fp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_int, ip, fp]
+        L.oracle_phi_trws.restype = None
         L.oracle_phi_normals.argtypes = [fp, C.c_int, C.c_int, dp, fp]
         L.oracle_fuse.argtypes = [C.c_int, ip, ip, dp, dp, dp, C.POINTER(fp), C.c_double, fp, ip,
                                   C.POINTER(C.c_int64)]
@@ -365,43 +368,47 @@ def phi_normals(depth, K):
     return n
 
 
-def phi_select(depth, hyp, cost, k1: float = 1.0, k2: float = 0.1, k3: float = 2.0, cmax: float = CMAX):
-    """Selection step of Sec. III-E for tiny maps (exact MAP by enumeration): the hypothesis
-    maps (H, W, 4) are subsampled to half size (node (X, Y) <- pixel (2X, 2Y)), the graph
-    model is decoded exactly, the decoded depth is brought back to full size (pixel (x, y)
-    <- node (x // 2, y // 2)) as the reference map, and each pixel without depth takes
-    its hypothesis closest to the reference (lowest k on ties; none without hypothesis or
-    reference).  -> depth (H, W) float32."""
+def phi_trws(depth, hyp, cost, k1: float = 1.0, k2: float = 0.1, k3: float = 2.0, cmax: float = CMAX,
+             iterations: int = 8):
+    """Sequential TRW decoding of the pairwise model of Sec. III-E (the paper's decoder)
+    -> (labels (H, W) int32, -1 = fixed or no state; depth (H, W) float32, 0 = no state)."""
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    h = np.ascontiguousarray(hyp, dtype=np.float32)
+    c = np.ascontiguousarray(cost, dtype=np.float32)
+    H, W = d.shape
+    lab = np.zeros((H, W), np.int32)
+    val = np.full((H, W), np.nan, np.float32)  # every element is written
+    lib().oracle_phi_trws(_ptr(d, C.c_float), _ptr(h, C.c_float), _ptr(c, C.c_float), W, H, k1, k2, k3, cmax,
+                          int(iterations), _ptr(lab, C.c_int32), _ptr(val, C.c_float))
+    return lab, val
+
+
+def phi_select(depth, hyp, cost, k1: float = 1.0, k2: float = 0.1, k3: float = 2.0, cmax: float = CMAX,
+               iterations=None):
+    """Selection step of Sec. III-E: the hypothesis maps (H, W, 4) are subsampled to half
+    size (node (X, Y) <- pixel (2X, 2Y)), the graph model is decoded (iterations None: the
+    exact MAP by enumeration, for tiny maps; else that many TRW iterations), the decoded
+    depth is brought back to full size (pixel (x, y) <- node (x // 2, y // 2)) as the
+    reference map, and each pixel without depth takes its hypothesis closest to the
+    reference (lowest k on ties; none without hypothesis or reference).  -> depth (H, W)
+    float32."""
     d = np.asarray(depth, np.float32)
     h = np.asarray(hyp, np.float32)
     c = np.asarray(cost, np.float32)
     d2, h2, c2 = d[::2, ::2], h[::2, ::2], c[::2, ::2]
-    lab, _ = phi_map_bruteforce(d2, h2, c2, k1, k2, k3, cmax)
-    H2, W2 = d2.shape
-    dec = np.zeros((H2, W2), np.float64)
-    for Y in range(H2):
-        for X in range(W2):
-            if d2[Y, X] > 0:
-                dec[Y, X] = d2[Y, X]
-            elif lab[Y, X] >= 0:
-                dec[Y, X] = h2[Y, X, lab[Y, X]]
+    if iterations is None:
+        lab, _ = phi_map_bruteforce(d2, h2, c2, k1, k2, k3, cmax)
+        fixed = d2 > 0
+        picked = np.take_along_axis(h2, np.maximum(lab, 0)[..., None], 2)[..., 0]
+        dec = np.where(fixed, d2, np.where(lab >= 0, picked, 0.0)).astype(np.float32)
+    else:
+        _, dec = phi_trws(d2, h2, c2, k1, k2, k3, cmax, iterations)
     H, W = d.shape
-    out = np.zeros((H, W), np.float32)
-    for y in range(H):
-        for x in range(W):
-            if d[y, x] > 0:
-                out[y, x] = d[y, x]
-                continue
-            ref = float(np.float32(dec[y // 2, x // 2]))
-            if not ref > 0:
-                continue
-            best, bd = 0.0, 0.0
-            for k in range(4):
-                hk = float(h[y, x, k])
-                if not hk > 0:
-                    continue
-                e = abs(hk - ref)
-                if best == 0.0 or e < bd:
-                    best, bd = hk, e
-            out[y, x] = best
+    ref = dec[np.arange(H)[:, None] // 2, np.arange(W)[None, :] // 2].astype(np.float64)
+    # distance of each hypothesis to the reference; a missing hypothesis never wins
+    dist = np.where(h > 0, np.abs(h.astype(np.float64) - ref[..., None]), np.inf)
+    k = np.argmin(dist, axis=2)  # the first of equal distances: lowest k
+    best = np.take_along_axis(h, k[..., None], 2)[..., 0]
+    usable = (ref > 0) & np.isfinite(np.take_along_axis(dist, k[..., None], 2)[..., 0])
+    out = np.where(d > 0, d, np.where(usable, best, 0.0)).astype(np.float32)
     return out

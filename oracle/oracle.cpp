@@ -65,6 +65,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <vector>
 #include <algorithm>
 #ifdef _OPENMP
@@ -1073,6 +1074,118 @@ double oracle_phi_map_bruteforce(const float* depth, const float* hyp, const flo
   }
   for (int i = 0; i < N; ++i) label[i] = states[i][best[i]];
   return best_e;
+}
+
+// Approximate MAP of the same model by sequential tree-reweighted message passing (the
+// paper decodes its graph model with TRW, Sec. III-E; TRW-S as published by Kolmogorov,
+// 2006, on the 4-connected grid with the nodes in raster order), minimising the sum of
+// -log potentials.  Nodes with a state: a fixed node has its depth as its only state,
+// with cost 0; a node without depth has its non-zero hypotheses, in order of k, with cost
+// -log((C_max - cost) / k1 + k2).  An edge between two nodes with states costs
+// -log([k3 - min(1, relative difference)]^2).  Messages start at 0.  One iteration is a
+// forward pass over the nodes in raster order, then a backward pass in reverse order.  At
+// each node the belief is its cost plus the incoming messages, added in the order up, left,
+// right, down; the node then sends to each of its later neighbours (right, down; in the
+// backward pass its earlier ones, up and left) the message
+//   m(s_j) = min over s of [gamma b(s) - m_{j->i}(s) + E(s, s_j)]
+// (evaluated left to right), minus its smallest value, where gamma = 1 / max(number of
+// earlier, number of later neighbours with states).  Then the nodes are labelled in raster
+// order: the state with the lowest cost plus edge costs to the labels already chosen for
+// the up and left neighbours plus the messages from the right and down neighbours (these
+// terms added in the order up, left, right, down), the first such state on ties.
+// label[i] receives k (-1 for a fixed node or one without states), value[i] its depth (0
+// without states).
+void oracle_phi_trws(const float* depth, const float* hyp, const float* cost, int W, int H, double k1, double k2,
+                     double k3, double cmax, int iterations, int32_t* label, float* value) {
+  const int N = W * H;
+  std::vector<std::vector<int>> states(N);
+  std::vector<std::vector<double>> val(N), unary(N);
+  for (int i = 0; i < N; ++i) {
+    if (depth[i] > 0.0f) {
+      states[i].push_back(-1);
+      val[i].push_back(depth[i]);
+      unary[i].push_back(0.0);
+      continue;
+    }
+    for (int k = 0; k < 4; ++k)
+      if (hyp[4 * i + k] > 0.0f) {
+        states[i].push_back(k);
+        val[i].push_back(hyp[4 * i + k]);
+        unary[i].push_back(-std::log((cmax - (double)cost[4 * i + k]) / k1 + k2));
+      }
+  }
+  // neighbour of node i in direction d (0 up, 1 left, 2 right, 3 down) with states, or -1
+  auto nb = [&](int i, int d) {
+    const int x = i % W, y = i / W;
+    int j = -1;
+    if (d == 0 && y > 0) j = i - W;
+    if (d == 1 && x > 0) j = i - 1;
+    if (d == 2 && x + 1 < W) j = i + 1;
+    if (d == 3 && y + 1 < H) j = i + W;
+    return j >= 0 && !states[j].empty() ? j : -1;
+  };
+  auto E = [&](double a, double b) { return -std::log(phi_pairwise(a, b, k3)); };
+  // msg[i][d]: the message node i received from its neighbour in direction d
+  std::vector<std::vector<std::vector<double>>> msg(N, std::vector<std::vector<double>>(4));
+  std::vector<double> gamma(N, 1.0);
+  for (int i = 0; i < N; ++i) {
+    for (int d = 0; d < 4; ++d) msg[i][d].assign(states[i].size(), 0.0);
+    int earlier = 0, later = 0;
+    for (int d = 0; d < 4; ++d)
+      if (nb(i, d) >= 0) (d < 2 ? earlier : later)++;
+    const int m = std::max(earlier, later);
+    if (m > 0) gamma[i] = 1.0 / m;
+  }
+  auto visit = [&](int i, int d_first) {
+    const size_t n = states[i].size();
+    if (n == 0) return;
+    std::vector<double> b(unary[i]);
+    for (int d = 0; d < 4; ++d)
+      if (nb(i, d) >= 0)
+        for (size_t s = 0; s < n; ++s) b[s] += msg[i][d][s];
+    for (int d = d_first; d < d_first + 2; ++d) {
+      const int j = nb(i, d);
+      if (j < 0) continue;
+      std::vector<double>& out = msg[j][3 - d];
+      double lo = std::numeric_limits<double>::infinity();
+      for (size_t t = 0; t < states[j].size(); ++t) {
+        double best = std::numeric_limits<double>::infinity();
+        for (size_t s = 0; s < n; ++s) {
+          const double v = gamma[i] * b[s] - msg[i][d][s] + E(val[i][s], val[j][t]);
+          if (v < best) best = v;
+        }
+        out[t] = best;
+        if (best < lo) lo = best;
+      }
+      for (double& v : out) v -= lo;
+    }
+  };
+  for (int it = 0; it < iterations; ++it) {
+    for (int i = 0; i < N; ++i) visit(i, 2);
+    for (int i = N - 1; i >= 0; --i) visit(i, 0);
+  }
+  std::vector<int> pick(N, -1);
+  for (int i = 0; i < N; ++i) {
+    label[i] = -1;
+    value[i] = 0.0f;
+    if (states[i].empty()) continue;
+    double best = std::numeric_limits<double>::infinity();
+    for (size_t s = 0; s < states[i].size(); ++s) {
+      double e = unary[i][s];
+      for (int d = 0; d < 4; ++d) {
+        const int j = nb(i, d);
+        if (j < 0) continue;
+        e += d < 2 ? E(val[j][pick[j]], val[i][s]) : msg[i][d][s];
+      }
+      if (e < best) {
+        best = e;
+        pick[i] = (int)s;
+      }
+    }
+    if (pick[i] < 0) pick[i] = 0;
+    label[i] = states[i][pick[i]];
+    value[i] = (float)val[i][pick[i]];
+  }
 }
 
 // Normals of Eq. 10 (with the norm, not its square): n = (X_u - X_d) x (X_l - X_r),

@@ -1,8 +1,11 @@
 """Pins of the plane-hypothesis-inference oracle (Sec. III-E): the line fits reproduce
 affine depth exactly in all four directions and equal numpy's least-squares fit on the
-six closest samples; the exact MAP agrees with hand-worked chains; the normals of Eq. 10
-equal the normal of the plane a depth map was rendered from."""
+six closest samples; the exact MAP agrees with hand-worked chains; the TRW decoder is
+exact on chains, reduces to closed forms where its messages are fixed or absent, and is
+near the exact MAP on small loopy grids; the normals of Eq. 10 equal the normal of the
+plane a depth map was rendered from."""
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -166,6 +169,208 @@ def test_map_on_a_grid_matches_enumeration():
         best = max(itertools.product(*[states(y, x) for y, x in nodes]), key=energy)
         assert np.isclose(e, energy(best), rtol=1e-12)
         assert list(lab.ravel()) == [s[0] for s in best]
+
+
+def _log_potential(d, hyp, cost, lab, k1, k2, k3, cmax=2.0):
+    """Sum of log potentials of a labelling (-1: the fixed depth, or no state)."""
+    H, W = d.shape
+
+    def value(y, x):
+        if d[y, x] > 0:
+            return float(d[y, x])
+        return float(hyp[y, x, lab[y, x]]) if lab[y, x] >= 0 else 0.0
+
+    e = 0.0
+    for y in range(H):
+        for x in range(W):
+            if d[y, x] <= 0 and lab[y, x] >= 0:
+                e += math.log((cmax - float(cost[y, x, lab[y, x]])) / k1 + k2)
+            for yy, xx in ((y, x + 1), (y + 1, x)):
+                if yy < H and xx < W and value(y, x) > 0 and value(yy, xx) > 0:
+                    a, b = value(y, x), value(yy, xx)
+                    rel = (a - b) / b if a > b else (b - a) / a
+                    e += math.log((k3 - min(1.0, rel)) * (k3 - min(1.0, rel)))
+    return e
+
+
+def _random_model(r, H, W, fixed=0.25, missing=0.3, lo=1.0, hi=6.0):
+    d = np.where(r.random((H, W)) < fixed, r.uniform(lo, hi, (H, W)), 0.0).astype(np.float32)
+    hyp = r.uniform(lo, hi, (H, W, 4)).astype(np.float32)
+    hyp[r.random((H, W, 4)) < missing] = 0
+    hyp[d > 0] = 0
+    cost = r.uniform(0, 2, (H, W, 4)).astype(np.float32)
+    return d, hyp, cost
+
+
+@pytest.mark.parametrize("shape", [(1, 2), (1, 5), (1, 8), (6, 1)])
+def test_trws_is_exact_on_chains(shape):
+    """A chain is a tree, on which sequential TRW decodes the exact MAP (Kolmogorov 2006):
+    its labelling reaches the enumerated optimum's log potential; depths follow the labels."""
+    r = np.random.default_rng(shape[1] * 10 + shape[0])
+    k2 = 0.1
+    for trial in range(15):
+        k3 = 2.0 if trial % 2 else 2.5
+        k1 = (0.5, 1.0, 2.0)[trial % 3]
+        d, hyp, cost = _random_model(r, *shape)
+        lab, val = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=10)
+        _, e_opt = oracle.phi_map_bruteforce(d, hyp, cost, k1, k2, k3)
+        assert np.isclose(_log_potential(d, hyp, cost, lab, k1, k2, k3), e_opt, rtol=1e-9, atol=1e-12)
+        picked = np.take_along_axis(hyp, np.maximum(lab, 0)[..., None], 2)[..., 0]
+        expect = np.where(d > 0, d, np.where(lab >= 0, picked, 0.0))
+        assert np.array_equal(val, expect.astype(np.float32))
+        assert np.all(lab[d > 0] == -1)
+
+
+def _is_forest(alive):
+    """The 4-connected graph of the True cells has no cycle."""
+    H, W = alive.shape
+    parent = {c: c for c in zip(*np.nonzero(alive))}
+
+    def root(c):
+        while parent[c] != c:
+            c = parent[c]
+        return c
+
+    for y, x in list(parent):
+        for c2 in ((y, x + 1), (y + 1, x)):
+            if c2 in parent:
+                a, b = root((y, x)), root(c2)
+                if a == b:
+                    return False
+                parent[a] = b
+    return True
+
+
+def test_trws_is_exact_on_forests_in_any_raster_order():
+    """Grids whose nodes with states form a forest (the others have neither depth nor
+    hypotheses): TRW decodes the exact MAP there too.  Unlike chains, such trees bend back
+    against the raster order (a node can have both its upper and its left neighbour in the
+    model), so messages in both sweeps and both directions are needed; k1 varies."""
+    r = np.random.default_rng(14)
+    k2, k3 = 0.1, 2.0
+    tested = 0
+    for trial in range(300):
+        alive = r.random((3, 4)) < 0.7
+        if alive.sum() < 5 or not _is_forest(alive):
+            continue
+        k1 = (0.5, 1.0, 2.0)[trial % 3]
+        d = np.where((r.random((3, 4)) < 0.2) & alive, r.uniform(1, 6, (3, 4)), 0.0).astype(np.float32)
+        hyp = r.uniform(1, 6, (3, 4, 4)).astype(np.float32)
+        hyp[r.random((3, 4, 4)) < 0.4] = 0
+        hyp[(d > 0) | ~alive] = 0
+        cost = r.uniform(0, 2, (3, 4, 4)).astype(np.float32)
+        lab, _ = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=10)
+        _, e_opt = oracle.phi_map_bruteforce(d, hyp, cost, k1, k2, k3)
+        assert np.isclose(_log_potential(d, hyp, cost, lab, k1, k2, k3), e_opt, rtol=1e-9, atol=1e-12)
+        tested += 1
+    assert tested >= 60
+
+
+def test_trws_ties_go_to_the_first_state():
+    """Two hypotheses of a node with the same depth and cost score the same under every
+    message: the lower k is taken, with and without message passing."""
+    r = np.random.default_rng(15)
+    for iters in (0, 1, 4):
+        d, hyp, cost = _random_model(r, 5, 6, fixed=0.3, missing=0.0)
+        free = np.argwhere(d <= 0)
+        for y, x in free:
+            hyp[y, x, 3] = hyp[y, x, 1]
+            cost[y, x, 3] = cost[y, x, 1]
+            hyp[y, x, 0] = 0.0  # state order: 1, 2, 3
+        lab, _ = oracle.phi_trws(d, hyp, cost, 0.7, 0.1, 2.0, iterations=iters)
+        assert not (lab == 3).any()
+        assert ((lab == 1) | (lab == 2))[d <= 0].all()
+
+
+def test_trws_free_nodes_between_fixed_ones():
+    """Free nodes whose neighbours all have a fixed depth (or no state) are independent:
+    after any number of iterations each takes the state with the highest product of its
+    potential and its edge potentials to the fixed neighbours."""
+    r = np.random.default_rng(11)
+    k1, k2, k3 = 1.7, 0.1, 2.0
+    H, W = 7, 9
+    for trial in range(6):
+        yy, xx = np.mgrid[0:H, 0:W]
+        d = np.where((yy + xx) % 2 == 0, r.uniform(1, 6, (H, W)), 0.0).astype(np.float32)
+        hyp = r.uniform(1, 6, (H, W, 4)).astype(np.float32)
+        hyp[r.random((H, W, 4)) < 0.3] = 0
+        hyp[d > 0] = 0
+        if trial % 2:
+            d[3, 4] = 0.0  # a node with neither depth nor hypotheses: no state
+            hyp[3, 4] = 0
+        cost = r.uniform(0, 2, (H, W, 4)).astype(np.float32)
+        for iters in (1, 3):
+            lab, _ = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=iters)
+            for y in range(H):
+                for x in range(W):
+                    if d[y, x] > 0 or not (hyp[y, x] > 0).any():
+                        continue
+                    score = {}
+                    for k in np.nonzero(hyp[y, x] > 0)[0]:
+                        h = float(hyp[y, x, k])
+                        e = math.log((2.0 - float(cost[y, x, k])) / k1 + k2)
+                        for y2, x2 in ((y - 1, x), (y, x - 1), (y, x + 1), (y + 1, x)):
+                            if 0 <= y2 < H and 0 <= x2 < W and d[y2, x2] > 0:
+                                a = float(d[y2, x2])
+                                rel = (a - h) / h if a > h else (h - a) / a
+                                e += math.log((k3 - min(1.0, rel)) ** 2)
+                        score[k] = e
+                    best = max(score.values())
+                    assert np.isclose(score[lab[y, x]], best, rtol=1e-12), (y, x, score, lab[y, x])
+
+
+def test_trws_without_iterations_labels_greedily():
+    """With no message passing the decoding is greedy in raster order: each node takes the
+    state with the highest product of its potential and the edge potentials to the states
+    already chosen for its upper and left neighbours (first state on ties)."""
+    r = np.random.default_rng(12)
+    k1, k2, k3 = 0.6, 0.1, 2.5
+    H, W = 6, 7
+    for _ in range(5):
+        d, hyp, cost = _random_model(r, H, W)
+        lab, val = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=0)
+        chosen = np.zeros((H, W))
+        for y in range(H):
+            for x in range(W):
+                if d[y, x] > 0:
+                    chosen[y, x] = d[y, x]
+                    assert lab[y, x] == -1
+                    continue
+                ks = [k for k in range(4) if hyp[y, x, k] > 0]
+                if not ks:
+                    assert lab[y, x] == -1 and val[y, x] == 0
+                    continue
+                best_k, best_e = None, None
+                for k in ks:
+                    h = float(hyp[y, x, k])
+                    e = math.log((2.0 - float(cost[y, x, k])) / k1 + k2)
+                    for y2, x2 in ((y - 1, x), (y, x - 1)):
+                        if y2 >= 0 and x2 >= 0 and chosen[y2, x2] > 0:
+                            a = chosen[y2, x2]
+                            rel = (a - h) / h if a > h else (h - a) / a
+                            e += math.log((k3 - min(1.0, rel)) ** 2)
+                    if best_e is None or e > best_e:
+                        best_k, best_e = k, e
+                assert lab[y, x] == best_k
+                chosen[y, x] = hyp[y, x, best_k]
+
+
+def test_trws_on_small_loopy_grids():
+    """On 3 x 3 grids (loops) TRW is an approximation: its labelling never beats the
+    enumerated optimum, reaches it in most cases and stays close otherwise."""
+    r = np.random.default_rng(13)
+    k1, k2, k3 = 1.0, 0.1, 2.0
+    gaps = []
+    for _ in range(25):
+        d, hyp, cost = _random_model(r, 3, 3, fixed=0.2, missing=0.15, lo=2.0, hi=5.0)
+        lab, _ = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=20)
+        _, e_opt = oracle.phi_map_bruteforce(d, hyp, cost, k1, k2, k3)
+        e = _log_potential(d, hyp, cost, lab, k1, k2, k3)
+        assert e <= e_opt + 1e-9
+        gaps.append((e_opt - e) / abs(e_opt))
+    gaps = np.array(gaps)
+    assert (gaps < 1e-9).mean() >= 0.8
+    assert gaps.max() < 0.05
 
 
 def test_normals_of_a_rendered_plane():
