@@ -324,7 +324,8 @@ void phimvs_default_phi_params(phimvs_phi_params* p);
  * takes pixel (2X, 2Y)), the graph model (node states = hypotheses with potential
  * (C_max - C) / k1 + k2, pixels with depth = fixed states, 4-connected edges with
  * [k3 - min(1, relative depth difference)]^2) is decoded on the host by sequential
- * tree-reweighted message passing, the decoded half-size depth is brought back to full
+ * tree-reweighted message passing (as phimvs_phi_decode_host), the decoded half-size
+ * depth is brought back to full
  * size (pixel (x, y) takes node (x / 2, y / 2)) as the reference map, and each pixel
  * without depth takes its hypothesis closest to the reference (lowest k on ties; stays
  * empty without hypothesis or reference).  Pixels with depth keep it.  depth, depth_out:
@@ -334,8 +335,14 @@ int phimvs_phi_select(phimvs_ctx* ctx, int width, int height, const float* depth
 
 /* The graph-model decoder of phimvs_phi_select on host arrays (CPU only): depth H*W
  * (> 0: fixed node), hyp and cost planar 4*H*W; label_out receives the chosen hypothesis
- * (-1: fixed or no state) and depth_out its depth (0: no state).  Returns PHIMVS_OK or
- * PHIMVS_E_ARG. */
+ * (-1: fixed or no state) and depth_out its depth (0: no state).  Sequential TRW-S
+ * (Kolmogorov 2006) in raster order, `iterations` forward and backward sweeps, then
+ * labelling in raster order; the result is that of the plain sequential schedule bit for
+ * bit, computed as wavefronts of tiles on up to 16 host threads (one for graphs under
+ * 8192 nodes).  Returns PHIMVS_OK; PHIMVS_E_ARG for a null array, a size below 1, k1 <= 0,
+ * k2 <= 0, k3 <= 1, iterations < 0 or a hypothesis whose potential (C_max - C) / k1 + k2
+ * is not positive; PHIMVS_E_UNSUPPORTED for graphs of 2^27 nodes or more; PHIMVS_E_OOM when
+ * host memory runs out. */
 int phimvs_phi_decode_host(int width, int height, const float* depth, const float* hyp, const float* cost,
                            double k1, double k2, double k3, double cost_max, int iterations, int32_t* label_out,
                            float* depth_out);

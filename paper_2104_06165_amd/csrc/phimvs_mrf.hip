@@ -7,9 +7,13 @@
 // (Eq. 8); decoding maximises the product, i.e. minimises the sum of -log potentials.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <limits>
+#include <memory>
+#include <new>
+#include <thread>
 #include <vector>
 
 #include "phimvs.h"
@@ -17,150 +21,298 @@
 namespace {
 
 constexpr int kMaxLab = 4;
+// tiles of the sweep schedule (nodes): a tile depends on its left and upper tiles in a
+// forward sweep, on its right and lower tiles in a backward sweep
+constexpr int kTileH = 32, kTileW = 64;
+constexpr unsigned kMaxThreads = 16;
 
-struct Node {
-  int n = 0;                 // number of states (0: not part of the model)
-  int label[kMaxLab];        // hypothesis index of each state (-1: the fixed depth)
-  double value[kMaxLab];     // depth of each state
-  double unary[kMaxLab];     // -log phi_n
-};
-
+// symmetric in its arguments, bit for bit: (h1, h2) and (h2, h1) take the same branch values
 double edge_energy(double h1, double h2, double k3) {
   const double rel = h1 > h2 ? (h1 - h2) / h2 : (h2 - h1) / h1;
   const double m = rel < 1.0 ? rel : 1.0;
   return -std::log((k3 - m) * (k3 - m));
 }
 
+unsigned worker_count(size_t nodes) {
+  if (nodes < (size_t)kTileH * kTileW * 4) return 1;
+  const unsigned hw = std::thread::hardware_concurrency();
+  return std::max(1u, std::min(hw, kMaxThreads));
+}
+
+// runs work() on up to T threads, the calling thread included (if a thread cannot be
+// started, the others share its part: every work() drains a common counter)
+template <class F>
+void on_threads(unsigned T, F&& work) {
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < T; ++t) {
+    try {
+      th.emplace_back(work);
+    } catch (...) {
+      break;
+    }
+  }
+  work();
+  for (auto& x : th) x.join();
+}
+
+// f(y0, y1) over blocks of rows
+template <class F>
+void parallel_rows(int H, unsigned T, F&& f) {
+  std::atomic<int> next{0};
+  on_threads(T, [&] {
+    for (;;) {
+      const int y = next.fetch_add(16);
+      if (y >= H) break;
+      f(y, std::min(H, y + 16));
+    }
+  });
+}
+
+// visit(i) for every node of a W x H grid, each after its left and upper neighbours
+// (forward) or after its right and lower neighbours (backward): tiles are handed out by
+// anti-diagonal, a tile starts once the tiles it borders in that direction are done, and
+// inside a tile the nodes go in raster (reverse raster) order
+template <class F>
+void wavefront(int W, int H, unsigned T, bool forward, F&& visit) {
+  const int nTX = (W + kTileW - 1) / kTileW, nTY = (H + kTileH - 1) / kTileH;
+  const int n_tiles = nTX * nTY;
+  std::vector<int> order;
+  order.reserve(n_tiles);
+  for (int s = 0; s < nTX + nTY - 1; ++s)
+    for (int ty = 0; ty < nTY; ++ty)
+      if (s - ty >= 0 && s - ty < nTX) order.push_back(ty * nTX + (s - ty));
+  std::unique_ptr<std::atomic<int>[]> done(new std::atomic<int>[n_tiles]);
+  for (int t = 0; t < n_tiles; ++t) done[t].store(0, std::memory_order_relaxed);
+  std::atomic<int> next{0};
+  const int dir = forward ? -1 : 1;
+  on_threads(T, [&] {
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n_tiles) break;
+      const int t = forward ? order[k] : order[n_tiles - 1 - k];
+      const int tx = t % nTX, ty = t / nTX;
+      // those tiles come earlier in the hand-out order, so someone already holds them
+      if (tx + dir >= 0 && tx + dir < nTX)
+        while (!done[ty * nTX + tx + dir].load(std::memory_order_acquire)) std::this_thread::yield();
+      if (ty + dir >= 0 && ty + dir < nTY)
+        while (!done[(ty + dir) * nTX + tx].load(std::memory_order_acquire)) std::this_thread::yield();
+      const int x0 = tx * kTileW, x1 = std::min(W, x0 + kTileW);
+      const int y0 = ty * kTileH, y1 = std::min(H, y0 + kTileH);
+      if (forward) {
+        for (int y = y0; y < y1; ++y)
+          for (int x = x0; x < x1; ++x) visit(y * W + x);
+      } else {
+        for (int y = y1 - 1; y >= y0; --y)
+          for (int x = x1 - 1; x >= x0; --x) visit(y * W + x);
+      }
+      done[t].store(1, std::memory_order_release);
+    }
+  });
+}
+
 }  // namespace
 
+// Sequential TRW-S visits the nodes in raster order (forward sweep: each node sends to its
+// right and lower neighbours) and then in reverse raster order (backward sweep: to its upper
+// and left neighbours).  In a forward sweep a node reads the messages its left and upper
+// neighbours sent in the same sweep and those its right and lower neighbours sent in the
+// previous backward sweep, which nothing in between rewrites; so any order that visits a
+// node after its left and upper neighbours computes the same messages, bit for bit, as the
+// raster order (likewise for the backward sweep and for the final decoding, which reads the
+// choices of the left and upper neighbours).  These passes run as wavefronts of tiles on
+// several threads.  The edge energies are computed once per edge (they do not change), and a
+// message into a node with a single state is 0 after its normalisation, whatever was sent.
 extern "C" int phimvs_phi_decode_host(int width, int height, const float* depth, const float* hyp, const float* cost,
                                       double k1, double k2, double k3, double cost_max, int iterations,
                                       int32_t* label_out, float* depth_out) {
   if (width < 1 || height < 1 || !depth || !hyp || !cost || !label_out || !depth_out) return PHIMVS_E_ARG;
   if (!(k1 > 0) || !(k2 > 0) || !(k3 > 1) || iterations < 0) return PHIMVS_E_ARG;
-  const int W = width, H = height, N = W * H;
-  const size_t plane = (size_t)N;
-  std::vector<Node> nodes(N);
-  for (int i = 0; i < N; ++i) {
-    Node& nd = nodes[i];
-    if (depth[i] > 0.0f) {
-      nd.n = 1;
-      nd.label[0] = -1;
-      nd.value[0] = depth[i];
-      nd.unary[0] = 0.0;
-      continue;
-    }
-    for (int k = 0; k < kMaxLab; ++k) {
-      const float h = hyp[k * plane + i];
-      if (!(h > 0.0f)) continue;
-      const double phi = (cost_max - (double)cost[k * plane + i]) / k1 + k2;
-      nd.label[nd.n] = k;
-      nd.value[nd.n] = h;
-      nd.unary[nd.n] = -std::log(phi);
-      ++nd.n;
-    }
-  }
-  // messages into node i from its neighbour in direction d (0 up, 1 left, 2 right, 3 down)
-  std::vector<double> msg((size_t)N * 4 * kMaxLab, 0.0);
-  auto nbr = [&](int i, int d) -> int {
-    const int x = i % W, y = i / W;
-    switch (d) {
-      case 0: return y > 0 ? i - W : -1;
-      case 1: return x > 0 ? i - 1 : -1;
-      case 2: return x + 1 < W ? i + 1 : -1;
-      default: return y + 1 < H ? i + W : -1;
-    }
-  };
-  auto opposite = [](int d) { return 3 - d; };
-  auto M = [&](int i, int d) -> double* { return &msg[((size_t)i * 4 + d) * kMaxLab]; };
-  // a neighbour takes part when it has states; gamma = 1 / max(#earlier, #later) neighbours
-  std::vector<double> gamma(N, 1.0);
-  for (int i = 0; i < N; ++i) {
-    if (!nodes[i].n) continue;
-    int before = 0, after = 0;
-    for (int d = 0; d < 4; ++d) {
-      const int j = nbr(i, d);
-      if (j < 0 || !nodes[j].n) continue;
-      (d < 2 ? before : after)++;
-    }
-    const int m = std::max(before, after);
-    gamma[i] = m > 0 ? 1.0 / m : 1.0;
-  }
-  auto belief = [&](int i, double* b) {
-    const Node& nd = nodes[i];
-    for (int l = 0; l < nd.n; ++l) b[l] = nd.unary[l];
-    for (int d = 0; d < 4; ++d) {
-      const int j = nbr(i, d);
-      if (j < 0 || !nodes[j].n) continue;
-      const double* m = M(i, d);
-      for (int l = 0; l < nd.n; ++l) b[l] += m[l];
-    }
-  };
-  // send the message i -> j (j is neighbour d of i)
-  auto send = [&](int i, int d, const double* b) {
-    const int j = nbr(i, d);
-    const Node& ni = nodes[i];
-    const Node& nj = nodes[j];
-    const double* back = M(i, d);  // message j -> i
-    double* out = M(j, opposite(d));
-    double lo = std::numeric_limits<double>::infinity();
-    for (int m = 0; m < nj.n; ++m) {
-      double best = std::numeric_limits<double>::infinity();
-      for (int l = 0; l < ni.n; ++l) {
-        const double v = gamma[i] * b[l] - back[l] + edge_energy(ni.value[l], nj.value[m], k3);
-        best = std::min(best, v);
+  if ((int64_t)width * height > INT32_MAX / 16) return PHIMVS_E_UNSUPPORTED;
+  try {
+    const int W = width, H = height, N = W * H;
+    const size_t plane = (size_t)N;
+    const unsigned T = worker_count(plane);
+    // node i: ns[i] states (0: not part of the model); state l: hypothesis lab (-1: the
+    // fixed depth), depth val, unary -log phi_n
+    std::vector<uint8_t> ns(N, 0), live(N, 0);
+    std::vector<int8_t> lab((size_t)N * kMaxLab);
+    std::vector<double> val((size_t)N * kMaxLab), un((size_t)N * kMaxLab);
+    std::atomic<bool> bad{false};
+    parallel_rows(H, T, [&](int y0, int y1) {
+      for (int i = y0 * W; i < y1 * W; ++i) {
+        const size_t q = (size_t)i * kMaxLab;
+        if (depth[i] > 0.0f) {
+          ns[i] = 1;
+          lab[q] = -1;
+          val[q] = depth[i];
+          un[q] = 0.0;
+          continue;
+        }
+        int n = 0;
+        for (int k = 0; k < kMaxLab; ++k) {
+          const float h = hyp[k * plane + i];
+          if (!(h > 0.0f)) continue;
+          const double phi = (cost_max - (double)cost[k * plane + i]) / k1 + k2;
+          if (!(phi > 0.0)) bad.store(true, std::memory_order_relaxed);
+          lab[q + n] = (int8_t)k;
+          val[q + n] = h;
+          un[q + n] = -std::log(phi);
+          ++n;
+        }
+        ns[i] = (uint8_t)n;
       }
-      out[m] = best;
-      lo = std::min(lo, best);
-    }
-    for (int m = 0; m < nj.n; ++m) out[m] -= lo;
-  };
-  double b[kMaxLab];
-  for (int it = 0; it < iterations; ++it) {
-    for (int i = 0; i < N; ++i) {  // forward: to the right and down neighbours
-      if (!nodes[i].n) continue;
-      belief(i, b);
-      for (int d = 2; d < 4; ++d) {
-        const int j = nbr(i, d);
-        if (j >= 0 && nodes[j].n) send(i, d, b);
+    });
+    if (bad.load()) return PHIMVS_E_ARG;  // a node potential that is not positive
+    // live[i] bit d: neighbour d (0 up, 1 left, 2 right, 3 down) exists and has states;
+    // gamma = 1 / max(#earlier, #later) such neighbours; the energies of the edge to the
+    // right (er) and the one below (ed) of node i, indexed [state of i][state of the
+    // neighbour], laid out row after row
+    const int step[4] = {-W, -1, 1, W};
+    std::vector<double> gamma(N, 1.0);
+    std::vector<int64_t> er(N, -1), ed(N, -1), row_start(H + 1, 0);
+    parallel_rows(H, T, [&](int y0, int y1) {
+      for (int y = y0; y < y1; ++y) {
+        int64_t count = 0;
+        for (int x = 0, i = y * W; x < W; ++x, ++i) {
+          if (!ns[i]) continue;
+          const bool has[4] = {y > 0 && ns[i - W], x > 0 && ns[i - 1], x + 1 < W && ns[i + 1],
+                               y + 1 < H && ns[i + W]};
+          int before = 0, after = 0;
+          for (int d = 0; d < 4; ++d) {
+            if (!has[d]) continue;
+            live[i] |= (uint8_t)(1 << d);
+            (d < 2 ? before : after)++;
+          }
+          // no energy is needed between two single-state nodes: no message goes into one,
+          // and one decodes to its only state
+          if (has[2] && ns[i] * ns[i + 1] > 1) er[i] = count, count += ns[i] * ns[i + 1];
+          if (has[3] && ns[i] * ns[i + W] > 1) ed[i] = count, count += ns[i] * ns[i + W];
+          const int m = std::max(before, after);
+          gamma[i] = m > 0 ? 1.0 / m : 1.0;
+        }
+        row_start[y + 1] = count;
       }
-    }
-    for (int i = N - 1; i >= 0; --i) {  // backward: to the up and left neighbours
-      if (!nodes[i].n) continue;
-      belief(i, b);
-      for (int d = 0; d < 2; ++d) {
-        const int j = nbr(i, d);
-        if (j >= 0 && nodes[j].n) send(i, d, b);
+    });
+    for (int y = 0; y < H; ++y) row_start[y + 1] += row_start[y];
+    std::unique_ptr<double[]> energy(new double[(size_t)row_start[H]]);
+    parallel_rows(H, T, [&](int y0, int y1) {
+      for (int y = y0; y < y1; ++y)
+        for (int i = y * W; i < (y + 1) * W; ++i)
+          for (int d = 2; d < 4; ++d) {
+            int64_t& o = d == 2 ? er[i] : ed[i];
+            if (o < 0) continue;
+            o += row_start[y];
+            const int j = i + step[d];
+            for (int l = 0; l < ns[i]; ++l)
+              for (int m = 0; m < ns[j]; ++m)
+                energy[o + l * ns[j] + m] = edge_energy(val[(size_t)i * kMaxLab + l], val[(size_t)j * kMaxLab + m], k3);
+          }
+    });
+    // E(i in state l, j in state m) for the edge from i to its neighbour j in direction d:
+    // e[l * sl + m * sm]
+    auto edge = [&](int i, int j, int d, const double*& e, int& sl, int& sm) {
+      if (d >= 2) {
+        e = &energy[d == 2 ? er[i] : ed[i]];
+        sl = ns[j];
+        sm = 1;
+      } else {
+        e = &energy[d == 1 ? er[j] : ed[j]];
+        sl = 1;
+        sm = ns[i];
       }
-    }
-  }
-  // decode in order: earlier neighbours contribute their chosen state, later ones their messages
-  std::vector<int> pick(N, -1);
-  for (int i = 0; i < N; ++i) {
-    const Node& nd = nodes[i];
-    label_out[i] = -1;
-    depth_out[i] = 0.0f;
-    if (!nd.n) continue;
-    double best = std::numeric_limits<double>::infinity();
-    int arg = 0;
-    for (int l = 0; l < nd.n; ++l) {
-      double e = nd.unary[l];
+    };
+    // messages into node i from its neighbour in direction d; those into a single-state
+    // node are never written (they stay 0)
+    std::unique_ptr<double[]> msg(new double[(size_t)N * 4 * kMaxLab]);
+    parallel_rows(H, T, [&](int y0, int y1) {
+      std::fill(&msg[(size_t)y0 * W * 4 * kMaxLab], &msg[(size_t)y1 * W * 4 * kMaxLab], 0.0);
+    });
+    auto M = [&](int i, int d) -> double* { return &msg[((size_t)i * 4 + d) * kMaxLab]; };
+    // the belief of node i, then its messages to the neighbours in directions d0, d0 + 1.
+    // A single-state node's belief is its unary term plus zeros, and what it sends depends
+    // on nothing else: its messages are the same in every sweep, so it only sends in the
+    // first sweep of each direction.
+    auto update = [&](int i, int d0, bool first) {
+      const int n = ns[i];
+      if (!n || (n == 1 && !first)) return;
+      double b[kMaxLab];
+      for (int l = 0; l < n; ++l) b[l] = un[(size_t)i * kMaxLab + l];
       for (int d = 0; d < 4; ++d) {
-        const int j = nbr(i, d);
-        if (j < 0 || !nodes[j].n) continue;
-        if (d < 2)
-          e += edge_energy(nodes[j].value[pick[j]], nd.value[l], k3);
-        else
-          e += M(i, d)[l];
+        if (!(live[i] >> d & 1)) continue;
+        if (n == 1) {
+          b[0] += 0.0;
+          continue;
+        }
+        const double* m = M(i, d);
+        for (int l = 0; l < n; ++l) b[l] += m[l];
       }
-      if (e < best) {
-        best = e;
-        arg = l;
+      for (int d = d0; d < d0 + 2; ++d) {
+        if (!(live[i] >> d & 1)) continue;
+        const int j = i + step[d], nj = ns[j];
+        if (nj == 1) continue;
+        double* out = M(j, 3 - d);
+        const double* back = M(i, d);  // message j -> i
+        const double* e;
+        int sl, sm;
+        edge(i, j, d, e, sl, sm);
+        double a[kMaxLab];
+        for (int l = 0; l < n; ++l) a[l] = gamma[i] * b[l] - back[l];
+        double lo = std::numeric_limits<double>::infinity();
+        for (int m = 0; m < nj; ++m) {
+          double best = std::numeric_limits<double>::infinity();
+          for (int l = 0; l < n; ++l) best = std::min(best, a[l] + e[l * sl + m * sm]);
+          out[m] = best;
+          lo = std::min(lo, best);
+        }
+        for (int m = 0; m < nj; ++m) out[m] -= lo;
       }
+    };
+    for (int it = 0; it < iterations; ++it) {
+      wavefront(W, H, T, true, [&](int i) { update(i, 2, it == 0); });
+      wavefront(W, H, T, false, [&](int i) { update(i, 0, it == 0); });
     }
-    pick[i] = arg;
-    label_out[i] = nd.label[arg];
-    depth_out[i] = (float)nd.value[arg];
+    // decode in order: earlier neighbours contribute their chosen state, later ones their messages
+    std::vector<int8_t> pick(N, -1);
+    wavefront(W, H, T, true, [&](int i) {
+      label_out[i] = -1;
+      depth_out[i] = 0.0f;
+      const int n = ns[i];
+      if (!n) return;
+      if (n == 1) {
+        pick[i] = 0;
+        label_out[i] = lab[(size_t)i * kMaxLab];
+        depth_out[i] = (float)val[(size_t)i * kMaxLab];
+        return;
+      }
+      double best = std::numeric_limits<double>::infinity();
+      int arg = 0;
+      for (int l = 0; l < n; ++l) {
+        double e = un[(size_t)i * kMaxLab + l];
+        for (int d = 0; d < 4; ++d) {
+          if (!(live[i] >> d & 1)) continue;
+          if (d < 2) {
+            const int j = i + step[d];
+            const double* ee;
+            int sl, sm;
+            edge(i, j, d, ee, sl, sm);
+            e += ee[l * sl + pick[j] * sm];
+          } else {
+            e += M(i, d)[l];
+          }
+        }
+        if (e < best) {
+          best = e;
+          arg = l;
+        }
+      }
+      pick[i] = (int8_t)arg;
+      label_out[i] = lab[(size_t)i * kMaxLab + arg];
+      depth_out[i] = (float)val[(size_t)i * kMaxLab + arg];
+    });
+  } catch (const std::bad_alloc&) {
+    return PHIMVS_E_OOM;
+  } catch (...) {
+    return PHIMVS_E_UNSUPPORTED;
   }
   return PHIMVS_OK;
 }

@@ -127,6 +127,25 @@ def test_selection_parity_on_a_chain(ctx, seed):
     assert np.array_equal(g.cpu().numpy(), o)
 
 
+@pytest.mark.parametrize("kind", ["sparse", "blocks"])
+def test_selection_parity_full_size(ctx, kind):
+    """1600 x 1066 maps (an 800 x 533 graph, decoded on several host threads): mostly empty
+    (most nodes free, up to four states) or mostly filled with holes, negative and NaN
+    depths; the library's selection equals the oracle's with its plain TRW decoder, at the
+    default 8 iterations, bitwise."""
+    H, W = 1066, 1600
+    d = hole_map(H + W + len(kind), H, W, kind)
+    D = torch.from_numpy(d).cuda()
+    hyp = ctx.phi_hypotheses(D)
+    cost = np.random.default_rng(17).uniform(0, 2, (4, H, W)).astype(np.float32)
+    say(f"selection {kind}: {(~(d > 0)).mean():.3f} of pixels empty; decoding")
+    g = ctx.phi_select(D, hyp, torch.from_numpy(cost).cuda(), pm.PhiParams(iterations=8)).cpu().numpy()
+    o = oracle.phi_select(d, hyp.cpu().numpy().transpose(1, 2, 0), cost.transpose(1, 2, 0), iterations=8)
+    filled = ~(d > 0) & (o > 0)
+    say(f"selection {kind}: {filled.mean():.3f} of pixels filled, bitwise equal {(g == o).mean():.6f}")
+    assert np.array_equal(g, o)
+
+
 def test_normals_parity(ctx, tiny):
     d = tiny.gt_depth.astype(np.float32).copy()
     d[30:40, 50:70] = 0.0

@@ -1,8 +1,10 @@
 """The library's host-side graph-model decoder of plane hypothesis inference (Sec. III-E;
 the paper runs it on the CPU, so does the library) against the oracle's exact MAP on
 tiny grids: exact on chains (a tree, where sequential tree-reweighted message passing
-is exact), and on small loopy grids equal to the optimum or within a small margin of it.
-No GPU needed: the decoder takes host arrays."""
+is exact), and on small loopy grids equal to the optimum or within a small margin of it;
+and against the oracle's plain sequential TRW decoder bit for bit on grids large enough
+for the library's threaded tile schedule, with fixed and single-state nodes, ragged tile
+edges and several iteration counts.  No GPU needed: the decoder takes host arrays."""
 import numpy as np
 import pytest
 
@@ -87,3 +89,36 @@ def test_decoder_arguments():
         pm.phi_decode_host(d, h[:3], h)
     lab, dep = pm.phi_decode_host(d, h, h)  # no states anywhere
     assert np.all(lab == -1) and np.all(dep == 0)
+
+
+@pytest.mark.parametrize("H,W,fixed,k1,k3,iters", [
+    (150, 260, 0.25, 1.0, 2.0, 8),   # several threads, ragged tiles at both edges
+    (150, 260, 0.6, 0.5, 2.5, 3),    # mostly fixed nodes, as in filtered maps
+    (33, 1000, 0.3, 1.0, 2.0, 1),    # one and a bit tile rows
+    (1000, 9, 0.3, 2.0, 1.5, 2),     # a single tile column
+    (129, 193, 0.0, 1.0, 2.0, 0),    # no message passing: the greedy raster decoding
+])
+def test_decoder_equals_the_oracle_trws(H, W, fixed, k1, k3, iters):
+    r = np.random.default_rng(H * 7 + W)
+    depth = np.where(r.uniform(size=(H, W)) < fixed, r.uniform(2, 5, (H, W)), 0.0).astype(np.float32)
+    hyp = r.uniform(2, 5, (H, W, 4)).astype(np.float32)
+    hyp[r.uniform(size=(H, W, 4)) < 0.3] = 0.0
+    hyp[depth > 0] = 0.0
+    single = r.uniform(size=(H, W)) < 0.05  # nodes left with one hypothesis
+    hyp[single, 1:] = 0.0
+    cost = r.uniform(0, 2, (H, W, 4)).astype(np.float32)
+    lab_o, dep_o = oracle.phi_trws(depth, hyp, cost, k1, 0.1, k3, iterations=iters)
+    lab, dep = pm.phi_decode_host(depth, hyp.transpose(2, 0, 1), cost.transpose(2, 0, 1),
+                                  pm.PhiParams(k1, 0.1, k3, iters))
+    assert np.array_equal(lab, lab_o), f"{(lab != lab_o).sum()} labels differ"
+    assert np.array_equal(dep, dep_o)
+
+
+def test_decoder_rejects_a_potential_that_is_not_positive():
+    """A cost above C_max + k1 k2 makes (C_max - C) / k1 + k2 negative: no valid potential."""
+    d = np.zeros((2, 2), np.float32)
+    h = np.full((4, 2, 2), 3.0, np.float32)
+    c = np.zeros((4, 2, 2), np.float32)
+    c[2, 1, 1] = 2.5
+    with pytest.raises(pm.PhimvsError):
+        pm.phi_decode_host(d, h, c)
