@@ -329,7 +329,11 @@ void phimvs_default_phi_params(phimvs_phi_params* p);
  * size (pixel (x, y) takes node (x / 2, y / 2)) as the reference map, and each pixel
  * without depth takes its hypothesis closest to the reference (lowest k on ties; stays
  * empty without hypothesis or reference).  Pixels with depth keep it.  depth, depth_out:
- * device H*W; hyp, cost: device planar 4*H*W.  Synchronises the stream. */
+ * device H*W; hyp, cost: device planar 4*H*W.  The half-size inputs are gathered on the
+ * device (9 (W+1)/2 (H+1)/2 floats of the context's scratch), copied to the host, decoded
+ * there, and the decoded map goes back for the last step.  Synchronises the stream.
+ * PHIMVS_E_ARG also for a cost above C_max + k1 k2 at a sampled hypothesis (no positive
+ * potential). */
 int phimvs_phi_select(phimvs_ctx* ctx, int width, int height, const float* depth, const float* hyp,
                       const float* cost, const phimvs_phi_params* p, float* depth_out);
 

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -1247,38 +1248,37 @@ int phimvs_phi_select(phimvs_ctx* c, int width, int height, const float* depth, 
   if (pp) p = *pp;
   HIPCHECK(c, hipSetDevice(c->device));
   const int W = width, H = height;
-  const size_t n = (size_t)W * H;
-  std::vector<float> d(n), hy(4 * n), co(4 * n);
-  HIPCHECK(c, hipMemcpyAsync(d.data(), depth, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-  HIPCHECK(c, hipMemcpyAsync(hy.data(), hyp, 4 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-  HIPCHECK(c, hipMemcpyAsync(co.data(), cost, 4 * n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-  HIPCHECK(c, hipStreamSynchronize(c->stream));
-  // half size: node (X, Y) takes pixel (2X, 2Y)
+  // half size: node (X, Y) takes pixel (2X, 2Y); the GPU gathers the nodes' inputs (depth,
+  // 4 hypotheses, 4 costs) and the host decodes
   const int W2 = (W + 1) / 2, H2 = (H + 1) / 2;
   const size_t n2 = (size_t)W2 * H2;
-  std::vector<float> d2(n2), h2(4 * n2), c2(4 * n2), dec(n2);
-  std::vector<int32_t> lab(n2);
-  for (int Y = 0; Y < H2; ++Y)
-    for (int X = 0; X < W2; ++X) {
-      const size_t q = (size_t)Y * W2 + X, src = (size_t)(2 * Y) * W + 2 * X;
-      d2[q] = d[src];
-      for (int k = 0; k < 4; ++k) {
-        h2[k * n2 + q] = hy[k * n + src];
-        c2[k * n2 + q] = co[k * n + src];
-      }
-    }
-  if (phimvs_phi_decode_host(W2, H2, d2.data(), h2.data(), c2.data(), p.k1, p.k2, p.k3, PHIMVS_COST_MAX,
-                             p.iterations, lab.data(), dec.data()) != PHIMVS_OK)
-    return fail(c, PHIMVS_E_ARG, "invalid PHI parameters (k1 > 0, k2 > 0, k3 > 1, iterations >= 0)");
-  // back to full size: pixel (x, y) takes node (x / 2, y / 2)
-  std::vector<float> ref(n);
-  for (int y = 0; y < H; ++y)
-    for (int x = 0; x < W; ++x) ref[(size_t)y * W + x] = dec[(size_t)(y / 2) * W2 + x / 2];
   int rc;
-  if ((rc = ensure(c, c->io_a, n))) return rc;
-  HIPCHECK(c, hipMemcpyAsync(c->io_a.p, ref.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
-  HIPCHECK(c, launch_phi_select(depth, hyp, c->io_a.p, W, H, depth_out, c->stream));
-  HIPCHECK(c, hipStreamSynchronize(c->stream));  // the host reference map goes out of scope
+  if ((rc = ensure(c, c->io_a, 10 * n2))) return rc;
+  float* half = c->io_a.p;
+  float* dec_d = c->io_a.p + 9 * n2;
+  HIPCHECK(c, launch_phi_half(depth, hyp, cost, W, H, half, c->stream));
+  std::vector<float> h, dec;
+  std::vector<int32_t> lab;
+  try {
+    h.resize(9 * n2);
+    dec.resize(n2);
+    lab.resize(n2);
+  } catch (const std::bad_alloc&) {
+    return fail(c, PHIMVS_E_OOM, "out of host memory for the graph model");
+  }
+  HIPCHECK(c, hipMemcpyAsync(h.data(), half, 9 * n2 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  rc = phimvs_phi_decode_host(W2, H2, h.data(), h.data() + n2, h.data() + 5 * n2, p.k1, p.k2, p.k3, PHIMVS_COST_MAX,
+                              p.iterations, lab.data(), dec.data());
+  if (rc == PHIMVS_E_OOM) return fail(c, rc, "out of host memory in the graph-model decoder");
+  if (rc == PHIMVS_E_UNSUPPORTED) return fail(c, rc, "graph model too large for the decoder (2^27 nodes or more)");
+  if (rc != PHIMVS_OK)
+    return fail(c, PHIMVS_E_ARG,
+                "invalid PHI parameters or costs (k1 > 0, k2 > 0, k3 > 1, iterations >= 0, cost <= C_max + k1 k2)");
+  // back to full size in the kernel: pixel (x, y) reads node (x / 2, y / 2)
+  HIPCHECK(c, hipMemcpyAsync(dec_d, dec.data(), n2 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(c, launch_phi_select(depth, hyp, dec_d, W, H, depth_out, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));  // the host copy of the decoded map goes out of scope
   return PHIMVS_OK;
 }
 

@@ -164,7 +164,12 @@ hipError_t phi_scratch_get(int device, uint64_t** p);
 hipError_t launch_phi_hypotheses(const float* depth, int W, int H, uint64_t* bits, float* hyp, hipStream_t st);
 hipError_t launch_phi_planes(const float* hyp, size_t n, float* planes, hipStream_t st);
 hipError_t launch_phi_mask_cost(const float* hyp, size_t n, float cmax, float* cost, hipStream_t st);
-hipError_t launch_phi_select(const float* depth, const float* hyp, const float* ref, int W, int H, float* out,
+// node (X, Y) of the half-size graph from pixel (2X, 2Y): depth, 4 hypothesis planes, 4
+// cost planes, one after the other in half (9 (W+1)/2 (H+1)/2 floats)
+hipError_t launch_phi_half(const float* depth, const float* hyp, const float* cost, int W, int H, float* half,
+                           hipStream_t st);
+// dec: the decoded half-size depth ((W+1)/2 x (H+1)/2)
+hipError_t launch_phi_select(const float* depth, const float* hyp, const float* dec, int W, int H, float* out,
                              hipStream_t st);
 hipError_t launch_phi_normals(const float* depth, int W, int H, const PhiCam& cam, float* normal, hipStream_t st);
 

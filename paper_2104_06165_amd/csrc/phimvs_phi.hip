@@ -176,9 +176,26 @@ __global__ void phi_mask_cost_kernel(const float* __restrict__ hyp, size_t n, fl
   if (!(hyp[i] > 0.0f)) cost[i] = cmax;
 }
 
-// each pixel without depth takes the hypothesis closest to the reference map
+// the graph model's inputs at half size, node (X, Y) from pixel (2X, 2Y), in one array:
+// depth (W2 H2), then the 4 hypothesis planes, then the 4 cost planes
+__global__ void phi_half_kernel(const float* __restrict__ depth, const float* __restrict__ hyp,
+                                const float* __restrict__ cost, int W, int H, int W2, int H2,
+                                float* __restrict__ half) {
+  const int X = blockIdx.x * blockDim.x + threadIdx.x, Y = blockIdx.y;
+  if (X >= W2 || Y >= H2) return;
+  const size_t q = (size_t)Y * W2 + X, n2 = (size_t)W2 * H2;
+  const size_t p = (size_t)(2 * Y) * W + 2 * X, plane = (size_t)W * H;
+  half[q] = depth[p];
+  for (int k = 0; k < 4; ++k) {
+    half[(1 + k) * n2 + q] = hyp[k * plane + p];
+    half[(5 + k) * n2 + q] = cost[k * plane + p];
+  }
+}
+
+// each pixel without depth takes the hypothesis closest to the reference map: the decoded
+// half-size depth dec, pixel (x, y) reading node (x / 2, y / 2)
 __global__ void phi_select_kernel(const float* __restrict__ depth, const float* __restrict__ hyp,
-                                  const float* __restrict__ ref, int W, int H, float* __restrict__ out) {
+                                  const float* __restrict__ dec, int W, int H, int W2, float* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= W || y >= H) return;
   const size_t p = (size_t)y * W + x, plane = (size_t)W * H;
@@ -187,7 +204,7 @@ __global__ void phi_select_kernel(const float* __restrict__ depth, const float* 
     out[p] = d;
     return;
   }
-  const double r = ref[p];
+  const double r = dec[(size_t)(y >> 1) * W2 + (x >> 1)];
   float best = 0.0f;
   double bd = 0.0;
   if (r > 0.0)
@@ -309,9 +326,19 @@ hipError_t launch_phi_mask_cost(const float* hyp, size_t n, float cmax, float* c
   return hipGetLastError();
 }
 
-hipError_t launch_phi_select(const float* depth, const float* hyp, const float* ref, int W, int H, float* out,
+hipError_t launch_phi_half(const float* depth, const float* hyp, const float* cost, int W, int H, float* half,
+                           hipStream_t st) {
+  const int W2 = (W + 1) / 2, H2 = (H + 1) / 2;
+  hipLaunchKernelGGL(pmp::phi_half_kernel, dim3((W2 + 255) / 256, H2), dim3(256), 0, st, depth, hyp, cost, W, H, W2,
+                     H2, half);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_select(const float* depth, const float* hyp, const float* dec, int W, int H, float* out,
                              hipStream_t st) {
-  hipLaunchKernelGGL(pmp::phi_select_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, depth, hyp, ref, W, H, out);
+  const int W2 = (W + 1) / 2;
+  hipLaunchKernelGGL(pmp::phi_select_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, depth, hyp, dec, W, H, W2,
+                     out);
   return hipGetLastError();
 }
 
