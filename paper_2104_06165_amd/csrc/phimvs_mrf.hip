@@ -10,6 +10,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <functional>
 #include <limits>
 #include <memory>
 #include <new>
@@ -21,9 +22,6 @@
 namespace {
 
 constexpr int kMaxLab = 4;
-// tiles of the sweep schedule (nodes): a tile depends on its left and upper tiles in a
-// forward sweep, on its right and lower tiles in a backward sweep
-constexpr int kTileH = 32, kTileW = 64;
 constexpr unsigned kMaxThreads = 16;
 
 // symmetric in its arguments, bit for bit: (h1, h2) and (h2, h1) take the same branch values
@@ -34,32 +32,70 @@ double edge_energy(double h1, double h2, double k3) {
 }
 
 unsigned worker_count(size_t nodes) {
-  if (nodes < (size_t)kTileH * kTileW * 4) return 1;
+  if (nodes < 8192) return 1;
   const unsigned hw = std::thread::hardware_concurrency();
   return std::max(1u, std::min(hw, kMaxThreads));
 }
 
-// runs work() on up to T threads, the calling thread included (if a thread cannot be
-// started, the others share its part: every work() drains a common counter)
-template <class F>
-void on_threads(unsigned T, F&& work) {
-  std::vector<std::thread> th;
-  for (unsigned t = 1; t < T; ++t) {
-    try {
-      th.emplace_back(work);
-    } catch (...) {
-      break;
+// Host threads kept for one decoding: run(f) runs f on every member, the calling thread
+// included, and returns once all have finished it.  Members wait for the next job by
+// yielding.  If a thread cannot be started the team is smaller; every job below shares its
+// work through counters, so any team size gives the same result.
+class Team {
+ public:
+  explicit Team(unsigned want) {
+    for (unsigned t = 1; t < want; ++t) {
+      try {
+        th_.emplace_back([this] { member(); });
+      } catch (...) {
+        break;
+      }
+    }
+    n_ = (unsigned)th_.size() + 1;
+    ready_.store(true, std::memory_order_release);
+  }
+  ~Team() {
+    stop_ = true;
+    gen_.fetch_add(1, std::memory_order_release);
+    for (auto& x : th_) x.join();
+  }
+  Team(const Team&) = delete;
+  Team& operator=(const Team&) = delete;
+  unsigned size() const { return n_; }
+  void run(const std::function<void()>& f) {
+    job_ = &f;
+    done_.store(0, std::memory_order_relaxed);
+    gen_.fetch_add(1, std::memory_order_release);
+    f();
+    while (done_.load(std::memory_order_acquire) != n_ - 1) std::this_thread::yield();
+  }
+
+ private:
+  void member() {
+    while (!ready_.load(std::memory_order_acquire)) std::this_thread::yield();
+    unsigned seen = 0;
+    for (;;) {
+      unsigned g;
+      while ((g = gen_.load(std::memory_order_acquire)) == seen) std::this_thread::yield();
+      seen = g;
+      if (stop_) return;
+      (*job_)();
+      done_.fetch_add(1, std::memory_order_acq_rel);
     }
   }
-  work();
-  for (auto& x : th) x.join();
-}
+  std::vector<std::thread> th_;
+  unsigned n_ = 1;
+  std::atomic<bool> ready_{false};
+  std::atomic<unsigned> gen_{0}, done_{0};
+  bool stop_ = false;
+  const std::function<void()>* job_ = nullptr;
+};
 
 // f(y0, y1) over blocks of rows
 template <class F>
-void parallel_rows(int H, unsigned T, F&& f) {
+void parallel_rows(Team& team, int H, F&& f) {
   std::atomic<int> next{0};
-  on_threads(T, [&] {
+  team.run([&] {
     for (;;) {
       const int y = next.fetch_add(16);
       if (y >= H) break;
@@ -68,36 +104,50 @@ void parallel_rows(int H, unsigned T, F&& f) {
   });
 }
 
+// The tiles of the sweep schedule: 32 x 64 nodes, halved (down to 8 x 16) until each
+// anti-diagonal of tiles can hold two per thread
+struct Tiling {
+  int th = 32, tw = 64, nx = 0, ny = 0;
+  std::vector<int> order;  // tiles by anti-diagonal
+  Tiling(int W, int H, unsigned T) {
+    for (;;) {
+      nx = (W + tw - 1) / tw;
+      ny = (H + th - 1) / th;
+      if (th <= 8 || (unsigned)std::min(nx, ny) >= 2 * T) break;
+      th /= 2;
+      tw /= 2;
+    }
+    order.reserve((size_t)nx * ny);
+    for (int s = 0; s < nx + ny - 1; ++s)
+      for (int ty = 0; ty < ny; ++ty)
+        if (s - ty >= 0 && s - ty < nx) order.push_back(ty * nx + (s - ty));
+  }
+};
+
 // visit(i) for every node of a W x H grid, each after its left and upper neighbours
 // (forward) or after its right and lower neighbours (backward): tiles are handed out by
 // anti-diagonal, a tile starts once the tiles it borders in that direction are done, and
 // inside a tile the nodes go in raster (reverse raster) order
 template <class F>
-void wavefront(int W, int H, unsigned T, bool forward, F&& visit) {
-  const int nTX = (W + kTileW - 1) / kTileW, nTY = (H + kTileH - 1) / kTileH;
-  const int n_tiles = nTX * nTY;
-  std::vector<int> order;
-  order.reserve(n_tiles);
-  for (int s = 0; s < nTX + nTY - 1; ++s)
-    for (int ty = 0; ty < nTY; ++ty)
-      if (s - ty >= 0 && s - ty < nTX) order.push_back(ty * nTX + (s - ty));
+void wavefront(Team& team, const Tiling& tl, int W, int H, bool forward, F&& visit) {
+  const int n_tiles = tl.nx * tl.ny;
   std::unique_ptr<std::atomic<int>[]> done(new std::atomic<int>[n_tiles]);
   for (int t = 0; t < n_tiles; ++t) done[t].store(0, std::memory_order_relaxed);
   std::atomic<int> next{0};
   const int dir = forward ? -1 : 1;
-  on_threads(T, [&] {
+  team.run([&] {
     for (;;) {
       const int k = next.fetch_add(1);
       if (k >= n_tiles) break;
-      const int t = forward ? order[k] : order[n_tiles - 1 - k];
-      const int tx = t % nTX, ty = t / nTX;
+      const int t = forward ? tl.order[k] : tl.order[n_tiles - 1 - k];
+      const int tx = t % tl.nx, ty = t / tl.nx;
       // those tiles come earlier in the hand-out order, so someone already holds them
-      if (tx + dir >= 0 && tx + dir < nTX)
-        while (!done[ty * nTX + tx + dir].load(std::memory_order_acquire)) std::this_thread::yield();
-      if (ty + dir >= 0 && ty + dir < nTY)
-        while (!done[(ty + dir) * nTX + tx].load(std::memory_order_acquire)) std::this_thread::yield();
-      const int x0 = tx * kTileW, x1 = std::min(W, x0 + kTileW);
-      const int y0 = ty * kTileH, y1 = std::min(H, y0 + kTileH);
+      if (tx + dir >= 0 && tx + dir < tl.nx)
+        while (!done[ty * tl.nx + tx + dir].load(std::memory_order_acquire)) std::this_thread::yield();
+      if (ty + dir >= 0 && ty + dir < tl.ny)
+        while (!done[(ty + dir) * tl.nx + tx].load(std::memory_order_acquire)) std::this_thread::yield();
+      const int x0 = tx * tl.tw, x1 = std::min(W, x0 + tl.tw);
+      const int y0 = ty * tl.th, y1 = std::min(H, y0 + tl.th);
       if (forward) {
         for (int y = y0; y < y1; ++y)
           for (int x = x0; x < x1; ++x) visit(y * W + x);
@@ -131,14 +181,15 @@ extern "C" int phimvs_phi_decode_host(int width, int height, const float* depth,
   try {
     const int W = width, H = height, N = W * H;
     const size_t plane = (size_t)N;
-    const unsigned T = worker_count(plane);
+    Team team(worker_count(plane));
+    const Tiling tiling(W, H, team.size());
     // node i: ns[i] states (0: not part of the model); state l: hypothesis lab (-1: the
     // fixed depth), depth val, unary -log phi_n
     std::vector<uint8_t> ns(N, 0), live(N, 0);
     std::vector<int8_t> lab((size_t)N * kMaxLab);
     std::vector<double> val((size_t)N * kMaxLab), un((size_t)N * kMaxLab);
     std::atomic<bool> bad{false};
-    parallel_rows(H, T, [&](int y0, int y1) {
+    parallel_rows(team, H, [&](int y0, int y1) {
       for (int i = y0 * W; i < y1 * W; ++i) {
         const size_t q = (size_t)i * kMaxLab;
         if (depth[i] > 0.0f) {
@@ -170,7 +221,7 @@ extern "C" int phimvs_phi_decode_host(int width, int height, const float* depth,
     const int step[4] = {-W, -1, 1, W};
     std::vector<double> gamma(N, 1.0);
     std::vector<int64_t> er(N, -1), ed(N, -1), row_start(H + 1, 0);
-    parallel_rows(H, T, [&](int y0, int y1) {
+    parallel_rows(team, H, [&](int y0, int y1) {
       for (int y = y0; y < y1; ++y) {
         int64_t count = 0;
         for (int x = 0, i = y * W; x < W; ++x, ++i) {
@@ -195,7 +246,7 @@ extern "C" int phimvs_phi_decode_host(int width, int height, const float* depth,
     });
     for (int y = 0; y < H; ++y) row_start[y + 1] += row_start[y];
     std::unique_ptr<double[]> energy(new double[(size_t)row_start[H]]);
-    parallel_rows(H, T, [&](int y0, int y1) {
+    parallel_rows(team, H, [&](int y0, int y1) {
       for (int y = y0; y < y1; ++y)
         for (int i = y * W; i < (y + 1) * W; ++i)
           for (int d = 2; d < 4; ++d) {
@@ -224,7 +275,7 @@ extern "C" int phimvs_phi_decode_host(int width, int height, const float* depth,
     // messages into node i from its neighbour in direction d; those into a single-state
     // node are never written (they stay 0)
     std::unique_ptr<double[]> msg(new double[(size_t)N * 4 * kMaxLab]);
-    parallel_rows(H, T, [&](int y0, int y1) {
+    parallel_rows(team, H, [&](int y0, int y1) {
       std::fill(&msg[(size_t)y0 * W * 4 * kMaxLab], &msg[(size_t)y1 * W * 4 * kMaxLab], 0.0);
     });
     auto M = [&](int i, int d) -> double* { return &msg[((size_t)i * 4 + d) * kMaxLab]; };
@@ -268,12 +319,12 @@ extern "C" int phimvs_phi_decode_host(int width, int height, const float* depth,
       }
     };
     for (int it = 0; it < iterations; ++it) {
-      wavefront(W, H, T, true, [&](int i) { update(i, 2, it == 0); });
-      wavefront(W, H, T, false, [&](int i) { update(i, 0, it == 0); });
+      wavefront(team, tiling, W, H, true, [&](int i) { update(i, 2, it == 0); });
+      wavefront(team, tiling, W, H, false, [&](int i) { update(i, 0, it == 0); });
     }
     // decode in order: earlier neighbours contribute their chosen state, later ones their messages
     std::vector<int8_t> pick(N, -1);
-    wavefront(W, H, T, true, [&](int i) {
+    wavefront(team, tiling, W, H, true, [&](int i) {
       label_out[i] = -1;
       depth_out[i] = 0.0f;
       const int n = ns[i];

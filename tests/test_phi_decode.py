@@ -97,6 +97,7 @@ def test_decoder_arguments():
     (33, 1000, 0.3, 1.0, 2.0, 1),    # one and a bit tile rows
     (1000, 9, 0.3, 2.0, 1.5, 2),     # a single tile column
     (129, 193, 0.0, 1.0, 2.0, 0),    # no message passing: the greedy raster decoding
+    (520, 1030, 0.6, 1.0, 2.0, 2),   # large enough for the largest tiles on 8 threads
 ])
 def test_decoder_equals_the_oracle_trws(H, W, fixed, k1, k3, iters):
     r = np.random.default_rng(H * 7 + W)
