@@ -850,7 +850,13 @@ def main():
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "eval_kernel (evaluate-and-select)", "avg_launch_ms": avg_launch_ms,
                      "launches_per_step": launches_per_step,
-                     "kernel_share_of_step": kernel_ms / (elapsed * 1e3)},
+                     "kernel_share_of_step": kernel_ms / (elapsed * 1e3),
+                     # every candidate the method offers counted as scored (score_all = 2), over the
+                     # same kernel time: the rate of the method's nominal work that leaving out the
+                     # candidates that cannot win gives; achieved and frac count only those scored
+                     "achieved_nominal": (achieved * hyp_by_level[2] / n_hyp) if 2 in hyp_by_level else None,
+                     "frac_nominal": (achieved * hyp_by_level[2] / n_hyp / PEAK_FP32_VECTOR_TFLOPS)
+                     if 2 in hyp_by_level else None},
         "pcie_inclusive_ms": pcie_ms,
         "hypotheses_per_step": n_hyp,
         "hypotheses_per_step_by_score_all": {str(k): v for k, v in sorted(hyp_by_level.items())},
