@@ -1094,7 +1094,10 @@ double oracle_phi_map_bruteforce(const float* depth, const float* hyp, const flo
 // the up and left neighbours plus the messages from the right and down neighbours (these
 // terms added in the order up, left, right, down), the first such state on ties.
 // label[i] receives k (-1 for a fixed node or one without states), value[i] its depth (0
-// without states).
+// without states).  Parity unpinned in part: on a forest TRW is exact and the tests hold
+// it to the enumerated MAP, but the weights gamma and the exact sweep schedule act on
+// graphs with loops alone, where TRW has no exact reference; there they are held only to
+// near-optimality.
 void oracle_phi_trws(const float* depth, const float* hyp, const float* cost, int W, int H, double k1, double k2,
                      double k3, double cmax, int iterations, int32_t* label, float* value) {
   const int N = W * H;
