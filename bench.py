@@ -221,6 +221,55 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_batched_refs(args):
+    """The batched workload's references one at a time through the single-view entry point
+    (one warm-up run each, then one run with the exact hypothesis count and the evaluate
+    kernel's time): scored tap-views per second of evaluate time, per reference and per
+    size class.  --job K runs only the K-th reference (e.g. under a counter profiler)."""
+    import torch
+
+    import paper_2104_06165_amd as pm
+    import scenegen as sg
+
+    mv = sg.make_multiview_scene(seed=sg.SCENE_SEEDS["batched"], device="cuda")
+    ctx = pm.Context(0)
+    ctx.set_views(mv.images, mv.K, mv.R, mv.t, mv.depth_ranges)
+    if args.tuning:
+        rows, persistent, wgs = (int(v) for v in args.tuning.split(","))
+        ctx.set_tuning(pm.Tuning(rows, bool(persistent), wgs))
+    iters = 8
+    refs = []
+    for i, (ref, srcs, (win, dil)) in enumerate(zip(mv.refs, mv.sources, mv.windows)):
+        if args.job >= 0 and i != args.job:
+            continue
+        p = pm.Params(top_k=min(5, len(srcs)), seed=sg.PM_SEED + i)
+        if args.job < 0:
+            ctx.patchmatch(ref, srcs, win, dil, iters, p)  # warm-up
+        ctx.diag_enable(pm.DIAG_COUNT | pm.DIAG_TIME)
+        ctx.patchmatch(ref, srcs, win, dil, iters, p)
+        torch.cuda.synchronize()
+        n_hyp, launches, ms = ctx.diag_read()
+        ctx.diag_enable(0)
+        R = (win - 1) // (2 * dil)
+        H, W = mv.images[ref].shape
+        tv = n_hyp * len(srcs) * (2 * R + 1) ** 2
+        refs.append({"job": i, "width": W, "height": H, "n_src": len(srcs),
+                     "larger_sources": sum(1 for s in srcs if mv.images[s].size > mv.images[ref].size),
+                     "hypotheses": n_hyp, "evaluate_ms": ms, "launches": launches,
+                     "tap_views_per_s": tv / (ms * 1e-3)})
+        log(f"[bench] job {i}: {W}x{H}, {len(srcs)} sources: {tv / (ms * 1e-3) / 1e12:.3f}e12 tap-views/s")
+    classes = {}
+    for r in refs:
+        classes.setdefault(f"{r['width']}x{r['height']}", []).append(r["tap_views_per_s"])
+    line = {"metric": "scored tap-views per second of evaluate time, batched workload's references one by one",
+            "value": float(np.mean([r["tap_views_per_s"] for r in refs])), "unit": "tap-views/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic (seeded 40-camera scene, seed 4)",
+            "config": {"workload": "batched_refs: each reference of the batched workload alone, 8 iterations",
+                       "tuning": ctx.get_tuning().__dict__},
+            "by_size": {k: {"min": min(v), "max": max(v)} for k, v in classes.items()}, "references": refs}
+    print(json.dumps(line), flush=True)
+
+
 def bench_filter(ctx, mv, jobs, outs, reps=5):
     """Geometric-consistency filter of the batch's 24 depth maps, each against the other
     references among its sources (Sec. III-D).  Algorithmic HBM bytes per reference pixel:
@@ -680,7 +729,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="highres",
-                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "resize", "taps", "train", "ceiling"])
+                    choices=["highres", "mid", "mid_dense", "tiny", "batched", "batched_refs", "resize", "taps", "train",
+                             "ceiling"])
     ap.add_argument("--cpu-iters", type=int, default=1,
                     help="iterations of the single-threaded oracle's sample (the all-thread runs take the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -699,6 +749,8 @@ def main():
                     help="lanes sharing each pixel (2..16: split tap sums, for small references); 0: one lane")
     ap.add_argument("--tuning", default="", metavar="ROWS,PERSISTENT,WGS",
                     help="evaluate-kernel launch configuration (batched workload: instead of autotuning)")
+    ap.add_argument("--job", type=int, default=-1,
+                    help="batched_refs workload: only this reference (index in the batch); -1: all 24")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM-counter calibration) and exit")
     args = ap.parse_args()
@@ -727,6 +779,8 @@ def main():
     wl = args.workload
     if wl == "batched":
         return bench_batched(args)
+    if wl == "batched_refs":
+        return bench_batched_refs(args)
     if wl == "resize":
         return bench_resize(args)
     if wl == "taps":
