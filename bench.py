@@ -54,6 +54,14 @@ def measured_traffic(kernel_file: str, profile: str):
         return None
 
 
+def parse_tuning(pm, text):
+    """ROWS,PERSISTENT,WGS[,ORDER_BY_DEPTH] -> the library's launch configuration."""
+    v = [int(x) for x in text.split(",")]
+    if len(v) not in (3, 4):
+        raise SystemExit("--tuning takes ROWS,PERSISTENT,WGS[,ORDER_BY_DEPTH]")
+    return pm.Tuning(v[0], bool(v[1]), v[2], order_by_depth=bool(v[3]) if len(v) == 4 else False)
+
+
 def nominal_tap_views(valid_px, n_src, taps, iters):
     # 1 initial hypothesis + per iteration 8 propagation + 3 refinement candidates
     return valid_px * (1 + 11 * iters) * n_src * taps
@@ -161,14 +169,15 @@ def bench_batched(args):
         jobs.append(dict(ref=ref, srcs=srcs, window=win, dilation=dil,
                          params=pm.Params(top_k=min(5, len(srcs)), seed=sg.PM_SEED + i)))
     if args.tuning:
-        rows, persistent, wgs = (int(v) for v in args.tuning.split(","))
-        ctx.set_tuning(pm.Tuning(rows, bool(persistent), wgs))
+        ctx.set_tuning(parse_tuning(pm, args.tuning))
         best, allr = ctx.get_tuning(), []
-        log(f"[bench] launch configuration fixed: rows{rows}/p{persistent}/{wgs}")
+        log(f"[bench] launch configuration fixed: rows{best.tile_rows}/p{int(best.persistent)}/{best.wgs_per_cu}"
+            f"{'/depth' if best.order_by_depth else ''}")
     else:
         best, allr = ctx.autotune(jobs, iters=args.autotune_iters)
-        log("[bench] autotune: " + ", ".join(f"rows{r.tile_rows}/p{int(r.persistent)}/{r.wgs_per_cu}={r.ms:.1f}ms"
-                                             for r in allr))
+        log("[bench] autotune: " + ", ".join(
+            f"rows{r.tile_rows}/p{int(r.persistent)}/{r.wgs_per_cu}{'/depth' if r.order_by_depth else ''}={r.ms:.1f}ms"
+            for r in allr))
     outs = [dict(depth=torch.empty(mv.images[j["ref"]].shape, dtype=torch.float32, device="cuda"),
                  normal=torch.empty(mv.images[j["ref"]].shape + (3,), dtype=torch.float32, device="cuda"),
                  cost=torch.empty(mv.images[j["ref"]].shape, dtype=torch.float32, device="cuda")) for j in jobs]
@@ -235,8 +244,7 @@ def bench_batched_refs(args):
     ctx = pm.Context(0)
     ctx.set_views(mv.images, mv.K, mv.R, mv.t, mv.depth_ranges)
     if args.tuning:
-        rows, persistent, wgs = (int(v) for v in args.tuning.split(","))
-        ctx.set_tuning(pm.Tuning(rows, bool(persistent), wgs))
+        ctx.set_tuning(parse_tuning(pm, args.tuning))
     iters = 8
     refs = []
     for i, (ref, srcs, (win, dil)) in enumerate(zip(mv.refs, mv.sources, mv.windows)):
@@ -747,7 +755,7 @@ def main():
                     help="do not count the hypotheses of the other score_all settings (extra untimed runs)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes sharing each pixel (2..16: split tap sums, for small references); 0: one lane")
-    ap.add_argument("--tuning", default="", metavar="ROWS,PERSISTENT,WGS",
+    ap.add_argument("--tuning", default="", metavar="ROWS,PERSISTENT,WGS[,ORDER_BY_DEPTH]",
                     help="evaluate-kernel launch configuration (batched workload: instead of autotuning)")
     ap.add_argument("--job", type=int, default=-1,
                     help="batched_refs workload: only this reference (index in the batch); -1: all 24")
@@ -800,8 +808,7 @@ def main():
     ctx = pm.Context(0)
     ctx.set_scene(scene)
     if args.tuning:
-        rows, persistent, wgs = (int(v) for v in args.tuning.split(","))
-        ctx.set_tuning(pm.Tuning(rows, bool(persistent), wgs))
+        ctx.set_tuning(parse_tuning(pm, args.tuning))
     n_src = len(scene.images) - 1
     srcs = list(range(1, n_src + 1))
     params = pm.Params(top_k=solver["top_k"], bilateral=True, sigma_spatial_px=(solver["window"] - 1) / 2.0,

@@ -80,7 +80,7 @@ struct phimvs_ctx {
   bool prepared = false;
   Batch single;                   // the step-wise interface's job
   Batch multi;                    // phimvs_patchmatch_batch
-  phimvs_tuning tuning{4, 1, 4, 0.0};  // persistent, 4 workgroups per CU (the occupancy limit)
+  phimvs_tuning tuning{4, 1, 4, 0, 0.0};  // persistent, 4 workgroups per CU (the occupancy limit), pixel order
   size_t eval_lds_max = 0;                // largest dynamic LDS of an evaluate launch on this device
   DevBuf<float> io_a, io_b, io_c, io_d;  // staging for host inputs / outputs
   DevBuf<FilterNbr> filter_nbrs;          // neighbour table of the consistency filter
@@ -455,6 +455,7 @@ int eval_grid(const phimvs_ctx* c, const Batch& b, bool persistent) {
 int run_eval(phimvs_ctx* c, Batch& b, Launch L, unsigned int* queue) {
   const bool persistent = c->tuning.persistent != 0;
   L.persistent = persistent ? 1 : 0;
+  L.order_by_depth = c->tuning.order_by_depth ? 1 : 0;
   L.queue = queue;
   if (c->diag & PHIMVS_DIAG_COUNT) L.count = c->diag_count;
   const bool split = b.jobs.size() == 1 && b.jobs[0].A.lanes > 1;
@@ -686,7 +687,7 @@ int run_single(phimvs_ctx* c, int ref, const int* srcs, int n_srcs, int window, 
     std::snprintf(ptrs, sizeof ptrs, "#%p#%p", (void*)b.d_jobs, (void*)b.queues.p);
     const std::string gkey = b.layout_key + "#" + std::to_string(iters) + "#" +
                              std::to_string(c->tuning.persistent) + "#" + std::to_string(c->tuning.wgs_per_cu) +
-                             ptrs;
+                             "#" + std::to_string(c->tuning.order_by_depth) + ptrs;
     rc = run_sequence_graph(c, b, gkey, iters);
   }
   if (rc) return rc;
@@ -1338,7 +1339,7 @@ int phimvs_patchmatch_batch(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, i
   }
   if ((rc = ensure(c, b.queues, (size_t)8 * (2 + 4 * iters)))) return rc;
   const std::string gkey = key + "#" + std::to_string(iters) + "#" + std::to_string(c->tuning.persistent) + "#" +
-                           std::to_string(c->tuning.wgs_per_cu);
+                           std::to_string(c->tuning.wgs_per_cu) + "#" + std::to_string(c->tuning.order_by_depth);
   if (!use_graph || c->diag) return issue_sequence(c, b, iters, true);
   return run_sequence_graph(c, b, gkey, iters);
 }
@@ -1349,6 +1350,7 @@ int phimvs_set_tuning(phimvs_ctx* c, const phimvs_tuning* t) {
     return fail(c, PHIMVS_E_ARG, "tile_rows must be 1, 2 or 4");
   if (t->persistent && (t->wgs_per_cu < 1 || t->wgs_per_cu > 16))
     return fail(c, PHIMVS_E_ARG, "wgs_per_cu must be in [1, 16] for persistent launches");
+  if (t->order_by_depth != 0 && t->order_by_depth != 1) return fail(c, PHIMVS_E_ARG, "order_by_depth must be 0 or 1");
   HIPCHECK(c, hipSetDevice(c->device));
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   const bool shape = t->tile_rows != c->tuning.tile_rows;
@@ -1374,8 +1376,10 @@ int phimvs_autotune(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, int iters
                     int* n_results) {
   if (!c) return PHIMVS_E_ARG;
   HIPCHECK(c, hipSetDevice(c->device));
-  const phimvs_tuning cands[] = {{4, 0, 0, 0}, {2, 0, 0, 0}, {1, 0, 0, 0}, {4, 1, 2, 0}, {4, 1, 3, 0},
-                                 {4, 1, 4, 0}, {4, 1, 6, 0}, {2, 1, 3, 0}, {2, 1, 4, 0}, {1, 1, 4, 0}};
+  // ten launch shapes in pixel order; the last trial is the fastest of them in depth order
+  phimvs_tuning cands[] = {{4, 0, 0, 0, 0}, {2, 0, 0, 0, 0}, {1, 0, 0, 0, 0}, {4, 1, 2, 0, 0},
+                           {4, 1, 3, 0, 0}, {4, 1, 4, 0, 0}, {4, 1, 6, 0, 0}, {2, 1, 3, 0, 0},
+                           {2, 1, 4, 0, 0}, {1, 1, 4, 0, 0}, {4, 1, 4, 1, 0}};
   const int n = (int)(sizeof(cands) / sizeof(cands[0]));
   const phimvs_tuning prev = c->tuning;
   phimvs_tuning best{};
@@ -1393,6 +1397,11 @@ int phimvs_autotune(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, int iters
   // a configuration that fails (its launch refused, say) is reported with ms = +inf and
   // passed over; the others are still timed
   for (int i = 0; i < n; ++i) {
+    if (i == n - 1 && best_ms < HUGE_VAL) {
+      cands[i] = best;
+      cands[i].order_by_depth = 1;
+      cands[i].ms = 0.0;
+    }
     phimvs_tuning r = cands[i];
     r.ms = HUGE_VAL;
     int rc = phimvs_set_tuning(c, &cands[i]);
@@ -1405,8 +1414,8 @@ int phimvs_autotune(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, int iters
     if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(c, PHIMVS_E_DEVICE, "hipEventElapsedTime");
     if (rc) {
       failures += " [rows " + std::to_string(cands[i].tile_rows) + ", persistent " +
-                  std::to_string(cands[i].persistent) + ", " + std::to_string(cands[i].wgs_per_cu) + "/CU: " + c->err +
-                  "]";
+                  std::to_string(cands[i].persistent) + ", " + std::to_string(cands[i].wgs_per_cu) + "/CU, order " +
+                  std::to_string(cands[i].order_by_depth) + ": " + c->err + "]";
     } else {
       r.ms = ms;
       if (ms < best_ms) {

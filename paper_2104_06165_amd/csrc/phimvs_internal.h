@@ -15,6 +15,8 @@ constexpr int kBlock = 256;        // threads per evaluate workgroup
 // var_a (3 kBlock), cost per (slot, pixel) (8 kBlock), the (pixel, slot) list as 16-bit
 // entries (4 kBlock) and the waves' counts (8)
 constexpr int kCompactLds = 15 * kBlock + 8;
+constexpr int kDepthBuckets = 64;  // inverse-depth buckets of the depth-ordered work list (one wave scans them)
+static_assert(kDepthBuckets == 64, "the bucket scan is one 64-lane wave");
 constexpr int kMaxTopK = PHIMVS_MAX_SOURCES;
 constexpr int kMaxTaps1D = 31;     // taps per window side
 
@@ -83,6 +85,8 @@ struct Launch {
   int total_tiles, total_cblk;
   int xcd_len[8];                      // evaluate tiles of each XCD's list
   int persistent;                      // evaluate: tiles pulled from per-XCD queues
+  int order_by_depth;                  // evaluate: work items of launches with <= 3 candidates per
+                                       // pixel handed out by the candidate's inverse depth
   int frac;                            // evaluate: some job uses the window-resize scheme
   int skip_current;                    // propagation candidates: drop those equal to the pixel's current
                                        // plane (only when every stored cost is its plane's own cost)

@@ -957,11 +957,20 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   ref_lds[kBlock + threadIdx.x] = rp.mu_a;
   ref_lds[2 * kBlock + threadIdx.x] = rp.var_a;
   unsigned live = 0;  // non-empty slots
+  float dk[3] = {0.f, 0.f, 0.f};  // their depths (launches of up to 3 candidates)
   if (valid)
-    for (int k = 0; k < L.ncand; ++k)
-      if (!__builtin_isnan(gl(J.cand)[k * plane_sz + cidx].w)) live |= 1u << k;
+    for (int k = 0; k < L.ncand; ++k) {
+      const float d = gl(J.cand)[k * plane_sz + cidx].w;
+      if (!__builtin_isnan(d)) live |= 1u << k;
+      if (k < 3) dk[k] = d;
+    }
   // the list: pixel order, slot order within a pixel (exclusive prefix of the counts over
-  // the workgroup: a scan within each wave, then the totals of the earlier waves)
+  // the workgroup: a scan within each wave, then the totals of the earlier waves); or, with
+  // order_by_depth in a launch of up to 3 candidates, by buckets of the candidate's inverse
+  // depth, so that a wave's lanes sample nearby points of each source.  Each item's cost is
+  // computed on its own and the selection below reads the costs in slot order, so the
+  // order of the list changes no result.
+  const bool by_depth = L.order_by_depth && L.ncand <= 3;
   const int cnt = __popc(live);
   int incl = cnt;
 #pragma unroll
@@ -978,7 +987,39 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
     n_items += wave_total[w];
     if (w < wave) off += wave_total[w];
   }
-  for (unsigned m = live; m; m &= m - 1) item_lds[off++] = (uint16_t)((threadIdx.x << 3) | (__ffs(m) - 1));
+  if (!by_depth) {
+    for (unsigned m = live; m; m &= m - 1) item_lds[off++] = (uint16_t)((threadIdx.x << 3) | (__ffs(m) - 1));
+  } else {
+    // counting sort into kDepthBuckets buckets of 1/d over [1/d_hi, 1/d_lo]: counts, an
+    // exclusive scan by one wave, then each item takes the next place of its bucket (the
+    // order within a bucket is whichever the atomics give; the cost slots of candidates 4..7,
+    // unused here, hold the counters)
+    int* bucket = reinterpret_cast<int*>(cost_lds + 4 * kBlock);
+    if (threadIdx.x < kDepthBuckets) bucket[threadIdx.x] = 0;
+    __syncthreads();
+    const float inv_lo = 1.0f / A.d_hi, scale = (float)kDepthBuckets / (1.0f / A.d_lo - 1.0f / A.d_hi);
+    int bk[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+      if ((live >> k) & 1u) {
+        const int b = (int)((1.0f / dk[k] - inv_lo) * scale);
+        bk[k] = b < 0 ? 0 : (b >= kDepthBuckets ? kDepthBuckets - 1 : b);
+        atomicAdd(&bucket[bk[k]], 1);
+      }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int c0 = bucket[threadIdx.x];
+      int inc = c0;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+      }
+      bucket[threadIdx.x] = inc - c0;
+    }
+    __syncthreads();
+    for (int k = 0; k < 3; ++k)
+      if ((live >> k) & 1u) item_lds[atomicAdd(&bucket[bk[k]], 1)] = (uint16_t)((threadIdx.x << 3) | k);
+  }
   if (L.count && threadIdx.x == 0) atomicAdd(L.count, (unsigned long long)n_items);
   __syncthreads();
   for (int base = wave * 64; base < n_items; base += kBlock) {

@@ -58,10 +58,12 @@ def single_runs(ctx, jobs, iters):
 
 
 TUNINGS = [pm.Tuning(4, False, 0), pm.Tuning(4, True, 3), pm.Tuning(2, True, 4), pm.Tuning(1, False, 0),
-           pm.Tuning(2, False, 0)]
+           pm.Tuning(2, False, 0), pm.Tuning(4, True, 4, order_by_depth=True),
+           pm.Tuning(1, False, 0, order_by_depth=True)]
 
 
-@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"rows{t.tile_rows}-p{int(t.persistent)}-{t.wgs_per_cu}")
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"rows{t.tile_rows}-p{int(t.persistent)}-{t.wgs_per_cu}"
+                                                          f"{'-depth' if t.order_by_depth else ''}")
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_batch_equals_single_runs(ctx, mv, tuning, use_graph):
     iters = 2
@@ -73,6 +75,21 @@ def test_batch_equals_single_runs(ctx, mv, tuning, use_graph):
     for k, ((d, n, c), (rd, rn, rc)) in enumerate(zip(outs, ref)):
         assert torch.equal(d, rd) and torch.equal(n, rn) and torch.equal(c, rc), f"job {k}"
     say(f"batch of {len(jobs)} jobs == single runs ({tuning}, graph={use_graph})")
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_depth_ordered_batch_equals_pixel_order_singles(ctx, mv, use_graph):
+    """The batch in depth order equals the single runs in pixel order, job by job."""
+    iters = 2
+    jobs = jobs_of(mv)
+    ctx.set_tuning(pm.Tuning(4, True, 4))
+    ref = single_runs(ctx, jobs, iters)
+    ctx.set_tuning(pm.Tuning(4, True, 4, order_by_depth=True))
+    outs = ctx.patchmatch_batch(jobs, iters, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for k, ((d, n, c), (rd, rn, rc)) in enumerate(zip(outs, ref)):
+        assert torch.equal(d, rd) and torch.equal(n, rn) and torch.equal(c, rc), f"job {k}"
+    say(f"depth-ordered batch of {len(jobs)} jobs == pixel-order single runs (graph={use_graph})")
 
 
 @pytest.mark.parametrize("use_graph", [False, True])

@@ -314,6 +314,26 @@ def test_patchmatch_parity_tiny(ctx, tiny):
     assert np.all(gd[~m] == 0) and np.all(c.cpu().numpy()[~m] == 2.0) and np.all(nrm.cpu().numpy()[~m] == 0)
 
 
+def test_patchmatch_parity_tiny_depth_ordered(ctx, tiny):
+    """The whole tiny run with its initialisation and refinement work handed out in order of
+    the candidates' inverse depth, against the oracle to the same bar as in pixel order."""
+    scene, cfg = tiny
+    pb = _prep(ctx, scene, cfg)
+    n = len(scene.images) - 1
+    prev = ctx.get_tuning()
+    ctx.set_tuning(pm.Tuning(prev.tile_rows, prev.persistent, prev.wgs_per_cu, order_by_depth=True))
+    try:
+        d, nrm, c = ctx.patchmatch(0, list(range(1, n + 1)), cfg["window"], cfg["dilation"], cfg["iters"],
+                                   params_for(cfg["window"], cfg["top_k"]))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_tuning(prev)
+    od, on, oc = oracle.patchmatch(pb, cfg["iters"])
+    m = pb.valid_mask()
+    frac, bit = compare("patchmatch tiny, depth-ordered work", c.cpu().numpy(), oc, m, d.cpu().numpy(), od)
+    assert frac >= FRAC
+
+
 # ----------------------------------------------------------------------------- edge cases
 @pytest.mark.parametrize("W,H,n_src,window,dilation,top_k,bilateral", [
     (133, 67, 2, 7, 1, 0, True),     # ragged width/height (not multiples of 128 / 4)

@@ -5,7 +5,12 @@ offered it has a cost no lower than the pixel's stored cost; only a strictly low
 is taken.  On the 3200x2130 workload (10 sources, 11x11 taps, 8 iterations) the three
 settings give bitwise the same depth, normal and cost at every pixel, while the number
 of hypotheses scored falls (reported, and asserted to fall at each step); so do they on
-the 160x120 workload, with one lane per pixel and with 16 lanes sharing each pixel."""
+the 160x120 workload, with one lane per pixel and with 16 lanes sharing each pixel.
+
+Likewise, handing a tile's initialisation and refinement work items to the lanes in order
+of the candidates' inverse depth (phimvs_tuning.order_by_depth) instead of pixel order
+gives bitwise the same maps: each item's cost is computed on its own, and the selection
+reads the costs in slot order."""
 import sys
 
 import pytest
@@ -61,5 +66,27 @@ def test_score_all_is_validated():
         ctx.set_scene(scene)
         with pytest.raises(RuntimeError, match="score_all"):
             ctx.patchmatch(0, [1, 2], 11, 1, 1, pm.Params(score_all=3))
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("workload", ["tiny", "highres"])
+def test_depth_ordered_work_lists_change_no_result(workload):
+    scene = sg.workload_scene(workload, device="cuda")
+    sol = sg.SOLVER[workload]
+    ctx = pm.Context(0)
+    try:
+        ctx.set_scene(scene)
+        srcs = list(range(1, len(scene.images)))
+        p = pm.Params(top_k=sol["top_k"], sigma_spatial_px=(sol["window"] - 1) / 2.0, seed=sg.PM_SEED)
+        res = []
+        for order in (False, True):
+            ctx.set_tuning(pm.Tuning(4, True, 4, order_by_depth=order))
+            d, n, c = ctx.patchmatch(0, srcs, sol["window"], sol["dilation"], sol["iters"], p)
+            res.append((d.clone(), n.clone(), c.clone()))
+        (d0, n0, c0), (d1, n1, c1) = res
+        same = torch.equal(d0, d1) and torch.equal(n0, n1) and torch.equal(c0, c1)
+        say(f"{workload}: depth-ordered work lists give the pixel-order maps bitwise: {same}")
+        assert same
     finally:
         ctx.close()
