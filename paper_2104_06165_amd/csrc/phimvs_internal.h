@@ -15,8 +15,8 @@ constexpr int kBlock = 256;        // threads per evaluate workgroup
 // var_a (3 kBlock), cost per (slot, pixel) (8 kBlock), the (pixel, slot) list as 16-bit
 // entries (4 kBlock) and the waves' counts (8)
 constexpr int kCompactLds = 15 * kBlock + 8;
-constexpr int kDepthBuckets = 64;  // inverse-depth buckets of the depth-ordered work list (one wave scans them)
-static_assert(kDepthBuckets == 64, "the bucket scan is one 64-lane wave");
+constexpr int kDepthBuckets = 256;  // inverse-depth buckets of the depth-ordered work list (one per thread)
+static_assert(kDepthBuckets == kBlock, "the bucket scan gives each thread of the workgroup one bucket");
 constexpr int kMaxTopK = PHIMVS_MAX_SOURCES;
 constexpr int kMaxTaps1D = 31;     // taps per window side
 

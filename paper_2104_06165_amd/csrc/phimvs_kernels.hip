@@ -990,12 +990,12 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   if (!by_depth) {
     for (unsigned m = live; m; m &= m - 1) item_lds[off++] = (uint16_t)((threadIdx.x << 3) | (__ffs(m) - 1));
   } else {
-    // counting sort into kDepthBuckets buckets of 1/d over [1/d_hi, 1/d_lo]: counts, an
-    // exclusive scan by one wave, then each item takes the next place of its bucket (the
-    // order within a bucket is whichever the atomics give; the cost slots of candidates 4..7,
-    // unused here, hold the counters)
+    // counting sort into kDepthBuckets (= kBlock) buckets of 1/d over [1/d_hi, 1/d_lo]:
+    // counts, an exclusive scan over the workgroup (one bucket per thread), then each item
+    // takes the next place of its bucket (the order within a bucket is whichever the atomics
+    // give; the cost slots of candidates 4..7, unused here, hold the counters)
     int* bucket = reinterpret_cast<int*>(cost_lds + 4 * kBlock);
-    if (threadIdx.x < kDepthBuckets) bucket[threadIdx.x] = 0;
+    bucket[threadIdx.x] = 0;
     __syncthreads();
     const float inv_lo = 1.0f / A.d_hi, scale = (float)kDepthBuckets / (1.0f / A.d_lo - 1.0f / A.d_hi);
     int bk[3] = {0, 0, 0};
@@ -1006,7 +1006,7 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
         atomicAdd(&bucket[bk[k]], 1);
       }
     __syncthreads();
-    if (threadIdx.x < 64) {
+    {
       const int c0 = bucket[threadIdx.x];
       int inc = c0;
 #pragma unroll
@@ -1014,7 +1014,11 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
         const int v = __shfl_up(inc, o);
         if (lane >= o) inc += v;
       }
-      bucket[threadIdx.x] = inc - c0;
+      if (lane == 63) wave_total[wave] = inc;  // the list's scan above has read its totals
+      __syncthreads();
+      int excl = inc - c0;
+      for (int w = 0; w < wave; ++w) excl += wave_total[w];
+      bucket[threadIdx.x] = excl;
     }
     __syncthreads();
     for (int k = 0; k < 3; ++k)
