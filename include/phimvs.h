@@ -196,9 +196,9 @@ int phimvs_patchmatch_batch(phimvs_ctx* ctx, int n_jobs, const phimvs_job* jobs,
 /* Launch configuration of the evaluate-and-select kernel: tile_rows (4, 2 or 1) rows of
  * 256 / tile_rows same-colour pixels per workgroup; persistent != 0 runs a fixed grid
  * of wgs_per_cu workgroups per compute unit pulling tiles from per-XCD queues, else
- * one workgroup per tile; order_by_depth (0 or 1) = 1 hands a tile's initialisation and
- * refinement work items to the lanes in order of the candidate's inverse depth instead of
- * pixel order (results are the same either way; it pays where random depths scatter the
+ * one workgroup per tile; order_by_depth (0 or 1) = 1 hands a tile's (pixel, candidate)
+ * work items to the lanes in order of the candidate's inverse depth instead of pixel order
+ * (results are the same either way; it pays where the candidates' depths scatter the
  * source gathers most, as with converging cameras).  ms is the time measured by
  * phimvs_autotune.  A new context starts with tile_rows 4, persistent, 4 workgroups per
  * compute unit, pixel order. */

@@ -14,9 +14,10 @@ constexpr int kBlock = 256;        // threads per evaluate workgroup
 // evaluate kernel's compaction arrays in dynamic LDS, in floats: per pixel S_w, mu_a,
 // var_a (3 kBlock), cost per (slot, pixel) (8 kBlock), the (pixel, slot) list as 16-bit
 // entries (4 kBlock) and the waves' counts (8)
-constexpr int kCompactLds = 15 * kBlock + 8;
 constexpr int kDepthBuckets = 256;  // inverse-depth buckets of the depth-ordered work list (one per thread)
 static_assert(kDepthBuckets == kBlock, "the bucket scan gives each thread of the workgroup one bucket");
+constexpr int kDepthBucketLds = 15 * kBlock + 8;  // their counters, after the wave totals
+constexpr int kCompactLds = kDepthBucketLds + kDepthBuckets;
 constexpr int kMaxTopK = PHIMVS_MAX_SOURCES;
 constexpr int kMaxTaps1D = 31;     // taps per window side
 

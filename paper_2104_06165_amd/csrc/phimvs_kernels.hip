@@ -850,7 +850,7 @@ __global__ __launch_bounds__(128) void cand_refine_kernel(const Job* __restrict_
 //
 // Dynamic LDS: the compaction's arrays (kCompactLds floats), the spatial weights, then the
 // reference tile.
-template <bool FR>
+template <bool FR, bool DEPTH>
 __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int tile_x, int tile_y, float* wcol,
                                           float* lds) {
   const Args& A = J.A;
@@ -957,20 +957,16 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
   ref_lds[kBlock + threadIdx.x] = rp.mu_a;
   ref_lds[2 * kBlock + threadIdx.x] = rp.var_a;
   unsigned live = 0;  // non-empty slots
-  float dk[3] = {0.f, 0.f, 0.f};  // their depths (launches of up to 3 candidates)
   if (valid)
-    for (int k = 0; k < L.ncand; ++k) {
-      const float d = gl(J.cand)[k * plane_sz + cidx].w;
-      if (!__builtin_isnan(d)) live |= 1u << k;
-      if (k < 3) dk[k] = d;
-    }
+    for (int k = 0; k < L.ncand; ++k)
+      if (!__builtin_isnan(gl(J.cand)[k * plane_sz + cidx].w)) live |= 1u << k;
   // the list: pixel order, slot order within a pixel (exclusive prefix of the counts over
   // the workgroup: a scan within each wave, then the totals of the earlier waves); or, with
-  // order_by_depth in a launch of up to 3 candidates, by buckets of the candidate's inverse
-  // depth, so that a wave's lanes sample nearby points of each source.  Each item's cost is
-  // computed on its own and the selection below reads the costs in slot order, so the
-  // order of the list changes no result.
-  const bool by_depth = L.order_by_depth && L.ncand <= 3;
+  // order_by_depth, by buckets of the candidate's inverse depth, so that a wave's lanes
+  // sample nearby points of each source.  Each item's cost is computed on its own and the
+  // selection below reads the costs in slot order, so the order of the list changes no
+  // result.
+
   const int cnt = __popc(live);
   int incl = cnt;
 #pragma unroll
@@ -987,24 +983,23 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
     n_items += wave_total[w];
     if (w < wave) off += wave_total[w];
   }
-  if (!by_depth) {
+  if constexpr (!DEPTH) {
     for (unsigned m = live; m; m &= m - 1) item_lds[off++] = (uint16_t)((threadIdx.x << 3) | (__ffs(m) - 1));
   } else {
     // counting sort into kDepthBuckets (= kBlock) buckets of 1/d over [1/d_hi, 1/d_lo]:
     // counts, an exclusive scan over the workgroup (one bucket per thread), then each item
     // takes the next place of its bucket (the order within a bucket is whichever the atomics
-    // give; the cost slots of candidates 4..7, unused here, hold the counters)
-    int* bucket = reinterpret_cast<int*>(cost_lds + 4 * kBlock);
+    // give).  A candidate's depth is read again from its slot where needed (a cache hit)
+    // rather than kept in registers.
+    int* bucket = reinterpret_cast<int*>(lds + kDepthBucketLds);
     bucket[threadIdx.x] = 0;
     __syncthreads();
     const float inv_lo = 1.0f / A.d_hi, scale = (float)kDepthBuckets / (1.0f / A.d_lo - 1.0f / A.d_hi);
-    int bk[3] = {0, 0, 0};
-    for (int k = 0; k < 3; ++k)
-      if ((live >> k) & 1u) {
-        const int b = (int)((1.0f / dk[k] - inv_lo) * scale);
-        bk[k] = b < 0 ? 0 : (b >= kDepthBuckets ? kDepthBuckets - 1 : b);
-        atomicAdd(&bucket[bk[k]], 1);
-      }
+    auto bucket_of = [&](int k) {
+      const int b = (int)((1.0f / gl(J.cand)[k * plane_sz + cidx].w - inv_lo) * scale);
+      return b < 0 ? 0 : (b >= kDepthBuckets ? kDepthBuckets - 1 : b);
+    };
+    for (unsigned m = live; m; m &= m - 1) atomicAdd(&bucket[bucket_of(__ffs(m) - 1)], 1);
     __syncthreads();
     {
       const int c0 = bucket[threadIdx.x];
@@ -1021,8 +1016,10 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
       bucket[threadIdx.x] = excl;
     }
     __syncthreads();
-    for (int k = 0; k < 3; ++k)
-      if ((live >> k) & 1u) item_lds[atomicAdd(&bucket[bk[k]], 1)] = (uint16_t)((threadIdx.x << 3) | k);
+    for (unsigned m = live; m; m &= m - 1) {
+      const int k = __ffs(m) - 1;
+      item_lds[atomicAdd(&bucket[bucket_of(k)], 1)] = (uint16_t)((threadIdx.x << 3) | k);
+    }
   }
   if (L.count && threadIdx.x == 0) atomicAdd(L.count, (unsigned long long)n_items);
   __syncthreads();
@@ -1089,8 +1086,9 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
 // XCD's list.  Persistent: a fixed grid; each workgroup pulls positions from its XCD's
 // queue, so uneven tiles balance dynamically within an XCD.  FR: instantiated with the
 // window-resize scheme's code (launches holding such a job), whose register needs then do
-// not weigh on the integer-spacing instance.
-template <bool FR>
+// not weigh on the integer-spacing instance; DEPTH likewise for the depth-ordered work
+// list, so that the pixel-order instance carries none of its code.
+template <bool FR, bool DEPTH>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void eval_kernel(
     const Job* __restrict__ jobs, Launch L) {
   // the colour-weight table at the start of LDS: a reference difference (x4) is then its
@@ -1106,7 +1104,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
     int tx, ty;
     band_tile(J, xcd, i - J.xoff[xcd], tx, ty);
-    eval_tile<FR>(J, L, tx, ty, wcol, lds);
+    eval_tile<FR, DEPTH>(J, L, tx, ty, wcol, lds);
     return;
   }
   for (;;) {
@@ -1118,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     const Job& J = jobs[job_of_xcd_tile(jobs, L.n_jobs, xcd, i)];
     int tx, ty;
     band_tile(J, xcd, i - J.xoff[xcd], tx, ty);
-    eval_tile<FR>(J, L, tx, ty, wcol, lds);
+    eval_tile<FR, DEPTH>(J, L, tx, ty, wcol, lds);
     __syncthreads();  // the next tile re-stages LDS
   }
 }
@@ -1355,9 +1353,10 @@ hipError_t eval_lds_setup(size_t* max_dynamic) {
     return e;
   const size_t per_wg = std::min<size_t>((size_t)std::max(optin, per_cu), 160 * 1024);
   size_t lim = per_wg;
-  const void* fns[6] = {(const void*)pmk::eval_kernel<false>,    (const void*)pmk::eval_kernel<true>,
-                        (const void*)pmk::eval_lanes_kernel<2>,  (const void*)pmk::eval_lanes_kernel<4>,
-                        (const void*)pmk::eval_lanes_kernel<8>,  (const void*)pmk::eval_lanes_kernel<16>};
+  const void* fns[8] = {(const void*)pmk::eval_kernel<false, false>, (const void*)pmk::eval_kernel<true, false>,
+                        (const void*)pmk::eval_kernel<false, true>,  (const void*)pmk::eval_kernel<true, true>,
+                        (const void*)pmk::eval_lanes_kernel<2>,      (const void*)pmk::eval_lanes_kernel<4>,
+                        (const void*)pmk::eval_lanes_kernel<8>,      (const void*)pmk::eval_lanes_kernel<16>};
   for (const void* fn : fns) {
     hipFuncAttributes a{};
     if ((e = hipFuncGetAttributes(&a, fn)) != hipSuccess) return e;
@@ -1375,7 +1374,9 @@ hipError_t launch_eval(const Job* d_jobs, const Launch& L, int grid, size_t lds,
   // earlier call's error on this thread)
   Launch l = L;
   void* args[] = {(void*)&d_jobs, (void*)&l};
-  const void* fn = L.frac ? (const void*)pmk::eval_kernel<true> : (const void*)pmk::eval_kernel<false>;
+  const void* fn = L.order_by_depth
+                       ? (L.frac ? (const void*)pmk::eval_kernel<true, true> : (const void*)pmk::eval_kernel<false, true>)
+                       : (L.frac ? (const void*)pmk::eval_kernel<true, false> : (const void*)pmk::eval_kernel<false, false>);
   return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, lds, st);
 }
 

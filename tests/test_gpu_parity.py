@@ -315,7 +315,7 @@ def test_patchmatch_parity_tiny(ctx, tiny):
 
 
 def test_patchmatch_parity_tiny_depth_ordered(ctx, tiny):
-    """The whole tiny run with its initialisation and refinement work handed out in order of
+    """The whole tiny run with its work items handed out in order of
     the candidates' inverse depth, against the oracle to the same bar as in pixel order."""
     scene, cfg = tiny
     pb = _prep(ctx, scene, cfg)

@@ -7,7 +7,7 @@ settings give bitwise the same depth, normal and cost at every pixel, while the 
 of hypotheses scored falls (reported, and asserted to fall at each step); so do they on
 the 160x120 workload, with one lane per pixel and with 16 lanes sharing each pixel.
 
-Likewise, handing a tile's initialisation and refinement work items to the lanes in order
+Likewise, handing a tile's (pixel, candidate) work items to the lanes in order
 of the candidates' inverse depth (phimvs_tuning.order_by_depth) instead of pixel order
 gives bitwise the same maps: each item's cost is computed on its own, and the selection
 reads the costs in slot order."""
