@@ -199,7 +199,8 @@ int phimvs_patchmatch_batch(phimvs_ctx* ctx, int n_jobs, const phimvs_job* jobs,
  * one workgroup per tile; order_by_depth (0 or 1) = 1 hands a tile's (pixel, candidate)
  * work items to the lanes in order of the candidate's inverse depth instead of pixel order
  * (results are the same either way; it pays where the candidates' depths scatter the
- * source gathers most, as with converging cameras).  ms is the time measured by
+ * source gathers most, as with converging cameras; the split-lane path of
+ * phimvs_params.lanes > 1 has no work list and ignores it).  ms is the time measured by
  * phimvs_autotune.  A new context starts with tile_rows 4, persistent, 4 workgroups per
  * compute unit, pixel order. */
 typedef struct {
