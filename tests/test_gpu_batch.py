@@ -93,10 +93,11 @@ def test_depth_ordered_batch_equals_pixel_order_singles(ctx, mv, use_graph):
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_mixing_window_resize_and_integer_jobs(ctx, mv, use_graph):
+@pytest.mark.parametrize("order_by_depth", [False, True])
+def test_batch_mixing_window_resize_and_integer_jobs(ctx, mv, use_graph, order_by_depth):
     """A launch that holds a window-resize job runs the fractional-spacing kernel instance
     for every job in it: each job, resize or integer spacing, still equals its single run
-    bitwise."""
+    bitwise (the single runs in pixel order; the batch in either order)."""
     iters = 2
     jobs = jobs_of(mv)
     j0 = jobs[0]  # radius 6 sampled by 5 taps per side (spacing 6/5)
@@ -104,11 +105,13 @@ def test_batch_mixing_window_resize_and_integer_jobs(ctx, mv, use_graph):
                    params=pm.Params(top_k=j0["params"].top_k, seed=j0["params"].seed, tap_radius=5))
     ctx.set_tuning(pm.Tuning(4, False, 0))
     ref = single_runs(ctx, jobs, iters)
+    ctx.set_tuning(pm.Tuning(4, False, 0, order_by_depth=order_by_depth))
     outs = ctx.patchmatch_batch(jobs, iters, use_graph=use_graph)
     torch.cuda.synchronize()
     for k, ((d, n, c), (rd, rn, rc)) in enumerate(zip(outs, ref)):
         assert torch.equal(d, rd) and torch.equal(n, rn) and torch.equal(c, rc), f"job {k}"
-    say(f"mixed batch ({len(jobs)} jobs, one window-resize) == single runs (graph={use_graph})")
+    say(f"mixed batch ({len(jobs)} jobs, one window-resize) == single runs (graph={use_graph}, "
+        f"depth order {order_by_depth})")
 
 
 def test_graph_replays_with_eager_work_between(ctx, mv):

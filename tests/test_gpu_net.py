@@ -356,6 +356,23 @@ def test_patchmatch_with_proposal_parity(ctx, net, tiny):
     assert ok[m].mean() >= 0.999
 
 
+def test_patchmatch_with_proposal_depth_ordered(ctx, net, tiny):
+    """The gated initialisation (two candidates per pixel) and the iterations with the work
+    items in inverse-depth order give bitwise the maps of pixel order."""
+    planes, srcs = _proposal(ctx, net, tiny)
+    params = pm.Params(top_k=len(srcs), sigma_spatial_px=5.0)
+    prev = ctx.get_tuning()
+    try:
+        out = []
+        for order in (False, True):
+            ctx.set_tuning(pm.Tuning(prev.tile_rows, prev.persistent, prev.wgs_per_cu, order_by_depth=order))
+            d, n, c = ctx.patchmatch_proposal(0, srcs, 11, 1, 2, planes, params)
+            out.append((d.clone(), n.clone(), c.clone()))
+    finally:
+        ctx.set_tuning(prev)
+    assert all(torch.equal(a, b) for a, b in zip(*out))
+
+
 def test_proposal_argument_errors(ctx, net, tiny):
     H, W = tiny.images[0].shape
     with pytest.raises(ValueError):
