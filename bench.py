@@ -55,11 +55,12 @@ def measured_traffic(kernel_file: str, profile: str):
 
 
 def parse_tuning(pm, text):
-    """ROWS,PERSISTENT,WGS[,ORDER_BY_DEPTH] -> the library's launch configuration."""
+    """ROWS,PERSISTENT,WGS[,ORDER_BY_DEPTH] -> the library's launch configuration (the order
+    a mask: 1 initialisation, 2 propagation, 4 refinement)."""
     v = [int(x) for x in text.split(",")]
     if len(v) not in (3, 4):
         raise SystemExit("--tuning takes ROWS,PERSISTENT,WGS[,ORDER_BY_DEPTH]")
-    return pm.Tuning(v[0], bool(v[1]), v[2], order_by_depth=bool(v[3]) if len(v) == 4 else False)
+    return pm.Tuning(v[0], bool(v[1]), v[2], order_by_depth=v[3] if len(v) == 4 else 0)
 
 
 def nominal_tap_views(valid_px, n_src, taps, iters):
@@ -172,11 +173,11 @@ def bench_batched(args):
         ctx.set_tuning(parse_tuning(pm, args.tuning))
         best, allr = ctx.get_tuning(), []
         log(f"[bench] launch configuration fixed: rows{best.tile_rows}/p{int(best.persistent)}/{best.wgs_per_cu}"
-            f"{'/depth' if best.order_by_depth else ''}")
+            f"{f'/depth{best.order_by_depth}' if best.order_by_depth else ''}")
     else:
         best, allr = ctx.autotune(jobs, iters=args.autotune_iters)
         log("[bench] autotune: " + ", ".join(
-            f"rows{r.tile_rows}/p{int(r.persistent)}/{r.wgs_per_cu}{'/depth' if r.order_by_depth else ''}={r.ms:.1f}ms"
+            f"rows{r.tile_rows}/p{int(r.persistent)}/{r.wgs_per_cu}{f'/depth{r.order_by_depth}' if r.order_by_depth else ''}={r.ms:.1f}ms"
             for r in allr))
     outs = [dict(depth=torch.empty(mv.images[j["ref"]].shape, dtype=torch.float32, device="cuda"),
                  normal=torch.empty(mv.images[j["ref"]].shape + (3,), dtype=torch.float32, device="cuda"),

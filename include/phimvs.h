@@ -196,11 +196,12 @@ int phimvs_patchmatch_batch(phimvs_ctx* ctx, int n_jobs, const phimvs_job* jobs,
 /* Launch configuration of the evaluate-and-select kernel: tile_rows (4, 2 or 1) rows of
  * 256 / tile_rows same-colour pixels per workgroup; persistent != 0 runs a fixed grid
  * of wgs_per_cu workgroups per compute unit pulling tiles from per-XCD queues, else
- * one workgroup per tile; order_by_depth (0 or 1) = 1 hands a tile's (pixel, candidate)
- * work items to the lanes in order of the candidate's inverse depth instead of pixel order
- * (results are the same either way; it pays where the candidates' depths scatter the
- * source gathers most, as with converging cameras; the split-lane path of
- * phimvs_params.lanes > 1 has no work list and ignores it).  ms is the time measured by
+ * one workgroup per tile; order_by_depth, a mask of 1 (initialisation), 2 (propagation)
+ * and 4 (refinement), hands those launches' (pixel, candidate) work items to the lanes in
+ * order of the candidate's inverse depth instead of pixel order (results are the same
+ * either way; it pays where the candidates' depths scatter the source gathers most, as
+ * with converging cameras; the split-lane path of phimvs_params.lanes > 1 has no work list
+ * and ignores it).  ms is the time measured by
  * phimvs_autotune.  A new context starts with tile_rows 4, persistent, 4 workgroups per
  * compute unit, pixel order. */
 typedef struct {
@@ -215,7 +216,7 @@ int phimvs_set_tuning(phimvs_ctx* ctx, const phimvs_tuning* t);
 int phimvs_get_tuning(phimvs_ctx* ctx, phimvs_tuning* t);
 /* Time every built-in configuration on the given batch (graph replays, `iters`
  * iterations: ten launch shapes in pixel order, then the fastest of them again with
- * order_by_depth), keep the fastest in the context and report all of them in results
+ * order_by_depth = 7), keep the fastest in the context and report all of them in results
  * (capacity *n_results, updated to the number written).  A configuration that fails to
  * run is reported with ms = +inf and passed over (phimvs_last_error then names it); when
  * none runs, the previous configuration is restored and PHIMVS_E_DEVICE returned. */

@@ -115,7 +115,7 @@ class Tuning:
     persistent: bool = False
     wgs_per_cu: int = 0
     ms: float = 0.0
-    order_by_depth: bool = False
+    order_by_depth: int = 0  # mask: 1 initialisation, 2 propagation, 4 refinement (True: all)
 
 
 @dataclass
@@ -566,12 +566,12 @@ class Context:
 
     def set_tuning(self, t: Tuning):
         self._check(lib().phimvs_set_tuning(self.h, C.byref(_Tuning(t.tile_rows, int(t.persistent), t.wgs_per_cu,
-                                                                     int(t.order_by_depth), t.ms))))
+                                                                     (7 if t.order_by_depth is True else int(t.order_by_depth)), t.ms))))
 
     def get_tuning(self) -> Tuning:
         t = _Tuning()
         self._check(lib().phimvs_get_tuning(self.h, C.byref(t)))
-        return Tuning(t.tile_rows, bool(t.persistent), t.wgs_per_cu, t.ms, bool(t.order_by_depth))
+        return Tuning(t.tile_rows, bool(t.persistent), t.wgs_per_cu, t.ms, int(t.order_by_depth))
 
     def autotune(self, jobs, iters: int = 1):
         """Time the built-in launch configurations on this batch; keep the fastest.
@@ -582,7 +582,7 @@ class Context:
         res = (_Tuning * cap)()
         n = C.c_int(cap)
         self._check(lib().phimvs_autotune(self.h, len(jobs), arr, iters, res, C.byref(n)))
-        allr = [Tuning(r.tile_rows, bool(r.persistent), r.wgs_per_cu, r.ms, bool(r.order_by_depth))
+        allr = [Tuning(r.tile_rows, bool(r.persistent), r.wgs_per_cu, r.ms, int(r.order_by_depth))
                 for r in res[:n.value]]
         return self.get_tuning(), allr
 

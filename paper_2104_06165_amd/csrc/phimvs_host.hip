@@ -455,7 +455,10 @@ int eval_grid(const phimvs_ctx* c, const Batch& b, bool persistent) {
 int run_eval(phimvs_ctx* c, Batch& b, Launch L, unsigned int* queue) {
   const bool persistent = c->tuning.persistent != 0;
   L.persistent = persistent ? 1 : 0;
-  L.order_by_depth = c->tuning.order_by_depth ? 1 : 0;
+  // the depth-ordered instance for the launch kinds the tuning names (mask: 1 initialisation,
+  // 2 propagation, 4 refinement)
+  const int kind_bit = L.mode == 0 ? 1 : (L.ncand > 3 ? 2 : 4);
+  L.order_by_depth = (c->tuning.order_by_depth & kind_bit) ? 1 : 0;
   L.queue = queue;
   if (c->diag & PHIMVS_DIAG_COUNT) L.count = c->diag_count;
   const bool split = b.jobs.size() == 1 && b.jobs[0].A.lanes > 1;
@@ -1350,7 +1353,8 @@ int phimvs_set_tuning(phimvs_ctx* c, const phimvs_tuning* t) {
     return fail(c, PHIMVS_E_ARG, "tile_rows must be 1, 2 or 4");
   if (t->persistent && (t->wgs_per_cu < 1 || t->wgs_per_cu > 16))
     return fail(c, PHIMVS_E_ARG, "wgs_per_cu must be in [1, 16] for persistent launches");
-  if (t->order_by_depth != 0 && t->order_by_depth != 1) return fail(c, PHIMVS_E_ARG, "order_by_depth must be 0 or 1");
+  if (t->order_by_depth < 0 || t->order_by_depth > 7)
+    return fail(c, PHIMVS_E_ARG, "order_by_depth is a mask of 1 (initialisation), 2 (propagation), 4 (refinement)");
   HIPCHECK(c, hipSetDevice(c->device));
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   const bool shape = t->tile_rows != c->tuning.tile_rows;
@@ -1399,7 +1403,7 @@ int phimvs_autotune(phimvs_ctx* c, int n_jobs, const phimvs_job* jobs, int iters
   for (int i = 0; i < n; ++i) {
     if (i == n - 1 && best_ms < HUGE_VAL) {
       cands[i] = best;
-      cands[i].order_by_depth = 1;
+      cands[i].order_by_depth = 7;
       cands[i].ms = 0.0;
     }
     phimvs_tuning r = cands[i];
