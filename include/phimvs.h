@@ -317,8 +317,11 @@ int phimvs_phi_hypotheses_noalloc(phimvs_ctx* ctx, int width, int height, const 
 
 /* Matching cost (Eq. 5, the prepared problem's cost) of every hypothesis: the fronto-
  * parallel plane at the hypothesis depth, i.e. every window point back-projected at that
- * depth and projected into the sources.  Needs phimvs_prepare of the same reference.
- * hyp, cost: device planar 4*H*W; cost of an empty hypothesis is PHIMVS_COST_MAX. */
+ * depth and projected into the sources.  Needs phimvs_prepare of the same reference; the
+ * hypotheses pass through the prepared problem's candidate slots (so only the present ones
+ * are scored), which the next step overwrites anyway.  hyp, cost: device planar 4*H*W;
+ * cost of an empty hypothesis, or of a pixel whose window leaves the image, is
+ * PHIMVS_COST_MAX. */
 int phimvs_phi_costs(phimvs_ctx* ctx, const float* hyp, float* cost);
 
 typedef struct {

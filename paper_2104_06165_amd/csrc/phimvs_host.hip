@@ -1223,13 +1223,27 @@ int phimvs_phi_costs(phimvs_ctx* c, const float* hyp, float* cost) {
   if (rc) return rc;
   if (!hyp || !cost) return fail(c, PHIMVS_E_ARG, "null array");
   HIPCHECK(c, hipSetDevice(c->device));
-  const Job& J = c->single.jobs[0];
+  // the hypotheses become the candidate slots of each colour in turn, and one evaluate
+  // launch per colour scores the present ones through the compacted work list (pixels with
+  // depth or without a hypothesis take no lane) and writes every slot's cost
+  Batch& b = c->single;
+  Job& J = b.jobs[0];
   const size_t n = (size_t)J.A.W * J.A.H;
-  if ((rc = ensure(c, c->io_d, 4 * n))) return rc;
-  for (int k = 0; k < 4; ++k) {
-    HIPCHECK(c, launch_phi_planes(hyp + k * n, n, c->io_d.p, c->stream));
-    if ((rc = phimvs_eval_cost(c, c->io_d.p, cost + k * n, nullptr, nullptr, 1))) return rc;
+  J.cost_out = cost;
+  if ((rc = upload_jobs(c, b))) return rc;
+  Launch L = base_launch(b);
+  L.mode = 3;
+  L.ncand = 4;
+  for (int colour = 0; colour < 2 && !rc; ++colour) {
+    L.colour = colour;
+    const hipError_t e = launch_hyp_candidates(b.d_jobs, L, hyp, c->stream);
+    if (e != hipSuccess) rc = fail(c, PHIMVS_E_DEVICE, std::string("hypothesis candidates: ") + hipGetErrorString(e));
+    if (!rc) rc = eval_once(c, b, L);
   }
+  J.cost_out = nullptr;
+  const int rc2 = upload_jobs(c, b);  // the next upload drops the caller's pointer
+  if (rc) return rc;
+  if (rc2) return rc2;
   HIPCHECK(c, launch_phi_mask_cost(hyp, 4 * n, PHIMVS_COST_MAX, cost, c->stream));
   return PHIMVS_OK;
 }

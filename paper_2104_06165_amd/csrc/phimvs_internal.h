@@ -81,7 +81,8 @@ struct Job {
 // one launch over all jobs
 struct Launch {
   int n_jobs;
-  int colour, iteration, ncand, mode;  // mode 0: initialise, 1: update, 2: evaluate
+  int colour, iteration, ncand, mode;  // mode 0: initialise, 1: update, 2: evaluate planes_in, 3: cost of
+                                       // every candidate slot, written out
   int tile_rows;                       // rows of an evaluate tile (4, 2 or 1); 256 / tile_rows columns
   int total_tiles, total_cblk;
   int xcd_len[8];                      // evaluate tiles of each XCD's list
@@ -111,6 +112,8 @@ hipError_t launch_eval_lanes(const Job* d_jobs, const Launch& L, int lanes, int 
                              hipStream_t st);
 // kind 0: random initialisation (+ proposal), 1: propagation, 2: refinement candidates
 hipError_t launch_candidates(int kind, const Job* d_jobs, const Launch& L, hipStream_t st);
+// the 4 planar hypothesis maps hyp (4 W H) as candidate slots 0..L.ncand-1 of colour L.colour
+hipError_t launch_hyp_candidates(const Job* d_jobs, const Launch& L, const float* hyp, hipStream_t st);
 hipError_t launch_unpack(const Job* d_jobs, const Launch& L, hipStream_t st);
 // row-major planes + cost -> the colour planes of job 0 (W x H)
 hipError_t launch_pack(const Job* d_jobs, int W, int H, const float* planes, const float* cost, hipStream_t st);
@@ -167,7 +170,6 @@ constexpr size_t kPhiScratchWords = (size_t)1 << 20;
 hipError_t phi_scratch_setup(int device);
 hipError_t phi_scratch_get(int device, uint64_t** p);
 hipError_t launch_phi_hypotheses(const float* depth, int W, int H, uint64_t* bits, float* hyp, hipStream_t st);
-hipError_t launch_phi_planes(const float* hyp, size_t n, float* planes, hipStream_t st);
 hipError_t launch_phi_mask_cost(const float* hyp, size_t n, float cmax, float* cost, hipStream_t st);
 // node (X, Y) of the half-size graph from pixel (2X, 2Y): depth, 4 hypothesis planes, 4
 // cost planes, one after the other in half (9 (W+1)/2 (H+1)/2 floats)

@@ -1054,6 +1054,16 @@ __device__ __forceinline__ void eval_tile(const Job& J, const Launch& L, int til
     }
   }
   __syncthreads();
+  if (L.mode == 3) {
+    // the cost of every slot, written out row-major (slot k of pixel (x, y) at k H W + y W +
+    // x); an empty slot, or a pixel whose window leaves the image, costs C_max
+    if (in_img) {
+      const size_t n = (size_t)A.W * A.H, p = (size_t)y * A.W + x;
+      for (int k = 0; k < L.ncand; ++k)
+        gl(J.cost_out)[k * n + p] = ((live >> k) & 1u) ? cost_lds[k * kBlock + threadIdx.x] : kCmax;
+    }
+    return;
+  }
   if (!in_img || (L.mode == 1 && !valid)) return;
   float4 best = make_float4(0.f, 0.f, 0.f, 0.f);
   float bc = kCmax;
@@ -1270,6 +1280,22 @@ __global__ void build_view_kernel(const uint8_t* __restrict__ img, int64_t strid
 
 // colour planes -> row-major outputs (planes and cost, or depth / normal / cost); blocks of
 // 256 pixels of one row (cblk_x counts 128-wide compacted blocks = 256-wide pixel blocks)
+// the depth hypotheses of plane hypothesis inference as candidate planes of the fronto-
+// parallel kind (0, 0, -1, h) for the pixels of one colour: slot k from hypothesis map k
+// (planar, k H W + y W + x); a missing hypothesis (h <= 0) is an empty slot
+__global__ __launch_bounds__(128) void cand_hyp_kernel(const Job* __restrict__ jobs, Launch L,
+                                                       const float* __restrict__ hyp) {
+  int jb, x, y, ci;
+  if (!cblk_pixel(jobs, L, jb, x, y, ci)) return;
+  const Job& J = jobs[jb];
+  const Args& A = J.A;
+  const size_t cidx = (size_t)y * A.Wc + ci, plane_sz = (size_t)A.H * A.Wc, n = (size_t)A.W * A.H;
+  for (int k = 0; k < L.ncand; ++k) {
+    const float h = gl(hyp)[k * n + (size_t)y * A.W + x];
+    st4(J.cand, k * plane_sz + cidx, make_float4(0.0f, 0.0f, -1.0f, h > 0.0f ? h : __int_as_float(0x7fc00000)));
+  }
+}
+
 __global__ __launch_bounds__(256) void unpack_kernel(const Job* __restrict__ jobs, Launch L) {
   const int g = blockIdx.x;
   const int jb = job_of_cblk(jobs, L.n_jobs, g);
@@ -1406,6 +1432,11 @@ hipError_t launch_candidates(int kind, const Job* d_jobs, const Launch& L, hipSt
   if (kind == 0) hipLaunchKernelGGL(pmk::cand_init_kernel, grid, dim3(128), 0, st, d_jobs, L);
   else if (kind == 1) hipLaunchKernelGGL(pmk::cand_prop_kernel, grid, dim3(128), 0, st, d_jobs, L);
   else hipLaunchKernelGGL(pmk::cand_refine_kernel, grid, dim3(128), 0, st, d_jobs, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_hyp_candidates(const Job* d_jobs, const Launch& L, const float* hyp, hipStream_t st) {
+  hipLaunchKernelGGL(pmk::cand_hyp_kernel, dim3(L.total_cblk), dim3(128), 0, st, d_jobs, L, hyp);
   return hipGetLastError();
 }
 

@@ -158,18 +158,7 @@ __global__ __launch_bounds__(256) void phi_hyp_kernel(const float* __restrict__ 
   for (int k = 0; k < 4; ++k) hyp[k * plane + p] = hole ? (float)line_fit(depth, W, H, B, k, x, y) : 0.0f;
 }
 
-// hypothesis k -> fronto-parallel plane (n = (0, 0, -1), d = h); an empty one gets d = NaN,
-// which the cost evaluation scores C_max without running the window
-__global__ void phi_planes_kernel(const float* __restrict__ hyp, size_t n, float* __restrict__ planes) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float h = hyp[i];
-  planes[4 * i] = 0.0f;
-  planes[4 * i + 1] = 0.0f;
-  planes[4 * i + 2] = -1.0f;
-  planes[4 * i + 3] = h > 0.0f ? h : __int_as_float(0x7fc00000);
-}
-
+// an empty hypothesis (h <= 0) costs C_max
 __global__ void phi_mask_cost_kernel(const float* __restrict__ hyp, size_t n, float cmax, float* __restrict__ cost) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -312,11 +301,6 @@ hipError_t launch_phi_hypotheses(const float* depth, int W, int H, uint64_t* bit
   hipLaunchKernelGGL(pmp::phi_bits_cols_kernel, dim3((W + H - 1 + 255) / 256, B.words[1], 3), dim3(256), 0, st,
                      depth, W, H, B);
   hipLaunchKernelGGL(pmp::phi_hyp_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, depth, W, H, B, hyp);
-  return hipGetLastError();
-}
-
-hipError_t launch_phi_planes(const float* hyp, size_t n, float* planes, hipStream_t st) {
-  hipLaunchKernelGGL(pmp::phi_planes_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hyp, n, planes);
   return hipGetLastError();
 }
 
