@@ -1095,9 +1095,11 @@ double oracle_phi_map_bruteforce(const float* depth, const float* hyp, const flo
 // terms added in the order up, left, right, down), the first such state on ties.
 // label[i] receives k (-1 for a fixed node or one without states), value[i] its depth (0
 // without states).  Parity unpinned in part: on a forest TRW is exact and the tests hold
-// it to the enumerated MAP, but the weights gamma and the exact sweep schedule act on
-// graphs with loops alone, where TRW has no exact reference; there they are held only to
-// near-optimality.
+// it to the enumerated MAP; the weights gamma and the exact sweep schedule act on graphs
+// with loops alone, where the tests hold the decoder to the enumerated MAP only for binary
+// submodular energies (where TRW reaches the global minimum, Kolmogorov and Wainwright
+// 2005: over-counting weights fail there, smaller weights or a changed schedule do not)
+// and otherwise to near-optimality.
 void oracle_phi_trws(const float* depth, const float* hyp, const float* cost, int W, int H, double k1, double k2,
                      double k3, double cmax, int iterations, int32_t* label, float* value) {
   const int N = W * H;

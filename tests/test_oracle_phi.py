@@ -1,8 +1,9 @@
 """Pins of the plane-hypothesis-inference oracle (Sec. III-E): the line fits reproduce
 affine depth exactly in all four directions and equal numpy's least-squares fit on the
 six closest samples; the exact MAP agrees with hand-worked chains; the TRW decoder is
-exact on chains, reduces to closed forms where its messages are fixed or absent, and is
-near the exact MAP on small loopy grids; the normals of Eq. 10 equal the normal of the
+exact on chains, forests and loopy grids with binary submodular energies, reduces to
+closed forms where its messages are fixed or absent, and is near the exact MAP on other
+small loopy grids; the normals of Eq. 10 equal the normal of the
 plane a depth map was rendered from."""
 import itertools
 import math
@@ -371,6 +372,45 @@ def test_trws_on_small_loopy_grids():
     gaps = np.array(gaps)
     assert (gaps < 1e-9).mean() >= 0.8
     assert gaps.max() < 0.05
+
+
+def test_trws_is_exact_on_binary_submodular_loopy_grids():
+    """Loopy grids whose free nodes hold two hypotheses, one near 2.1 and one near 3.9 in
+    depth, so that every edge between two such nodes is submodular (the two same-side pairs
+    cost no more together than the two mixed pairs): for such binary energies TRW reaches
+    the global minimum (Kolmogorov and Wainwright, UAI 2005), so the decoding must equal the
+    enumerated optimum although the graph has cycles.  Greedy decoding misses it on most of
+    these instances; decoders that over-count beliefs (gamma = 1, plain max-product, or
+    gamma = m instead of 1/m) miss it on some."""
+    r = np.random.default_rng(21)
+    greedy_misses = 0
+    n = 120
+    for trial in range(n):
+        H, W = [(3, 4), (4, 4), (4, 3), (2, 6)][trial % 4]
+        k1, k2, k3 = (0.5, 1.0, 2.0)[trial % 3], 0.1, (2.5, 2.0)[trial % 2]
+        d = np.where(r.random((H, W)) < 0.1, r.uniform(1.5, 4.5, (H, W)), 0.0).astype(np.float32)
+        hyp = np.zeros((H, W, 4), np.float32)
+        hyp[..., 0] = r.uniform(2.0, 2.3, (H, W))
+        hyp[..., 1] = r.uniform(3.6, 4.2, (H, W))
+        hyp[d > 0] = 0
+        cost = r.uniform(0, 2, (H, W, 4)).astype(np.float32)
+
+        def e_pair(a, b):
+            rel = (a - b) / b if a > b else (b - a) / a
+            return -math.log((k3 - min(1.0, rel)) ** 2)
+
+        for y in range(H):
+            for x in range(W):
+                for yy, xx in ((y, x + 1), (y + 1, x)):
+                    if yy < H and xx < W and d[y, x] <= 0 and d[yy, xx] <= 0:
+                        a, b = hyp[y, x].astype(float), hyp[yy, xx].astype(float)
+                        assert e_pair(a[0], b[0]) + e_pair(a[1], b[1]) <= e_pair(a[0], b[1]) + e_pair(a[1], b[0])
+        _, e_opt = oracle.phi_map_bruteforce(d, hyp, cost, k1, k2, k3)
+        lab, _ = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=30)
+        assert np.isclose(_log_potential(d, hyp, cost, lab, k1, k2, k3), e_opt, rtol=1e-9, atol=1e-12), trial
+        lab0, _ = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=0)
+        greedy_misses += not np.isclose(_log_potential(d, hyp, cost, lab0, k1, k2, k3), e_opt, rtol=1e-9, atol=1e-12)
+    assert greedy_misses >= n // 3
 
 
 def test_normals_of_a_rendered_plane():
