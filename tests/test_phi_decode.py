@@ -1,7 +1,8 @@
 """The library's host-side graph-model decoder of plane hypothesis inference (Sec. III-E;
 the paper runs it on the CPU, so does the library) against the oracle's exact MAP on
 tiny grids: exact on chains (a tree, where sequential tree-reweighted message passing
-is exact), and on small loopy grids equal to the optimum or within a small margin of it;
+is exact), on loopy grids with binary submodular energies (where TRW is exact too), and
+on other small loopy grids equal to the optimum or within a small margin of it;
 and against the oracle's plain sequential TRW decoder bit for bit on grids large enough
 for the library's threaded tile schedule, with fixed and single-state nodes, ragged tile
 edges and several iteration counts.  No GPU needed: the decoder takes host arrays."""
@@ -78,6 +79,25 @@ def test_decoder_on_small_loopy_grids():
     gaps = np.array(gaps)
     assert (gaps < 1e-9).mean() >= 0.8  # the optimum itself in most cases
     assert gaps.max() < 0.05
+
+
+def test_decoder_is_exact_on_binary_submodular_loopy_grids():
+    """Loopy grids whose free nodes hold one hypothesis near each of two depths (every edge
+    between two of them submodular): there TRW reaches the global minimum (Kolmogorov and
+    Wainwright, UAI 2005), so the decoder must give the enumerated optimum."""
+    r = np.random.default_rng(22)
+    for trial in range(40):
+        H, W = [(3, 4), (4, 4), (4, 3), (2, 6)][trial % 4]
+        k1, k2, k3 = (0.5, 1.0, 2.0)[trial % 3], 0.1, (2.5, 2.0)[trial % 2]
+        depth = np.where(r.uniform(size=(H, W)) < 0.1, r.uniform(1.5, 4.5, (H, W)), 0.0).astype(np.float32)
+        hyp = np.zeros((H, W, 4), np.float32)
+        hyp[..., 0] = r.uniform(2.0, 2.3, (H, W))
+        hyp[..., 1] = r.uniform(3.6, 4.2, (H, W))
+        hyp[depth > 0] = 0.0
+        cost = r.uniform(0, 2, (H, W, 4)).astype(np.float32)
+        _, e_o = oracle.phi_map_bruteforce(depth, hyp, cost, k1, k2, k3)
+        lab, _ = pm.phi_decode_host(depth, hyp.transpose(2, 0, 1), cost.transpose(2, 0, 1), pm.PhiParams(k1, k2, k3, 30))
+        assert np.isclose(log_potential(depth, hyp, cost, lab, k1, k2, k3), e_o, rtol=1e-9, atol=1e-12), trial
 
 
 def test_decoder_arguments():
