@@ -1026,7 +1026,9 @@ void oracle_phi_hypotheses(const float* depth, int W, int H, float* hyp) {
 // single-state node with that depth and potential 1; otherwise its states are the
 // non-zero hyp[4 i + k] with unary (C_max - cost[4 i + k]) / k1 + k2.  Edge potential
 // [k3 - min(1, relative difference)]^2 (Eq. 8).  label[i] receives the chosen k (or -1
-// for fixed nodes / nodes without a state); returns the maximal log-potential.
+// for fixed nodes / nodes without a state); returns the maximal log-potential.  Labellings
+// are enumerated with node 0 varying fastest and each node's states in order of k; of
+// equal maxima the first one is kept.
 double oracle_phi_map_bruteforce(const float* depth, const float* hyp, const float* cost, int W, int H, double k1,
                                  double k2, double k3, double cmax, int32_t* label) {
   const int N = W * H;

@@ -78,10 +78,11 @@ def test_reprojection_error_closed_form(b, ok):
     assert np.all(oc[:, xs - disp < 0] == 0)  # projects left of the neighbour's image
 
 
-@pytest.mark.parametrize("disp,parity", [(2.4, 0), (2.6, 1)])
+@pytest.mark.parametrize("disp,parity", [(2.4, 0), (2.6, 1), (-2.4, 0), (-2.6, 1)])
 def test_normal_taken_at_the_rounded_position(disp, parity):
     """The neighbour's normal is read at floor(u + 1/2): with disparity 2.4 the rounded
-    column has x's parity, with 2.6 the other one."""
+    column has x's parity, with 2.6 the other one.  Negative disparities move the points
+    right, so that u within half a pixel of the last column reads that column (odd)."""
     Wb = 80
     Z = 4.0
     b = disp * Z / F
@@ -200,10 +201,11 @@ def test_normals_compared_in_world_coordinates(frame, ok):
     assert np.degrees(np.arccos(np.clip(nn0 @ nn1, -1, 1))) > 30.0
 
 
-@pytest.mark.parametrize("disp,parity", [(2.4, 0), (2.6, 1)])
+@pytest.mark.parametrize("disp,parity", [(2.4, 0), (2.6, 1), (-2.4, 0), (-2.6, 1)])
 def test_normal_taken_at_the_rounded_row(disp, parity):
     """The same as for columns, with a vertical baseline: the neighbour's normal is read in
-    row floor(v + 1/2); odd rows hold a normal that fails the test."""
+    row floor(v + 1/2); odd rows hold a normal that fails the test.  Negative disparities
+    reach the last row (odd)."""
     Hb = 60
     Z = 4.0
     b = disp * Z / F
@@ -237,14 +239,14 @@ def test_normals_tilted_out_of_the_horizontal_plane(deg):
     assert np.all(oc == 1)
 
 
-@pytest.mark.parametrize("sx,sy", [(0.5, 0.5), (0.5, 1e-6), (1e-6, 0.5)])
+@pytest.mark.parametrize("sx,sy", [(0.5, 0.5), (0.5, 1e-6), (1e-6, 0.5), (1 - 1e-6, 0.5), (0.5, 1 - 1e-6)])
 def test_a_hole_texel_voids_the_four_cells_that_hold_it(sx, sy):
     """The neighbour's principal point shifted by (sx, sy): pixel (x, y) interpolates the
     cell of texels x..x+1, y..y+1.  A single hole texel (depth 0) at (hx, hy) makes the
     neighbour unusable at exactly the four pixels whose cells hold it, one for each corner
     of the cell.  With a shift of 1e-6 along one axis the far corners weigh almost nothing,
     so the interpolated depth would pass the depth test: there the corner check alone
-    decides."""
+    decides; with 1 - 1e-6 the near corners weigh almost nothing instead."""
     K0, R0, t0 = cam(F, W, H)
     K1 = K0.copy()
     K1[0, 2] += sx

@@ -105,6 +105,13 @@ def test_half_resolution_copy_first_in_row_major_order_wins(tau, merged):
         assert np.all(s0 == 1) and np.all(sup[n0:] == 1)
 
 
+@pytest.mark.parametrize("shape", [(0, 5), (5, 0)])
+def test_a_map_without_pixels_is_refused(shape):
+    K, R, t = stack([cam(40.0, 5, 5), cam(40.0, 5, 5)])
+    with pytest.raises(ValueError):
+        oracle.fuse([np.ones((5, 5), np.float32), np.ones(shape, np.float32)], K, R, t)
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_support_is_conserved_on_random_views(seed):
     """Five cameras on an arc looking at a noisy plane, maps with holes: every pixel with

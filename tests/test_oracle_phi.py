@@ -73,6 +73,39 @@ def test_tie_at_the_sixth_sample_takes_the_negative_side(k):
     assert not np.isclose(np.polyval(alt, 0.0), np.polyval(coef, 0.0), rtol=1e-6)
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_line_fits_match_brute_force_up_to_the_borders(seed):
+    """Every hypothesis of small maps with half the pixels empty, where most lines reach an
+    image border (row 0 and column 0 included): walk steps -1, +1, -2, +2, ... along the
+    direction, keep the samples inside the image with depth, take the first six, and fit
+    a straight line with numpy (no hypothesis below two samples or for a fit <= 0)."""
+    r = np.random.default_rng(100 + seed)
+    H, W = 9, 11
+    d = r.uniform(1.0, 9.0, (H, W)).astype(np.float32)
+    d[r.random((H, W)) < 0.5] = 0.0
+    hyp = oracle.phi_hypotheses(d)
+    for y in range(H):
+        for x in range(W):
+            for k, (dx, dy) in enumerate(DIRS):
+                if d[y, x] > 0:
+                    assert hyp[y, x, k] == 0
+                    continue
+                take = []
+                for step in itertools.chain.from_iterable((-m, m) for m in range(1, max(H, W) + 1)):
+                    xs, ys = x + step * dx, y + step * dy
+                    if 0 <= xs < W and 0 <= ys < H and d[ys, xs] > 0 and len(take) < 6:
+                        take.append((step, float(d[ys, xs])))
+                if len(take) < 2:
+                    assert hyp[y, x, k] == 0
+                    continue
+                st, dv = np.array(take).T
+                v = np.polyval(np.polyfit(st, dv, 1), 0.0)
+                if v <= 0:
+                    assert hyp[y, x, k] == 0
+                else:
+                    assert np.isclose(hyp[y, x, k], v, rtol=1e-6), (y, x, k, take)
+
+
 def test_negative_and_nan_depths_are_holes():
     r = np.random.default_rng(4)
     d = r.uniform(1.0, 9.0, (15, 17)).astype(np.float32)
@@ -124,6 +157,20 @@ def test_map_on_chains_matches_enumeration():
         val = best[0][2] + best[1][2] + best[2][2] + pw(best[0][1], best[1][1]) + pw(best[1][1], best[2][1])
         assert np.isclose(e, val, rtol=1e-12)
         assert list(lab[0]) == [c[0] for c in best]
+
+
+def test_map_ties_take_the_first_labelling_in_enumeration_order():
+    """Two hypotheses of a node with the same depth and cost tie under every labelling of
+    the others: the enumeration (node 0 varying fastest, states in order of k) keeps the
+    first maximal labelling, so the lower k."""
+    d = np.zeros((1, 3), np.float32)
+    d[0, 0] = 3.0
+    hyp = np.zeros((1, 3, 4), np.float32)
+    hyp[0, 1] = [0.0, 3.5, 2.0, 3.5]
+    hyp[0, 2] = [2.5, 0.0, 0.0, 4.0]
+    cost = np.full((1, 3, 4), 0.4, np.float32)
+    lab, _ = oracle.phi_map_bruteforce(d, hyp, cost, 1.0, 0.1, 2.0)
+    assert lab[0, 0] == -1 and lab[0, 1] == 1
 
 
 def test_map_on_a_grid_matches_enumeration():
