@@ -91,6 +91,49 @@ def test_reprojection_threshold(ctx, b):
     assert_same(g, o, f"baseline {b}")
 
 
+@pytest.mark.parametrize("axis", ["column", "row"])
+@pytest.mark.parametrize("disp", [-2.4, -2.6, 2.6])
+def test_normal_at_the_rounded_position_up_to_the_last_column_and_row(ctx, axis, disp):
+    """The neighbour's normal is read at the rounded position; odd columns (rows) hold a
+    normal that fails the test.  Negative disparities move the points right (down), so
+    that with -2.6 a position within half a pixel of the last column (row) reads it."""
+    Z = 4.0
+    b = disp * Z / F
+    Wb, Hb = (80, H) if axis == "column" else (W, 60)
+    K0, R0, _ = cam(F, Wb, Hb)
+    shift = np.array([b, 0.0, 0.0]) if axis == "column" else np.array([0.0, b, 0.0])
+    cams = [(K0, R0, np.zeros(3)), (K0, R0, -R0 @ shift)]
+    d, n = flat(Wb, Hb, Z)
+    nb = n.copy()
+    a = np.radians(40.0)
+    if axis == "column":
+        nb[:, 1::2] = [np.sin(a), 0.0, -np.cos(a)]
+    else:
+        nb[1::2, :] = [0.0, np.sin(a), -np.cos(a)]
+    g, o = run_both(ctx, cams, [(Wb, Hb)] * 2, {0: d, 1: d}, {0: n, 1: nb}, 0, [1], pm.FilterParams(min_consistent=1))
+    assert_same(g, o, f"rounded {axis}, disparity {disp}")
+    edge = (slice(None), Wb - 4) if axis == "column" else (Hb - 4, slice(None))
+    assert np.array_equal(g[2][edge], o[2][edge])
+
+
+@pytest.mark.parametrize("sx,sy", [(1 - 1e-6, 0.5), (0.5, 1 - 1e-6), (0.5, 1e-6), (1e-6, 0.5)])
+def test_a_hole_texel_at_each_corner_of_the_cell(ctx, sx, sy):
+    """The neighbour's principal point shifted by (sx, sy) and one hole texel: the four
+    pixels whose bilinear cells hold it lose the neighbour, also where the hole's weight
+    is almost zero (the corner check alone decides)."""
+    K0, R0, t0 = cam(F, W, H)
+    K1 = K0.copy()
+    K1[0, 2] += sx
+    K1[1, 2] += sy
+    d, n = flat(W, H, 4.0)
+    d1 = d.copy()
+    d1[20, 30] = 0.0
+    g, o = run_both(ctx, [(K0, R0, t0), (K1, R0, t0)], [(W, H)] * 2, {0: d, 1: d1}, {0: n, 1: n}, 0, [1],
+                    pm.FilterParams(min_consistent=1))
+    assert_same(g, o, f"hole corner ({sx}, {sy})")
+    assert np.array_equal(g[2][18:23, 28:33], o[2][18:23, 28:33])
+
+
 def test_normals_holes_and_unusable_views(ctx):
     c0 = cam(F, W, H)
     c1 = cam(F, W, H, tx=0.05)

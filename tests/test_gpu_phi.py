@@ -59,7 +59,7 @@ def test_hypotheses_parity(ctx, tiny):
 
 
 def hole_map(seed, H, W, kind):
-    """Depths in [1, 9] with holes: sparse (90% empty), blocks (rectangles and a band wider
+    """Depths in [1, 9] with holes: sparse (90% empty), half empty, blocks (rectangles and a band wider
     than one 64-pixel word, negative and NaN entries), empty, or full."""
     r = np.random.default_rng(seed)
     d = r.uniform(1.0, 9.0, size=(H, W)).astype(np.float32)
@@ -73,13 +73,15 @@ def hole_map(seed, H, W, kind):
         d[y:y + 5, max(0, W // 2 - 150):W // 2 + 150] = 0.0
         d[r.uniform(size=(H, W)) < 0.01] = -1.0
         d[r.uniform(size=(H, W)) < 0.005] = np.nan
+    elif kind == "half":
+        d[r.uniform(size=(H, W)) < 0.5] = 0.0
     elif kind == "empty":
         d[:] = 0.0
     return d
 
 
-@pytest.mark.parametrize("H,W", [(1, 1), (1, 150), (150, 1), (3, 65), (67, 130), (64, 64), (129, 400)])
-@pytest.mark.parametrize("kind", ["sparse", "blocks", "empty", "full"])
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 150), (150, 1), (3, 65), (9, 11), (67, 130), (64, 64), (129, 400)])
+@pytest.mark.parametrize("kind", ["sparse", "half", "blocks", "empty", "full"])
 def test_hypotheses_parity_shapes(ctx, H, W, kind):
     """Image sizes around the 64-pixel words of the occupancy bitmaps, single rows and
     columns, holes reaching the image border and spanning several words: bitwise."""
