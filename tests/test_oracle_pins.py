@@ -224,33 +224,46 @@ def test_dilation_equals_dense_window_on_decimated_images():
     assert n > 50
 
 
-def test_border_rule_invalidates_view():
-    """A window warped (by a translation) partly past the source border gives C_max for
-    that view only, and C_max overall when no view is valid (paper: C_max = 1 - Z_min)."""
+@pytest.mark.parametrize("dcx,dcy", [(6, 0), (6.5, 0), (-6.5, 0), (0, 6.5), (0, -6.5), (4.5, -3.5)])
+def test_border_rule_invalidates_view(dcx, dcy):
+    """A window warped by a translation (dcx, dcy) partly past the source border gives
+    C_max for that view only, at exactly the pixels where a corner of the 7 x 7 window
+    leaves [0, W - 1] x [0, H - 1] (each side of the image in turn), and C_max overall
+    when no view is valid (paper: C_max = 1 - Z_min)."""
     h, w = 30, 40
     A = _textured(h, w, 11)
     K0 = _K(w, h)
-    pb = _pose_problem([A, A, A], [K0, _K(w, h, dcx=6), _K(w, h, dcx=-500)], window=7)
+    pb = _pose_problem([A, A, A], [K0, _K(w, h, dcx=dcx, dcy=dcy), _K(w, h, dcx=-500)], window=7)
     c, pv, ok = oracle.eval_cost(pb, _fronto(h, w), fp64=True)
     m = pb.valid_mask()
-    xs = np.nonzero(m.any(0))[0]
-    inside = (xs + 6 + 3) <= w - 1
-    for x in xs:
-        y = h // 2
-        assert ok[y, x, 0] == ((x + 6 + 3) <= w - 1)
-        assert not ok[y, x, 1] and pv[y, x, 1] == 2.0
+    ys, xs = np.nonzero(m)
+    r = 3
+    inside = (xs + dcx - r >= 0) & (xs + dcx + r <= w - 1) & (ys + dcy - r >= 0) & (ys + dcy + r <= h - 1)
+    assert np.array_equal(ok[ys, xs, 0], inside)
+    assert not ok[ys, xs, 1].any() and np.all(pv[ys, xs, 1] == 2.0)
     assert inside.any() and (~inside).any()
-    y = h // 2
-    xo = xs[~inside][0]
-    assert c[y, xo] == 2.0
+    assert np.all(c[ys[~inside], xs[~inside]] == 2.0)
 
 
 # ----------------------------------------------------------------------------- homography
-def test_homography_maps_plane_points_exactly():
+@pytest.mark.parametrize("kind", ["pinhole", "skew", "general"])
+def test_homography_maps_plane_points_exactly(kind):
+    """Points of a plane through a reference pixel's ray: the homography maps each one's
+    reference projection onto its source projection.  Besides pinhole matrices, a K with
+    skew and non-square pixels, and general invertible 3 x 3 matrices (every entry
+    non-zero: the mapping is a projective one for any invertible K), so that every
+    cofactor of the inverse matters."""
     rng = np.random.default_rng(3)
     w, h = 200, 150
     K0 = _K(w, h)
     Kj = _K(w, h, f=170.0, dcx=3.5, dcy=-2.0)
+    if kind == "skew":
+        K0[0, 1], K0[1, 1] = 4.3, 0.93 * K0[1, 1]
+        Kj[0, 1], Kj[0, 0] = -2.1, 1.07 * Kj[0, 0]
+    elif kind == "general":
+        K0 = K0 + rng.normal(size=(3, 3)) * np.array([[3.0, 3.0, 3.0], [3.0, 3.0, 3.0], [1e-3, 1e-3, 0.05]])
+        Kj = Kj + rng.normal(size=(3, 3)) * np.array([[3.0, 3.0, 3.0], [3.0, 3.0, 3.0], [1e-3, 1e-3, 0.05]])
+        assert np.all(K0 != 0) and np.all(Kj != 0)
     R0, Rj = _rand_rot(rng), _rand_rot(rng)
     t0, tj = rng.normal(size=3), rng.normal(size=3)
     img = np.zeros((h, w), np.float32)
