@@ -3,6 +3,7 @@ seeded inputs.  Bar (per result): |cost_gpu - cost_oracle| <= 1e-4 and
 |depth_gpu - depth_oracle| <= 1e-3 depth_oracle on >= 99.9% of valid pixels; the
 teacher-forced stages are expected to agree bitwise and are held to that on >= 99.9%.
 The FP64 oracle's distance to each FP32 result is printed."""
+import dataclasses
 import os
 import sys
 
@@ -132,6 +133,45 @@ def test_eval_cost_parity_tiny(ctx, tiny):
         # the FP64 oracle's distance to the FP32 cost (teacher-forced)
         o64, _, _ = oracle.eval_cost(pb, planes, fp64=True)
         fp64_report(f"  eval[{name}]", gc.cpu().numpy(), o64, m)
+
+
+@pytest.mark.parametrize("kind", ["skew", "shifted", "general"])
+def test_eval_cost_parity_with_other_intrinsics(ctx, tiny, kind):
+    """Teacher-forced costs under intrinsics the images were not rendered with (both sides
+    take K as given, so they must still agree): a skewed K with non-square pixels on every
+    view; the sources' principal points moved 6.5 pixels right, left, down and up, so that
+    windows leave each side of a source image; general invertible matrices (every entry
+    non-zero), so that every cofactor of K's inverse matters."""
+    scene, cfg = tiny
+    rng = np.random.default_rng(7)
+    cams = []
+    for i, c in enumerate(scene.cams):
+        K = c.K.copy()
+        if kind == "skew":
+            K[0, 1] = 4.3 if i % 2 else -2.1
+            K[1, 1] *= 0.93 if i % 2 else 1.07
+        elif kind == "shifted" and i > 0:
+            dx, dy = [(6.5, 0.0), (-6.5, 0.0), (0.0, 6.5), (0.0, -6.5)][(i - 1) % 4]
+            K[0, 2] += dx
+            K[1, 2] += dy
+        elif kind == "general":
+            K = K + rng.normal(size=(3, 3)) * np.array([[2.0, 2.0, 2.0], [2.0, 2.0, 2.0], [1e-4, 1e-4, 0.02]])
+        cams.append(dataclasses.replace(c, K=K))
+    sc = dataclasses.replace(scene, cams=cams)
+    pb = _prep(ctx, sc, cfg)
+    m = pb.valid_mask()
+    for name, planes in _test_planes(sc, pb, np.random.default_rng(1)).items():
+        say(f"intrinsics {kind}, planes {name}")
+        gc, gpv, gvm = ctx.eval_cost(torch.tensor(planes, dtype=torch.float32, device="cuda"), per_view=True)
+        oc, opv, ovm = oracle.eval_cost(pb, planes)
+        frac, bit = compare(f"eval[{kind}/{name}]", gc.cpu().numpy(), oc, np.ones_like(m))
+        assert frac >= FRAC and bit >= FRAC
+        vm = ovm[m]
+        say(f"  valid views {vm.mean():.3f} of {vm.size}")
+        assert (gvm.cpu().numpy().astype(bool) == ovm).mean() >= FRAC
+        assert (np.abs(gpv.cpu().numpy() - opv) <= COST_TOL).mean() >= FRAC
+        if kind == "shifted" and name == "gt":
+            assert 0.3 < vm.mean() < 0.99  # windows do leave the sources
 
 
 def test_init_parity_tiny(ctx, tiny):
