@@ -134,6 +134,27 @@ def test_a_hole_texel_at_each_corner_of_the_cell(ctx, sx, sy):
     assert np.array_equal(g[2][18:23, 28:33], o[2][18:23, 28:33])
 
 
+def test_skewed_intrinsics(ctx):
+    """Cameras with skew and non-square pixels (a fronto-parallel plane stays consistent
+    under a sideways move whatever K is), one neighbour with holes and depth noise, so
+    that the camera chain runs through every entry of K's inverse."""
+    r = np.random.default_rng(5)
+    K0, R0, _ = cam(F, W, H)
+    Ka, Kb = K0.copy(), K0.copy()
+    Ka[0, 1], Ka[1, 1] = 3.7, 0.92 * F
+    Kb[0, 1], Kb[0, 0] = -2.2, 1.06 * F
+    cams = [(Ka, R0, np.zeros(3)), (Ka, R0, -R0 @ np.array([0.05, 0.0, 0.0])),
+            (Kb, R0, -R0 @ np.array([-0.04, 0.02, 0.0]))]
+    d, n = flat(W, H, 4.0)
+    d2 = (d * (1 + 0.012 * r.standard_normal(d.shape))).astype(np.float32)
+    d2[r.uniform(size=d.shape) < 0.1] = 0.0
+    for k in (1, 2):
+        g, o = run_both(ctx, cams, [(W, H)] * 3, {0: d, 1: d, 2: d2}, {0: n, 1: n, 2: n}, 0, [1, 2],
+                        pm.FilterParams(min_consistent=k))
+        assert_same(g, o, f"skewed intrinsics, min {k}")
+        assert 0 < (o[2] == 2).mean() < 1
+
+
 def test_normals_holes_and_unusable_views(ctx):
     c0 = cam(F, W, H)
     c1 = cam(F, W, H, tx=0.05)

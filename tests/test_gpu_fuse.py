@@ -1,6 +1,7 @@
 """GPU parity of depth-map fusion (Sec. III-F) through the C ABI against the oracle's
 sequential walk: points, support and owners bitwise equal on random multi-view maps of
-mixed sizes, on a half-resolution copy (where several pixels compete for one), on the
+mixed sizes (also with skewed intrinsics), on a half-resolution copy (where several
+pixels compete for one), on the
 PatchMatch depth maps of every view of the tiny scene, and in the degenerate cases (one
 map, no depth at all, threshold zero)."""
 import sys
@@ -33,8 +34,9 @@ def cam(f, W, H, centre=(0.0, 0.0, 0.0), yaw=0.0):
     return K, R, t
 
 
-def arc_maps(seed, sizes, f_scale=0.8, noise=0.003, holes=0.15):
-    """Cameras on an arc looking at the world plane z = 4; depth maps with noise and holes."""
+def arc_maps(seed, sizes, f_scale=0.8, noise=0.003, holes=0.15, skew=None):
+    """Cameras on an arc looking at the world plane z = 4; depth maps with noise and holes.
+    skew: per view (s, a), a K with skew s and the vertical focal length scaled by a."""
     r = np.random.default_rng(seed)
     cams, depths = [], []
     n = len(sizes)
@@ -42,7 +44,11 @@ def arc_maps(seed, sizes, f_scale=0.8, noise=0.003, holes=0.15):
         a = 0.05 * (v - (n - 1) / 2)
         K, R, t = cam(f_scale * W, W, H, (4.0 * np.sin(a), 0.03 * v, 4.0 - 4.0 * np.cos(a)), a)
         y, x = np.mgrid[0:H, 0:W].astype(np.float64)
-        ray = np.stack([(x - K[0, 2]) / K[0, 0], (y - K[1, 2]) / K[1, 1], np.ones_like(x)], -1) @ R
+        if skew is None:
+            ray = np.stack([(x - K[0, 2]) / K[0, 0], (y - K[1, 2]) / K[1, 1], np.ones_like(x)], -1) @ R
+        else:
+            K[0, 1], K[1, 1] = skew[v][0], K[1, 1] * skew[v][1]
+            ray = np.stack([x, y, np.ones_like(x)], -1) @ np.linalg.inv(K).T @ R
         C = -R.T @ t
         d = ((4.0 - C[2]) / ray[..., 2] * (1 + noise * r.standard_normal((H, W)))).astype(np.float32)
         d[r.uniform(size=(H, W)) < holes] = 0.0
@@ -89,6 +95,16 @@ def test_fuse_parity_random_views(seed):
     sizes = [(96, 72), (64, 48), (96, 72), (80, 60), (96, 72), (48, 36)]
     cams, depths = arc_maps(seed, sizes)
     o = check(cams, depths, 0.01, f"arc seed {seed}")
+    assert (o[1] > 1).sum() > 0.1 * (o[1] > 0).sum()
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_fuse_parity_with_skewed_intrinsics(seed):
+    """Cameras with skew and non-square pixels (each map rendered through its own K), so
+    that every entry of K's inverse takes part in the back-projections."""
+    sizes = [(96, 72), (64, 48), (80, 60), (96, 72)]
+    cams, depths = arc_maps(seed, sizes, skew=[(3.1, 0.95), (-1.7, 1.05), (0.0, 1.0), (2.4, 0.9)])
+    o = check(cams, depths, 0.01, f"skewed seed {seed}")
     assert (o[1] > 1).sum() > 0.1 * (o[1] > 0).sum()
 
 
