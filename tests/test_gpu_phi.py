@@ -161,6 +161,32 @@ def test_normals_parity(ctx, tiny):
     assert np.median(err[inner]) < 1.0
 
 
+@pytest.mark.parametrize("kind", ["skew", "general"])
+def test_normals_parity_with_other_intrinsics(tiny, kind):
+    """Eq. 10 back-projects through K's inverse: with a skewed K with non-square pixels, and
+    with a general invertible matrix (every entry non-zero), the normals are still the
+    oracle's, bitwise."""
+    d = tiny.gt_depth.astype(np.float32).copy()
+    d[30:40, 50:70] = 0.0
+    K = tiny.K[0].copy()
+    if kind == "skew":
+        K[0, 1], K[1, 1] = 3.3, 0.94 * K[1, 1]
+    else:
+        K = K + np.random.default_rng(9).normal(size=(3, 3)) * np.array([[2.0, 2.0, 2.0], [2.0, 2.0, 2.0],
+                                                                         [1e-4, 1e-4, 0.02]])
+    c = pm.Context(0)
+    try:
+        H, W = d.shape
+        c.set_views([np.zeros((H, W), np.uint8)] * 2, np.stack([K, K]), tiny.R[:2], tiny.t[:2],
+                    np.tile([1.0, 10.0], (2, 1)))
+        g = c.phi_normals(0, torch.from_numpy(d).cuda()).cpu().numpy()
+    finally:
+        c.close()
+    o = oracle.phi_normals(d, K)
+    say(f"normals with {kind} intrinsics: {(o != 0).any(-1).mean():.3f} of the pixels defined")
+    assert np.array_equal(g, o)
+
+
 def test_phi_fills_holes_of_a_filtered_map(ctx, tiny):
     """Holes inside planes (the case the method is for: pixels of a plane the search left
     empty) get filled, and the filled depths are near the ground truth."""
