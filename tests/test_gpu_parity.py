@@ -135,14 +135,10 @@ def test_eval_cost_parity_tiny(ctx, tiny):
         fp64_report(f"  eval[{name}]", gc.cpu().numpy(), o64, m)
 
 
-@pytest.mark.parametrize("kind", ["skew", "shifted", "general"])
-def test_eval_cost_parity_with_other_intrinsics(ctx, tiny, kind):
-    """Teacher-forced costs under intrinsics the images were not rendered with (both sides
-    take K as given, so they must still agree): a skewed K with non-square pixels on every
-    view; the sources' principal points moved 6.5 pixels right, left, down and up, so that
-    windows leave each side of a source image; general invertible matrices (every entry
-    non-zero), so that every cofactor of K's inverse matters."""
-    scene, cfg = tiny
+def _with_intrinsics(scene, kind):
+    """The scene with other intrinsics than its images were rendered with: "skew" (skew and
+    non-square pixels on every view), "shifted" (the sources' principal points moved 6.5
+    pixels right, left, down and up), "general" (every entry of every K perturbed)."""
     rng = np.random.default_rng(7)
     cams = []
     for i, c in enumerate(scene.cams):
@@ -157,7 +153,18 @@ def test_eval_cost_parity_with_other_intrinsics(ctx, tiny, kind):
         elif kind == "general":
             K = K + rng.normal(size=(3, 3)) * np.array([[2.0, 2.0, 2.0], [2.0, 2.0, 2.0], [1e-4, 1e-4, 0.02]])
         cams.append(dataclasses.replace(c, K=K))
-    sc = dataclasses.replace(scene, cams=cams)
+    return dataclasses.replace(scene, cams=cams)
+
+
+@pytest.mark.parametrize("kind", ["skew", "shifted", "general"])
+def test_eval_cost_parity_with_other_intrinsics(ctx, tiny, kind):
+    """Teacher-forced costs under intrinsics the images were not rendered with (both sides
+    take K as given, so they must still agree): a skewed K with non-square pixels on every
+    view; the sources' principal points moved 6.5 pixels right, left, down and up, so that
+    windows leave each side of a source image; general invertible matrices (every entry
+    non-zero), so that every cofactor of K's inverse matters."""
+    scene, cfg = tiny
+    sc = _with_intrinsics(scene, kind)
     pb = _prep(ctx, sc, cfg)
     m = pb.valid_mask()
     for name, planes in _test_planes(sc, pb, np.random.default_rng(1)).items():
@@ -352,6 +359,24 @@ def test_patchmatch_parity_tiny(ctx, tiny):
     fp64_report("  tiny: free-running depth", gpu_depth=gd, fp64_depth=od64, mask=m)
     # invalid pixels: depth 0, normal 0, cost C_max
     assert np.all(gd[~m] == 0) and np.all(c.cpu().numpy()[~m] == 2.0) and np.all(nrm.cpu().numpy()[~m] == 0)
+
+
+@pytest.mark.parametrize("kind", ["skew", "general"])
+def test_patchmatch_parity_tiny_with_other_intrinsics(ctx, tiny, kind):
+    """The whole tiny run (initialisation, propagation with its ray-plane re-expression,
+    refinement) under skewed or general invertible intrinsics: within the tolerances, as
+    for the rendered cameras."""
+    scene, cfg = tiny
+    sc = _with_intrinsics(scene, kind)
+    pb = _prep(ctx, sc, cfg)
+    n = len(sc.images) - 1
+    d, nrm, c = ctx.patchmatch(0, list(range(1, n + 1)), cfg["window"], cfg["dilation"], cfg["iters"],
+                               params_for(cfg["window"], cfg["top_k"]))
+    torch.cuda.synchronize()
+    od, on, oc = oracle.patchmatch(pb, cfg["iters"])
+    m = pb.valid_mask()
+    frac, bit = compare(f"patchmatch tiny, {kind} intrinsics", c.cpu().numpy(), oc, m, d.cpu().numpy(), od)
+    assert frac >= FRAC
 
 
 def test_patchmatch_parity_tiny_depth_ordered(ctx, tiny):
