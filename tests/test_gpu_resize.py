@@ -1,6 +1,8 @@
 """GPU parity of the window-resize scheme (Sec. III-C, Fig. 4, Table III; `tap_radius`):
 integer spacings are bitwise the integer dilation on the GPU itself, fractional spacings
-match the oracle teacher-forced and end to end (same bar as the other parity tests)."""
+match the oracle teacher-forced and end to end (same bar as the other parity tests), also
+under skewed intrinsics with windows leaving the sources."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -69,6 +71,50 @@ def test_fractional_spacing_parity(ctx, tiny, window, tap_radius):
     assert bit >= 0.999
     # end to end, 2 iterations
     gd, _, gcost = run(ctx, tiny, window, 1, tap_radius)
+    od, _, ocost = oracle.patchmatch(pb, 2)
+    ok = (np.abs(gcost - ocost) <= 1e-4) & (np.abs(gd - od) <= 1e-3 * np.abs(od))
+    say(f"  end to end: {ok[m].mean():.6f} within tolerance, cost bitwise {(gcost[m] == ocost[m]).mean():.6f}")
+    assert ok[m].mean() >= 0.999
+
+
+@pytest.mark.parametrize("window,tap_radius", [(17, 5), (15, 4)])
+def test_fractional_spacing_parity_with_skewed_shifted_intrinsics(tiny, window, tap_radius):
+    """Fractional spacing under intrinsics the images were not rendered with: skew and
+    non-square pixels on every view, the sources' principal points moved 6.5 pixels so
+    that windows leave each side of a source image.  Teacher-forced bitwise, end to end
+    within the tolerances."""
+    cams = []
+    for i, c in enumerate(tiny.cams):
+        K = c.K.copy()
+        K[0, 1] = 3.9 if i % 2 else -2.4
+        K[1, 1] *= 0.95 if i % 2 else 1.04
+        if i > 0:
+            dx, dy = [(6.5, 0.0), (-6.5, 0.0), (0.0, 6.5), (0.0, -6.5)][(i - 1) % 4]
+            K[0, 2] += dx
+            K[1, 2] += dy
+        cams.append(dataclasses.replace(c, K=K))
+    sc = dataclasses.replace(tiny, cams=cams)
+    srcs = list(range(1, len(sc.images)))
+    sig = (window - 1) / 2.0
+    pb = oracle.Problem.from_scene(sc, window, 1, top_k=3, bilateral=True, sigma_s=sig, sigma_c=12.0,
+                                   tap_radius=tap_radius)
+    m = pb.valid_mask()
+    planes = np.concatenate([sc.gt_normal, sc.gt_depth[..., None]], -1)
+    c = pm.Context(0)
+    try:
+        c.set_scene(sc)
+        c.prepare(0, srcs, window, 1, pm.Params(top_k=3, sigma_spatial_px=sig, tap_radius=tap_radius))
+        gc, _, gok = [t.cpu().numpy() for t in c.eval_cost(torch.from_numpy(planes.astype(np.float32)).cuda(),
+                                                           per_view=True)]
+        gd, _, gcost = run(c, sc, window, 1, tap_radius)
+    finally:
+        c.close()
+    oc, _, ook = oracle.eval_cost(pb, planes.astype(np.float32).astype(np.float64))
+    bit = (gc[m] == oc[m].astype(np.float32)).mean()
+    say(f"skewed, shifted; window {window} / {tap_radius} taps per side: teacher-forced cost bitwise {bit:.6f}, "
+        f"valid views {ook[m].mean():.3f}")
+    assert bit >= 0.999 and (gok.astype(bool) == ook).mean() >= 0.999
+    assert ook[m].mean() < 0.99  # windows do leave the sources
     od, _, ocost = oracle.patchmatch(pb, 2)
     ok = (np.abs(gcost - ocost) <= 1e-4) & (np.abs(gd - od) <= 1e-3 * np.abs(od))
     say(f"  end to end: {ok[m].mean():.6f} within tolerance, cost bitwise {(gcost[m] == ocost[m]).mean():.6f}")
