@@ -195,6 +195,35 @@ def test_init_parity_tiny(ctx, tiny):
     assert plane_bit >= FRAC and frac >= FRAC
 
 
+@pytest.mark.parametrize("seed", [0x9E3779B97F4A7C15, 0xFFFFFFFF00000001])
+def test_init_and_refinement_parity_with_64_bit_seeds(ctx, tiny, seed):
+    """Seeds whose high 32 bits are set (the second word of the Philox key): the random
+    initial planes bitwise, and one teacher-forced half-sweep (its refinement draws)."""
+    scene, cfg = tiny
+    pb = _prep(ctx, scene, cfg, seed=seed)
+    ctx.init_planes()
+    gp, gc = ctx.get_state()
+    op, oc = oracle.init(pb)
+    m = pb.valid_mask()
+    gp = gp.cpu().numpy()
+    plane_bit = np.all(gp == op.astype(np.float32), axis=-1)[m].mean()
+    say(f"seed {seed:#x}: init planes bitwise {plane_bit:.6f}")
+    frac, _ = compare(f"init seed {seed:#x}", gc.cpu().numpy(), oc, m, gp[..., 3], op[..., 3])
+    assert plane_bit >= FRAC and frac >= FRAC
+    ctx.set_state(torch.tensor(op, dtype=torch.float32, device="cuda"), torch.tensor(oc, dtype=torch.float32, device="cuda"))
+    ctx.step(1, 0)
+    gp, gc = ctx.get_state()
+    P2, C2 = oracle.halfsweep(pb, op, oc, 1, 0)
+    gp = gp.cpu().numpy()
+    plane_bit = np.all(gp == P2.astype(np.float32), axis=-1)[m].mean()
+    say(f"  half-sweep: planes bitwise {plane_bit:.6f}")
+    frac, _ = compare(f"half-sweep seed {seed:#x}", gc.cpu().numpy(), C2, m, gp[..., 3], P2[..., 3])
+    assert frac >= FRAC and plane_bit >= FRAC
+    # the high word matters: the initial planes differ from those of the low word alone
+    op_lo, _ = oracle.init(oracle_problem(scene, cfg["window"], cfg["dilation"], cfg["top_k"], seed=seed & 0xFFFFFFFF))
+    assert not np.array_equal(op_lo[m], op[m])
+
+
 def test_halfsweep_parity_tiny(ctx, tiny):
     """Teacher-forced: both sides start each half-sweep from the oracle's state."""
     scene, cfg = tiny
