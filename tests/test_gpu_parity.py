@@ -181,6 +181,33 @@ def test_eval_cost_parity_with_other_intrinsics(ctx, tiny, kind):
             assert 0.3 < vm.mean() < 0.99  # windows do leave the sources
 
 
+@pytest.mark.parametrize("sc,ss,ev,ec,k", [(5.5, 2.3, 2e-3, 0.05, 2), (30.0, 7.5, 1e-6, 1e-6, 0)])
+def test_parity_with_other_cost_parameters(ctx, tiny, sc, ss, ev, ec, k):
+    """Colour and spatial sigmas, the variance floor, the cost floor of Eq. 5 and top-K
+    away from their defaults: teacher-forced costs on every plane set and the whole tiny
+    run against the oracle with the same parameters."""
+    scene, cfg = tiny
+    n = len(scene.images) - 1
+    p = pm.Params(top_k=k, sigma_spatial_px=ss, sigma_color=sc, eps_var=ev, eps_cost=ec, seed=0x5EED)
+    ctx.set_scene(scene)
+    ctx.prepare(0, list(range(1, n + 1)), cfg["window"], cfg["dilation"], p)
+    pb = oracle.Problem.from_scene(scene, cfg["window"], cfg["dilation"], top_k=k, bilateral=True, sigma_s=ss,
+                                   sigma_c=sc, eps_v=ev, eps_c=ec, seed=0x5EED)
+    m = pb.valid_mask()
+    for name, planes in _test_planes(scene, pb, np.random.default_rng(2)).items():
+        gc, gpv, gvm = ctx.eval_cost(torch.tensor(planes, dtype=torch.float32, device="cuda"), per_view=True)
+        oc, opv, ovm = oracle.eval_cost(pb, planes)
+        frac, bit = compare(f"eval[{name}] sigma_c {sc} sigma_s {ss} eps_v {ev} eps_c {ec} top-{k}", gc.cpu().numpy(),
+                            oc, np.ones_like(m))
+        assert frac >= FRAC and bit >= FRAC
+        assert (gvm.cpu().numpy().astype(bool) == ovm).mean() >= FRAC
+    d, nrm, c = ctx.patchmatch(0, list(range(1, n + 1)), cfg["window"], cfg["dilation"], cfg["iters"], p)
+    torch.cuda.synchronize()
+    od, on, oc = oracle.patchmatch(pb, cfg["iters"])
+    frac, bit = compare(f"patchmatch tiny, sigma_c {sc} top-{k}", c.cpu().numpy(), oc, m, d.cpu().numpy(), od)
+    assert frac >= FRAC
+
+
 def test_init_parity_tiny(ctx, tiny):
     scene, cfg = tiny
     pb = _prep(ctx, scene, cfg)
