@@ -78,6 +78,41 @@ def test_batch_equals_single_runs(ctx, mv, tuning, use_graph):
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_with_per_job_cost_parameters(ctx, mv, use_graph):
+    """Every job with its own colour and spatial sigmas, variance and cost floors, top-K,
+    bilateral switch and seed: the batch equals the single runs bitwise, so each job's
+    parameters reach its own tiles only."""
+    jobs = jobs_of(mv)
+    for i, j in enumerate(jobs):
+        j["params"] = pm.Params(top_k=i % (len(j["srcs"]) + 1), bilateral=i % 5 != 3, sigma_spatial_px=1.5 + 0.7 * i,
+                                sigma_color=4.0 + 3.5 * i, eps_var=10.0 ** -(3 + i % 4), eps_cost=10.0 ** -(1 + i % 5),
+                                seed=(i + 1) * 0x9E3779B97F4A7C15 % (1 << 64))
+    ctx.set_tuning(pm.Tuning(4, True, 4))
+    ref = single_runs(ctx, jobs, 2)
+    outs = ctx.patchmatch_batch(jobs, 2, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for k, ((d, n, c), (rd, rn, rc)) in enumerate(zip(outs, ref)):
+        assert torch.equal(d, rd) and torch.equal(n, rn) and torch.equal(c, rc), f"job {k}"
+    say(f"batch of {len(jobs)} jobs with per-job parameters == single runs (graph={use_graph})")
+    if use_graph:
+        return
+    for k in (3, 4):  # job 3 without the bilateral weights
+        j, (d, n, c) = jobs[k], outs[k]
+        p = j["params"]
+        views = [j["ref"]] + list(j["srcs"])
+        pb = oracle.Problem([mv.images[v] for v in views], mv.K[views], mv.R[views], mv.t[views],
+                            mv.depth_ranges[j["ref"]], j["window"], j["dilation"], top_k=p.top_k,
+                            bilateral=p.bilateral, sigma_s=p.sigma_spatial_px, sigma_c=p.sigma_color,
+                            eps_v=p.eps_var, eps_c=p.eps_cost, seed=p.seed)
+        od, on, oc = oracle.patchmatch(pb, 2)
+        m = pb.valid_mask()
+        gc, gd = c.cpu().numpy(), d.cpu().numpy()
+        ok = (np.abs(gc - oc) <= 1e-4) & (np.abs(gd - od) <= 1e-3 * np.abs(od))
+        say(f"  job {k} vs oracle: {ok[m].mean():.6f} within tolerance, bitwise {(gc[m] == oc[m]).mean():.6f}")
+        assert ok[m].mean() >= 0.999
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
 def test_depth_ordered_batch_equals_pixel_order_singles(ctx, mv, use_graph):
     """The batch in depth order equals the single runs in pixel order, job by job."""
     iters = 2
