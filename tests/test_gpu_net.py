@@ -7,6 +7,7 @@ Tolerances: the GPU stores weights, activations and back-propagated gradients in
 bfloat16 and accumulates in FP32; the oracle is run with the same roundings
 (``like_gpu``), so what remains is FP32 summation order (relative ~1e-6) plus the rare
 activation whose bfloat16 rounding flips by one unit (2^-8 relative) because of it."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -265,6 +266,43 @@ def test_proposal_inputs_parity(ctx, net, tiny):
     say(f"proposal inputs: {close.mean():.6f} within 5e-4, max err {err.max():.3g} (views {n})")
     assert close[..., 0].all()
     assert close.mean() >= 0.999  # a sample exactly on a source border may fall either side
+
+
+@pytest.mark.parametrize("kind", ["skew", "general"])
+def test_proposal_inputs_and_decode_with_other_intrinsics(net, tiny, kind):
+    """The input builder's plane homographies and the decoder's rays under a skewed K with
+    non-square pixels on every view, and under general invertible matrices (every entry
+    non-zero): the same bars as with the rendered cameras."""
+    r = np.random.default_rng(11)
+    cams = []
+    for i, c in enumerate(tiny.cams):
+        K = c.K.copy()
+        if kind == "skew":
+            K[0, 1] = 3.4 if i % 2 else -1.9
+            K[1, 1] *= 0.94 if i % 2 else 1.05
+        else:
+            K = K + r.normal(size=(3, 3)) * np.array([[2.0, 2.0, 2.0], [2.0, 2.0, 2.0], [1e-4, 1e-4, 0.02]])
+        cams.append(dataclasses.replace(c, K=K))
+    sc = dataclasses.replace(tiny, cams=cams)
+    srcs = list(range(1, len(sc.images)))
+    H, W = sc.images[0].shape
+    out = r.normal(0, 1.5, ((H + 3) // 4, (W + 3) // 4, 4)).astype(np.float32)
+    c = pm.Context(0)
+    try:
+        c.set_scene(sc)
+        x = c.net_inputs(net, 0, srcs).cpu().numpy()
+        planes = c.net_decode(net, 0, dev(out)).cpu().numpy()
+    finally:
+        c.close()
+    ref = cnn.proposal_inputs([im.astype(np.float64) for im in sc.images], sc.K, sc.R, sc.t, sc.depth_range, 0, srcs)
+    err = np.abs(x - ref)
+    say(f"proposal inputs, {kind} intrinsics: {(err <= 5e-4).mean():.6f} within 5e-4, max err {err.max():.3g}")
+    assert (err[..., 0] <= 5e-4).all() and (err <= 5e-4).mean() >= 0.999
+    dref = cnn.decode(out.astype(np.float64), sc.K[0], sc.depth_range, H, W)
+    derr = np.abs(planes[..., 3] - dref[..., 3]) / dref[..., 3]
+    nerr = np.abs(planes[..., :3] - dref[..., :3]).max(-1)
+    say(f"  decode: depth max rel err {derr.max():.3g}, normals within 1e-5 {(nerr <= 1e-5).mean():.6f}")
+    assert derr.max() <= 1e-5 and (nerr <= 1e-5).mean() >= 0.999
 
 
 def test_decode_parity(ctx, net, tiny):
