@@ -1098,10 +1098,11 @@ double oracle_phi_map_bruteforce(const float* depth, const float* hyp, const flo
 // label[i] receives k (-1 for a fixed node or one without states), value[i] its depth (0
 // without states).  Parity unpinned in part: on a forest TRW is exact and the tests hold
 // it to the enumerated MAP; the weights gamma and the exact sweep schedule act on graphs
-// with loops alone, where the tests hold the decoder to the enumerated MAP only for binary
+// with loops alone, where the tests hold the decoder to the exact minimum only for binary
 // submodular energies (where TRW reaches the global minimum, Kolmogorov and Wainwright
-// 2005: over-counting weights fail there, smaller weights or a changed schedule do not)
-// and otherwise to near-optimality.
+// 2005; the enumerated MAP on small grids, a minimum s-t cut on larger ones: over-counting
+// and smaller weights fail there, a message also sent against the sweep direction does
+// not) and otherwise to near-optimality.
 void oracle_phi_trws(const float* depth, const float* hyp, const float* cost, int W, int H, double k1, double k2,
                      double k3, double cmax, int iterations, int32_t* label, float* value) {
   const int N = W * H;

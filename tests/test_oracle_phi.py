@@ -11,6 +11,7 @@ import math
 import numpy as np
 import pytest
 
+import binary_mincut
 import oracle
 
 DIRS = [(1, 0), (0, 1), (1, 1), (1, -1)]
@@ -458,6 +459,27 @@ def test_trws_is_exact_on_binary_submodular_loopy_grids():
         lab0, _ = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=0)
         greedy_misses += not np.isclose(_log_potential(d, hyp, cost, lab0, k1, k2, k3), e_opt, rtol=1e-9, atol=1e-12)
     assert greedy_misses >= n // 3
+
+
+@pytest.mark.parametrize("shape,iters", [((20, 20), 30), ((16, 24), 30), ((12, 30), 30), ((30, 30), 30),
+                                         ((100, 100), 100)])
+def test_trws_reaches_the_min_cut_minimum_on_larger_binary_submodular_grids(shape, iters):
+    """Grids too large to enumerate, with the two-cluster hypotheses of the test above: the
+    exact minimum is a minimum s-t cut (Kolmogorov and Zabih 2004, computed with scipy's
+    maximum flow, written in the tests), and TRW reaches it within the given sweeps.  A
+    decoder with smaller weights (the right neighbour counted as earlier) falls short here
+    within these sweeps."""
+    r = np.random.default_rng(shape[0] * 100 + shape[1])
+    for trial in range(2):
+        k1, k2, k3 = (0.5, 1.0, 2.0)[trial % 3], 0.1, (2.5, 2.0)[trial % 2]
+        d, hyp, cost = binary_mincut.two_cluster_problem(r, *shape)
+        terms = binary_mincut.energy_terms(d, hyp, cost, k1, k2, k3)
+        e_mc = binary_mincut.energy(terms, binary_mincut.min_cut_labels(terms, shape))
+        lab, _ = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=iters)
+        e = binary_mincut.energy(terms, lab)
+        assert e_mc - 1e-3 <= e <= e_mc + 1e-6, (e, e_mc)
+        lab0, _ = oracle.phi_trws(d, hyp, cost, k1, k2, k3, iterations=0)
+        assert binary_mincut.energy(terms, lab0) > e_mc + 1.0  # greedy decoding is far from it
 
 
 def test_normals_of_a_rendered_plane():

@@ -9,6 +9,7 @@ edges and several iteration counts.  No GPU needed: the decoder takes host array
 import numpy as np
 import pytest
 
+import binary_mincut
 import oracle
 import paper_2104_06165_amd as pm
 
@@ -79,6 +80,21 @@ def test_decoder_on_small_loopy_grids():
     gaps = np.array(gaps)
     assert (gaps < 1e-9).mean() >= 0.8  # the optimum itself in most cases
     assert gaps.max() < 0.05
+
+
+@pytest.mark.parametrize("shape", [(100, 100), (120, 160)])
+def test_decoder_reaches_the_min_cut_minimum_on_large_binary_submodular_grids(shape):
+    """Sizes that run the decoder's threaded tile schedule, two hypotheses per free node
+    (every free-free edge submodular): 100 sweeps reach the exact minimum, a minimum s-t
+    cut computed in the tests (Kolmogorov and Zabih 2004, scipy's maximum flow)."""
+    r = np.random.default_rng(shape[1])
+    k1, k2, k3 = 0.5, 0.1, 2.5
+    d, hyp, cost = binary_mincut.two_cluster_problem(r, *shape)
+    terms = binary_mincut.energy_terms(d, hyp, cost, k1, k2, k3)
+    e_mc = binary_mincut.energy(terms, binary_mincut.min_cut_labels(terms, shape))
+    lab, _ = pm.phi_decode_host(d, hyp.transpose(2, 0, 1), cost.transpose(2, 0, 1), pm.PhiParams(k1, k2, k3, 100))
+    e = binary_mincut.energy(terms, lab)
+    assert e_mc - 1e-3 <= e <= e_mc + 1e-6, (e, e_mc)
 
 
 def test_decoder_is_exact_on_binary_submodular_loopy_grids():
